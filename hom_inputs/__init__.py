@@ -1,0 +1,314 @@
+"""Seeded synthetic inputs for the periodic cell problem.
+
+This module is shared by the tests, the benchmark, the CPU oracle's callers
+and the GPU library's callers.  It holds generators only: random numbers,
+geometry and coefficient fields.  None of the homogenization arithmetic (DFT,
+projection, solver, quadrature) lives here.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014): state_i = seed + i * gamma,
+output = mix(state_i).  Uniforms are (z >> 11) * 2**-53; normals use the
+Box-Muller transform with u1 in (0, 1].  Grid draws are made in FFT-order,
+row-major over the grid.
+
+Grids follow the paper's convention: on a cell prod [-Y_a, Y_a] with N_a odd
+points per axis, storage index i holds x = k h with k = i if i <= (N-1)/2 else
+i - N and h = 2 Y / N, so the origin is index 0.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """n outputs of SplitMix64 started from ``seed`` (outputs offset+1 .. offset+n)."""
+    with np.errstate(over="ignore"):
+        i = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def splitmix_one(seed: int, i: int) -> int:
+    """The i-th output (i >= 1) of SplitMix64 from ``seed``, as a Python int."""
+    return int(splitmix64(seed, 1, offset=i - 1)[0])
+
+
+def uniform(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """n uniforms in [0, 1) with 53 random bits."""
+    return (splitmix64(seed, n, offset) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+def normal(seed: int, n: int) -> np.ndarray:
+    """n standard normals by Box-Muller from consecutive uniform pairs."""
+    m = (n + 1) // 2
+    u = uniform(seed, 2 * m).reshape(m, 2)
+    u1 = 1.0 - u[:, 0]              # (0, 1]
+    rad = np.sqrt(-2.0 * np.log(u1))
+    th = 2.0 * np.pi * u[:, 1]
+    z = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1).reshape(-1)
+    return z[:n]
+
+
+# --------------------------------------------------------------------------
+# grids
+# --------------------------------------------------------------------------
+
+def signed_index(n: int) -> np.ndarray:
+    """Signed index k of each storage position on an axis of length n."""
+    i = np.arange(n)
+    return np.where(i <= (n - 1) // 2, i, i - n)
+
+
+def coords(N, Y=None):
+    """Grid coordinates x_a = k h_a (open grid, origin at index 0), one 1-D
+    array per axis."""
+    d = len(N)
+    Y = (0.5,) * d if Y is None else Y
+    return [signed_index(n) * (2.0 * y / n) for n, y in zip(N, Y)]
+
+
+def mesh(N, Y=None):
+    return np.meshgrid(*coords(N, Y), indexing="ij")
+
+
+# --------------------------------------------------------------------------
+# microstructures
+# --------------------------------------------------------------------------
+
+def square_inclusion(N, half_width=0.25, a_in=10.0, a_out=1.0, Y=None):
+    """Centred square (cube) inclusion: a_in where max_a |x_a| < half_width."""
+    X = mesh(N, Y)
+    inside = np.ones(tuple(N), dtype=bool)
+    for x in X:
+        inside &= np.abs(x) < half_width
+    return np.where(inside, a_in, a_out).astype(np.float64)
+
+
+def bernoulli_majority(N, p=0.4, passes=3, a1=100.0, a0=1.0, seed=2):
+    """Two-phase pixel field: phase 1 with probability p per pixel (uniform < p,
+    FFT-order row-major draws), then ``passes`` synchronous periodic 3^d Moore
+    majority votes (phase 1 iff more than half of the 3^d cells, centre
+    included, are phase 1).  Returns the conductivity field."""
+    N = tuple(N)
+    ph = (uniform(seed, int(np.prod(N))) < p).reshape(N).astype(np.int32)
+    d = len(N)
+    k = 3 ** d
+    for _ in range(passes):
+        s = np.zeros(N, dtype=np.int32)
+        for shift in np.ndindex(*(3,) * d):
+            s += np.roll(ph, tuple(int(t) - 1 for t in shift), axis=tuple(range(d)))
+        ph = (2 * s > k).astype(np.int32)
+    return np.where(ph == 1, a1, a0).astype(np.float64)
+
+
+def rsa_centres(d, count, r, seed, max_draws=10_000_000):
+    """Random sequential addition: uniform centres in [0,1)^d, a candidate is
+    accepted when its periodic minimum-image distance to every accepted centre
+    is >= 2r; stops at ``count`` centres."""
+    centres = []
+    off = 0
+    batch = 4096
+    draws = 0
+    while len(centres) < count:
+        u = uniform(seed, batch * d, offset=off).reshape(batch, d)
+        off += batch * d
+        for c in u:
+            draws += 1
+            if draws > max_draws:
+                raise RuntimeError("RSA did not place all inclusions")
+            ok = True
+            for q in centres:
+                dd = c - q
+                dd -= np.round(dd)
+                if float(np.dot(dd, dd)) < (2 * r) ** 2:
+                    ok = False
+                    break
+            if ok:
+                centres.append(c.copy())
+                if len(centres) == count:
+                    break
+    return np.array(centres)
+
+
+def inclusions(N, count, r, a_in, a_out=1.0, seed=3):
+    """Non-overlapping discs/spheres of radius r (cell of unit size), centres
+    by RSA; a grid point is inside when its minimum-image distance to a centre
+    is < r."""
+    N = tuple(N)
+    d = len(N)
+    C = rsa_centres(d, count, r, seed)
+    X = mesh(N)
+    inside = np.zeros(N, dtype=bool)
+    for c in C:
+        dist2 = np.zeros(N)
+        for a in range(d):
+            dx = X[a] - (c[a] - 0.5)       # centres drawn in [0,1) -> cell [-1/2, 1/2)
+            dx -= np.round(dx)
+            dist2 += dx * dx
+        inside |= dist2 < r * r
+    return np.where(inside, a_in, a_out).astype(np.float64)
+
+
+def gaussian_field(M, ell=0.1, sigma=1.5, seed=4):
+    """Stationary Gaussian field on the periodic grid M by circulant embedding:
+    lambda = DFT of the periodised covariance sigma^2 exp(-|r|^2 / (2 ell^2))
+    (minimum-image r), negative eigenvalues clipped to 0, g = IDFT(sqrt(lambda)
+    DFT(w)) for white N(0,1) noise w; the sample mean is removed."""
+    M = tuple(M)
+    X = mesh(M)
+    r2 = np.zeros(M)
+    for x in X:
+        r2 += x * x                 # coordinates are already minimum-image in [-1/2, 1/2)
+    cov = sigma ** 2 * np.exp(-r2 / (2 * ell * ell))
+    lam = np.fft.fftn(cov).real
+    lam = np.maximum(lam, 0.0)
+    w = normal(seed, int(np.prod(M))).reshape(M)
+    g = np.fft.ifftn(np.sqrt(lam) * np.fft.fftn(w)).real
+    return g - g.mean()
+
+
+def lognormal_diag(M, factors=(1.0, 2.0, 0.5), ell=0.1, sigma=1.5, seed=4):
+    """Diagonal coefficient field A = exp(g) diag(factors) on grid M:
+    returns (nA=d, *M)."""
+    g = gaussian_field(M, ell, sigma, seed)
+    eg = np.exp(g)
+    return np.stack([f * eg for f in factors])
+
+
+def laminate(N, values_along_axis0):
+    """Isotropic laminate a(x_1): values given per grid index along axis 0."""
+    N = tuple(N)
+    v = np.asarray(values_along_axis0, dtype=np.float64)
+    assert v.shape == (N[0],)
+    return np.broadcast_to(v.reshape((N[0],) + (1,) * (len(N) - 1)), N).copy()
+
+
+def random_spd_field(N, kind, seed, contrast=10.0):
+    """Random SPD coefficient field of the given kind (0 iso, 1 diag,
+    2 full symmetric) with eigenvalues in [1, contrast]."""
+    N = tuple(N)
+    d = len(N)
+    n = int(np.prod(N))
+    if kind == 0:
+        return (1.0 + (contrast - 1.0) * uniform(seed, n)).reshape(N)
+    if kind == 1:
+        return (1.0 + (contrast - 1.0) * uniform(seed, d * n)).reshape((d,) + N)
+    # full symmetric: Q diag(l) Q^T with Q from a random rotation per point
+    lam = 1.0 + (contrast - 1.0) * uniform(seed, d * n).reshape(n, d)
+    g = normal(seed + 1, d * d * n).reshape(n, d, d)
+    Qm, _ = np.linalg.qr(g)
+    A = np.einsum("pab,pb,pcb->pac", Qm, lam, Qm)
+    if d == 1:
+        idx = [(0, 0)]
+    elif d == 2:
+        idx = [(0, 0), (1, 1), (0, 1)]
+    else:
+        idx = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    return np.stack([A[:, a, b].reshape(N) for a, b in idx])
+
+
+# --------------------------------------------------------------------------
+# named workloads (the configurations the library is measured on)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    d: int
+    N: tuple
+    scheme: int            # 0 GaNi, 1 Ga
+    kind: int              # 0 iso, 1 diag, 2 full symmetric
+    A: np.ndarray          # (nA, *Q) or Q for iso
+    E: np.ndarray          # (L, d)
+    tol: float
+    info: dict = field(default_factory=dict)
+
+
+def cfg1_square():
+    """2-D, N = 15^2, centred square of conductivity 10 in a matrix of 1,
+    E = (1, 0), tol 1e-8 (grid samples |x_a| < 0.25 give 7x7 pixels)."""
+    N = (15, 15)
+    A = square_inclusion(N, 0.25, 10.0, 1.0)
+    return Workload("square-15x15-fp64", 2, N, 0, 0, A, np.array([[1.0, 0.0]]), 1e-8,
+                    {"vf": float((A > 1).mean()), "contrast": 10.0})
+
+
+def cfg2_pixels(N=(1023, 1023), seed=2):
+    """2-D two-phase pixels: Bernoulli(0.4) + 3 majority passes, phases 100 / 1,
+    E = e1, e2, tol 1e-6."""
+    A = bernoulli_majority(N, 0.4, 3, 100.0, 1.0, seed)
+    return Workload(f"pixels-{N[0]}x{N[1]}", 2, tuple(N), 0, 0, A, np.eye(2), 1e-6,
+                    {"vf": float((A > 1).mean()), "contrast": 100.0, "seed": seed})
+
+
+def cfg3_spheres(N=(255, 255, 255), count=60, r=0.06, seed=3):
+    """3-D, 60 RSA spheres of radius 0.06, conductivity 1e3 / 1, E = e1..e3."""
+    A = inclusions(N, count, r, 1e3, 1.0, seed)
+    return Workload(f"spheres-{N[0]}^3", 3, tuple(N), 0, 0, A, np.eye(3), 1e-6,
+                    {"vf": float((A > 1).mean()), "contrast": 1e3, "seed": seed})
+
+
+def cfg4_lognormal(N=(127, 127, 127), seed=4):
+    """3-D Ga: trial grid N, lognormal diagonal coefficient on the 2N-1 grid."""
+    M = tuple(2 * n - 1 for n in N)
+    A = lognormal_diag(M, (1.0, 2.0, 0.5), 0.1, 1.5, seed)
+    lo = float(A.min(axis=0).min())
+    hi = float(A.max(axis=0).max())
+    return Workload(f"lognormal-Ga-{N[0]}^3-on-{M[0]}^3", 3, tuple(N), 1, 1, A, np.eye(3), 1e-6,
+                    {"contrast": hi / lo, "seed": seed})
+
+
+@dataclass
+class Request:
+    idx: int
+    arrival: float
+    d: int
+    N: tuple
+    A: np.ndarray
+    E: np.ndarray
+    tol: float
+    contrast: float
+    kind_micro: str
+
+
+def serving_stream(n_requests=10_000, rate=500.0, seed=5, sizes2=(63, 127, 255),
+                   sizes3=(31, 63, 127), tol=1e-6, materialize=True):
+    """Seeded request stream: Poisson arrivals (mean rate), d in {2,3} with
+    p = 1/2, N uniform from the size list, half RSA inclusions (count U{5..40}
+    in 2-D, U{10..60} in 3-D, r = 0.06), half Bernoulli pixels (p = 0.4, 3
+    majority passes), contrast 10^(1+3u), L = 1 + floor(u d) load cases e_1..e_L.
+    Per-request randomness uses seed_i = splitmix(seed, i)."""
+    t = 0.0
+    out = []
+    head = uniform(seed, n_requests)
+    for i in range(n_requests):
+        si = splitmix_one(seed, i + 1)
+        u = uniform(si, 8)
+        t += -math.log(1.0 - head[i]) / rate
+        d = 2 if u[0] < 0.5 else 3
+        sizes = sizes2 if d == 2 else sizes3
+        n = sizes[min(int(u[1] * len(sizes)), len(sizes) - 1)]
+        N = (n,) * d
+        contrast = 10.0 ** (1.0 + 3.0 * u[2])
+        L = 1 + min(int(u[3] * d), d - 1)
+        incl = u[4] < 0.5
+        A = None
+        if materialize:
+            if incl:
+                lo, hi = (5, 40) if d == 2 else (10, 60)
+                cnt = lo + min(int(u[5] * (hi - lo + 1)), hi - lo)
+                A = inclusions(N, cnt, 0.06, contrast, 1.0, seed=si)
+            else:
+                A = bernoulli_majority(N, 0.4, 3, contrast, 1.0, seed=si)
+        out.append(Request(i, t, d, N, A, np.eye(d)[:L], tol, contrast,
+                           "inclusions" if incl else "pixels"))
+    return out
