@@ -1,0 +1,162 @@
+/*
+ * hom.h -- C ABI of the MI355X FFT-Galerkin homogenization library.
+ *
+ * Solves the periodic cell problem of Vondrejc, Zeman & Marek, "An FFT-based
+ * Galerkin method for homogenization of periodic media": find the zero-mean
+ * curl-free fluctuation e~ in E_N with
+ *     G_N A_N e~ = -G_N A_N E                                (Sec. 5.2, Prop.)
+ * by conjugate gradients (Sec. 5.3, Lemma on CG), where
+ *     G_N = F_N^-1 Gamma^ F_N,  Gamma^(k) = xi xi^T / (xi . xi),  Gamma^(0) = 0
+ * with reference A0 = I (Sec. 3.2, Gamma hat; Sec. 5.1, FFT matrices), on a
+ * grid of odd size N (assumption A4).  Two quadratures are offered:
+ *   HOM_GANI -- A sampled on the trial grid N (Galerkin with numerical
+ *               integration, Sec. 4.3; the Moulinec-Suquet discretisation);
+ *   HOM_GA   -- A sampled on the doubled grid M = 2N - 1, where the product of
+ *               two trial polynomials is integrated exactly (Galerkin with
+ *               exact integration, Sec. 4.2, for the coefficient Q_M[A]).
+ * The homogenized coefficient is the energy W_lm = <(E_l + e~_l) . A
+ * (E_m + e~_m)> on the quadrature grid (A_H = W for E = I).
+ *
+ * Conventions (Sec. 4.1): the cell is prod [-Y_a, Y_a]; grid point index i
+ * along an axis of length n holds x = k h with k = i if i <= (n-1)/2 else
+ * i - n and h = 2Y/n ("FFT order", origin at index 0).  Arrays are C-order
+ * with the last axis contiguous.  A coefficient field has nA planes of the
+ * quadrature grid: nA = 1 (HOM_A_ISO: a I), d (HOM_A_DIAG) or d(d+1)/2
+ * (HOM_A_FULLSYM, Voigt order 11,22,33,23,13,12; in 2-D 11,22,12).
+ *
+ * Errors: every function returns a hom_status; nothing aborts or throws.
+ * Ownership: the caller owns every buffer it passes; the library copies what
+ * it keeps.  Threading: a cell is not re-entrant; distinct cells may be used
+ * from distinct threads.  Device pointers are HIP device pointers of the
+ * current device.
+ */
+#ifndef HOM_H
+#define HOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hom_cell hom_cell;
+typedef struct hom_server hom_server;
+
+typedef enum {
+  HOM_OK = 0,
+  HOM_EINVAL = -1,      /* bad argument: d, even N, sizes, non-finite values, tol <= 0, L < 1 */
+  HOM_ENOTSPD = -2,     /* A not symmetric positive definite at some point (A2) */
+  HOM_ENOMEM = -3,      /* device or host allocation failed, or over the server budget */
+  HOM_ENOTCONV = -4,    /* max_iter reached; the best iterate and info are still returned */
+  HOM_EBREAKDOWN = -5,  /* CG breakdown ((p, q) <= 0 or not finite) */
+  HOM_EDEVICE = -6,     /* HIP runtime error */
+  HOM_EBUSY = -7        /* server: request not finished yet */
+} hom_status;
+
+typedef enum { HOM_A_ISO = 0, HOM_A_DIAG = 1, HOM_A_FULLSYM = 2 } hom_a_kind;
+typedef enum { HOM_GANI = 0, HOM_GA = 1 } hom_scheme;
+/* HOM_FP64: FFTs, fields and reductions in FP64.
+ * HOM_MIXED: inner CG with FP32 FFTs and fields (FP64 dots and step
+ * lengths) inside an FP64 iterative-refinement loop whose residual uses the
+ * FP64 operator. */
+typedef enum { HOM_FP64 = 0, HOM_MIXED = 1 } hom_prec;
+
+typedef struct {
+  hom_scheme scheme;   /* default HOM_GANI */
+  hom_prec prec;       /* default HOM_FP64 */
+  double Y[3];         /* cell half-lengths, default 0.5 (unit cell) */
+  int max_iter;        /* CG iterations per (inner) solve, default 10000 */
+  int max_outer;       /* refinement steps (HOM_MIXED), default 30 */
+  double inner_tol;    /* relative residual of each inner FP32 solve, default 1e-4 */
+  int check_every;     /* iterations per captured graph between host checks, default 16 */
+  void* stream;        /* hipStream_t the caller orders work against, or NULL */
+} hom_options;
+
+typedef struct {
+  int iters_inner;       /* CG iterations (summed over refinement steps), max over load cases */
+  int iters_outer;       /* refinement steps (HOM_MIXED), 0 for HOM_FP64 */
+  double rel_resid_true; /* ||b - Op x|| / ||b|| with the FP64 operator, max over load cases */
+  double rho_A;          /* contrast C_A / c_A of the coefficient field (A2) */
+  double seconds;        /* wall time of the call */
+} hom_info;
+
+/* Fill *opt with the defaults above. */
+hom_status hom_options_default(hom_options* opt);
+
+/* Create a cell on the current device.
+ *  d        1, 2 or 3 (d = 1 runs as a 2-D cell with one grid point along axis 2)
+ *  N        d odd trial sizes (A4), each >= 1
+ *  kind     coefficient storage, see above
+ *  A        [nA][Q grid] FP64, Q = N (GaNi) or 2N-1 (Ga); host pointer, or a device
+ *           pointer when A_on_device != 0.  Copied; the caller may free it on return.
+ *  opt      options (NULL for defaults); scheme and Y are fixed for the cell
+ * Validates A (finite, symmetric positive definite at every point, A2) and
+ * records its contrast.  Errors: HOM_EINVAL, HOM_ENOTSPD, HOM_ENOMEM, HOM_EDEVICE. */
+hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const double* A,
+                           int A_on_device, const hom_options* opt, hom_cell** out);
+
+/* Solve L load cases.
+ *  E        [L][d] host, macroscopic gradients (Sec. 1, the split e = E + e~)
+ *  tol      stopping test ||r_i|| / ||r_0|| <= tol (HOM_FP64) or the outer
+ *           FP64 residual ||b - Op x|| / ||b|| <= tol (HOM_MIXED); tol > 0
+ *  strain   nullable device pointer, [L][d][N grid] FP64: total strain E + e~
+ *  W        nullable host pointer, [L][L] energies (A_H when E = I)
+ *  J        nullable host pointer, [L][d] mean fluxes <A (E_l + e~_l)>
+ *  strain0  nullable device pointer [L][d][N grid] FP64: warm start; its
+ *           E_N component is used (re-projected by G, Sec. 5.3 Lemma)
+ *  info     nullable
+ * Errors: HOM_EINVAL, HOM_ENOTCONV (results still written), HOM_EBREAKDOWN,
+ * HOM_ENOMEM, HOM_EDEVICE. */
+hom_status hom_solve(hom_cell* c, int L, const double* E, double tol, double* strain, double* W,
+                     double* J, const double* strain0, hom_info* info);
+
+/* One application of the system operator to L real fields:
+ * out = G_N A_N G_N u (Ga: the exact-integration operator), u and out device
+ * pointers [L][d][N grid] FP64; prec chooses FP64 or FP32 arithmetic inside.
+ * For u in E_N this is the operator of the linear system (Sec. 5.2). */
+hom_status hom_apply(hom_cell* c, hom_prec prec, int L, const double* u, double* out);
+
+/* Projection onto E_N: out = G_N u, device pointers [L][d][N grid] FP64. */
+hom_status hom_project(hom_cell* c, int L, const double* u, double* out);
+
+/* Time the kernels of one CG iteration on L load cases (reps repetitions
+ * each, HIP events on the cell's stream).  ms[0..7] receives the mean
+ * duration per launch of: axis-0 expand, axis-1 inverse, last-axis flux pass,
+ * axis-1 forward, axis-0 project, CG update, and the scalar kernels
+ * (alpha + beta); ms[7] the whole iteration.  bytes[0..7] receives the
+ * algorithmic HBM bytes of the same launches (each input read once, each
+ * output written once). */
+hom_status hom_profile_iteration(hom_cell* c, hom_prec prec, int L, int reps, double* ms,
+                                 double* bytes);
+
+void hom_destroy_cell(hom_cell* c);
+const char* hom_status_str(hom_status s);
+/* Grid sizes of a cell: N[3], Q[3] (unused axes 1), d. */
+hom_status hom_cell_dims(const hom_cell* c, int32_t* d, int32_t* N, int32_t* Q);
+
+/* ---- continuous batching ------------------------------------------------
+ * A server owns a background thread that admits submitted requests while
+ * their device footprint fits the budget, packs requests of equal (d, N,
+ * scheme) into batched iterations replayed as HIP graphs with per-request
+ * convergence masks, retires converged requests and admits waiting ones into
+ * the freed slots.  Requests are solved with the server's precision. */
+hom_status hom_server_create(size_t hbm_budget_bytes, const hom_options* opt, hom_server** out);
+/* Queue one request on cell c (the cell must outlive the request).  E [L][d]
+ * host, copied.  *ticket receives its id.  HOM_ENOMEM if the request alone
+ * exceeds the budget. */
+hom_status hom_server_submit(hom_server* s, hom_cell* c, int L, const double* E, double tol,
+                             uint64_t* ticket);
+/* HOM_EBUSY until the request is done; then its status, W [L][L], J [L][d]
+ * (both nullable) and info.  A finished ticket can be polled once. */
+hom_status hom_server_poll(hom_server* s, uint64_t ticket, double* W, double* J, hom_info* info);
+/* Per-request timestamps of a finished ticket (seconds since server start):
+ * t[0] submit, t[1] admit, t[2] done.  Call before polling it. */
+hom_status hom_server_times(hom_server* s, uint64_t ticket, double* t);
+/* Drain and stop the worker, free everything. */
+hom_status hom_server_destroy(hom_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

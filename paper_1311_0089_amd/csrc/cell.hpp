@@ -1,0 +1,90 @@
+// cell.hpp -- internal cell, workspace and pipeline declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "hom.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace hom {
+
+// device buffers of one precision for `items` solver items
+template <class T>
+struct Work {
+  int items = 0;
+  cpx<T>* x = nullptr;   // iterate (scalar potential)      [items][S]
+  cpx<T>* r = nullptr;   // residual                        [items][S]
+  cpx<T>* p = nullptr;   // search direction                [items][S]
+  cpx<T>* q = nullptr;   // operator output                 [items][S]
+  cpx<T>* b = nullptr;   // right-hand side                 [items][S]
+  cpx<T>* X1 = nullptr;  // component spectra, ping         [items][d][Xe]
+  cpx<T>* X2 = nullptr;  // component spectra, pong         [items][d][Xe]
+  double* part = nullptr;   // partial sums                 [items][P]
+  double* part2 = nullptr;  // second partial buffer        [items][P]
+  ItemScal* sc = nullptr;   // solver scalars               [items]
+  std::vector<void*> owned;
+  ~Work();
+  hipError_t alloc(int items, long S, long Xe, int d, int P);
+};
+
+struct GraphKey {
+  int prec, items, K;
+  bool operator<(const GraphKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (items != o.items) return items < o.items;
+    return K < o.K;
+  }
+};
+
+struct CellImpl {
+  int d = 0, dd = 0;          // user dimension, dimension run on the device (>= 2)
+  int N[3] = {1, 1, 1};       // trial grid (device dims)
+  int Q[3] = {1, 1, 1};       // quadrature grid
+  int scheme = HOM_GANI, kind = HOM_A_ISO, nA = 1;
+  double Y[3] = {0.5, 0.5, 0.5};
+  hom_options opt{};
+  double rhoA = 1.0;
+  long S = 0;                 // scalar spectrum elements per item
+  long Xe = 0;                // component-spectrum elements per component per item
+  long nN = 0, nQ = 0;        // grid points
+  int H = 0;                  // half-spectrum bins of the last axis
+  double* A64 = nullptr;      // [nA][Q]
+  float* A32 = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Work<double> w64;
+  Work<float> w32;
+  double* ebuf = nullptr;     // FP64 real strain scratch [items][d][Q]
+  long ebuf_items = 0;
+  double* quad = nullptr;     // quadrature partials / outputs
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::mutex mu;
+  ~CellImpl();
+};
+
+// pipeline entry points (solver.hip)
+hipError_t cell_setup(CellImpl* c);
+hipError_t ensure_work(CellImpl* c, int items, bool need32);
+template <class T>
+Work<T>& work_of(CellImpl* c);
+
+// RHS b = -n . F[A E] (with r = p = b, x = 0) and rho0 = (b, b)
+template <class T>
+hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemScal* sc);
+// q = Op(in) with epilogue epi
+template <class T>
+hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse, int epi,
+                      cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
+                      double* partials);
+// real strain on grid G (G = N or Q) from the potential: e = E + F_G^-1 Pad(n c)
+hipError_t pipe_synth(CellImpl* c, int items, const cpx<double>* cin, const double* dE,
+                      bool onQ, double* out);
+// scalar potential of a real field u on the N grid: c = n . F_N[u]
+hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double>* cout);
+
+}  // namespace hom

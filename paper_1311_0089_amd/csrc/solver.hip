@@ -1,0 +1,1164 @@
+// solver.hip -- cell setup, operator pipelines, CG drivers (FP64 and mixed
+// FP32/FP64 refinement), energy quadrature and the C ABI of hom.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cell.hpp"
+
+struct hom_cell {
+  hom::CellImpl impl;
+};
+
+namespace hom {
+
+// dynamic LDS budgets leave 1 KiB for the static LDS of the block reductions
+static size_t g_lds_budget = 63 * 1024;   // preferred: two or more workgroups per CU
+static size_t g_lds_max = 63 * 1024;      // device limit minus headroom (set once)
+static bool g_configured = false;
+static std::mutex g_cfg_mu;
+
+static hipError_t ensure_configured() {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  if (g_configured) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return e;
+  size_t mx = prop.sharedMemPerBlock;
+  if (mx < 64 * 1024) mx = 64 * 1024;
+  if (mx > 160 * 1024) mx = 160 * 1024;
+  e = configure_kernels(mx);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    mx = 64 * 1024;
+    e = configure_kernels(mx);
+  }
+  g_lds_max = mx - 1024;
+  g_configured = (e == hipSuccess);
+  return e;
+}
+
+template <class T>
+Work<T>::~Work() {
+  for (void* p : owned) (void)hipFree(p);
+}
+
+template <class T>
+hipError_t Work<T>::alloc(int n, long S, long Xe, int d, int P) {
+  for (void* p : owned) (void)hipFree(p);
+  owned.clear();
+  items = 0;
+  auto get = [&](void** ptr, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(ptr, bytes > 0 ? bytes : 16);
+    if (e == hipSuccess) owned.push_back(*ptr);
+    return e;
+  };
+  const size_t sv = sizeof(cpx<T>) * (size_t)S * n;
+  const size_t xv = sizeof(cpx<T>) * (size_t)Xe * d * n;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = get((void**)&x, sv);
+  if (e == hipSuccess) e = get((void**)&r, sv);
+  if (e == hipSuccess) e = get((void**)&p, sv);
+  if (e == hipSuccess) e = get((void**)&q, sv);
+  if (e == hipSuccess) e = get((void**)&b, sv);
+  if (e == hipSuccess) e = get((void**)&X1, xv);
+  if (e == hipSuccess) e = get((void**)&X2, xv);
+  if (e == hipSuccess) e = get((void**)&part, sizeof(double) * (size_t)P * n);
+  if (e == hipSuccess) e = get((void**)&part2, sizeof(double) * (size_t)P * n);
+  if (e == hipSuccess) e = get((void**)&sc, sizeof(ItemScal) * (size_t)n);
+  if (e == hipSuccess) items = n;
+  return e;
+}
+template struct Work<float>;
+template struct Work<double>;
+
+template <>
+Work<double>& work_of<double>(CellImpl* c) { return c->w64; }
+template <>
+Work<float>& work_of<float>(CellImpl* c) { return c->w32; }
+
+CellImpl::~CellImpl() {
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  if (A64) (void)hipFree(A64);
+  if (A32) (void)hipFree(A32);
+  if (ebuf) (void)hipFree(ebuf);
+  if (quad) (void)hipFree(quad);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+// ---------------------------------------------------------------------------
+// launch shapes
+// ---------------------------------------------------------------------------
+struct ColShape {
+  int W = 0;
+  size_t lds = 0;
+};
+
+static hipError_t col_shape(const FftPlan& p, int npos_rows, int inner, int esz, ColShape* s) {
+  s->W = choose_col_W(p, npos_rows, inner, esz, g_lds_budget, &s->lds);
+  if (!s->W) s->W = choose_col_W(p, npos_rows, inner, esz, g_lds_max, &s->lds);
+  return s->W ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+static hipError_t row_shape(const FftPlan& p, int d, long rows, int esz, int* RP, size_t* lds) {
+  *RP = choose_row_RP(p, d, rows, esz, g_lds_budget, lds);
+  if (!*RP) *RP = choose_row_RP(p, d, rows, esz, g_lds_max, lds);
+  return *RP ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+template <class T>
+static const cpx<T>* tw_of(const DevPlan* p);
+template <>
+const cpx<double>* tw_of<double>(const DevPlan* p) { return p->tw64; }
+template <>
+const cpx<float>* tw_of<float>(const DevPlan* p) { return p->tw32; }
+
+static int update_blocks(long S) {
+  long b = (S + kThreads - 1) / kThreads;
+  if (b > 512) b = 512;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+static int partial_slots(const CellImpl* c) {
+  // enough for every producer: column tiles (<= inner) and update blocks
+  long inner = (c->dd == 3) ? (long)c->N[1] * c->H : c->H;
+  long P = std::max<long>(inner, 512);
+  return (int)P;
+}
+
+hipError_t cell_setup(CellImpl* c) {
+  hipError_t e = ensure_configured();
+  if (e != hipSuccess) return e;
+  const int dd = c->dd;
+  c->H = (c->N[dd - 1] + 1) / 2;
+  c->nN = 1;
+  c->nQ = 1;
+  for (int a = 0; a < dd; ++a) {
+    c->nN *= c->N[a];
+    c->nQ *= c->Q[a];
+  }
+  c->S = (long)c->H;
+  c->Xe = (long)c->H;
+  for (int a = 0; a < dd - 1; ++a) {
+    c->S *= c->N[a];
+    c->Xe *= c->Q[a];
+  }
+  // plans for every length used
+  const DevPlan* p = nullptr;
+  for (int a = 0; a < dd; ++a) {
+    if ((e = get_dev_plan(c->Q[a], &p)) != hipSuccess) return e;
+    if ((e = get_dev_plan(c->N[a], &p)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t ensure_work(CellImpl* c, int items, bool need32) {
+  const int P = partial_slots(c);
+  hipError_t e = hipSuccess;
+  bool realloc = false;
+  if (c->w64.items < items) {
+    if ((e = c->w64.alloc(items, c->S, c->Xe, c->dd, P)) != hipSuccess) return e;
+    realloc = true;
+  }
+  if (need32 && c->w32.items < items) {
+    if ((e = c->w32.alloc(items, c->S, c->Xe, c->dd, P)) != hipSuccess) return e;
+    realloc = true;
+  }
+  if (realloc) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+  }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// pipeline stages on the quadrature grid
+// ---------------------------------------------------------------------------
+static NormalGeo normal_geo(const CellImpl* c) {
+  NormalGeo g{};
+  g.d = c->dd;
+  g.N1 = (c->dd == 3) ? c->N[1] : 1;
+  g.H = c->H;
+  for (int a = 0; a < 3; ++a) g.invY[a] = 1.0 / c->Y[a];
+  return g;
+}
+
+static long inner0(const CellImpl* c) { return (c->dd == 3) ? (long)c->N[1] * c->H : c->H; }
+
+template <class T>
+static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse,
+                               int G0, ItemScal* sc) {
+  const DevPlan* p0;
+  hipError_t e = get_dev_plan(G0, &p0);
+  if (e != hipSuccess) return e;
+  ColExpandArgs<T> a{};
+  a.c = fuse ? w.p : in;
+  a.r = w.r;
+  a.p = w.p;
+  a.X = w.X1;
+  a.c_stride = c->S;
+  a.X_stride = (long)c->dd * c->Xe;
+  a.X_cstride = c->Xe;
+  a.n_in = c->N[0];
+  a.n_fft = G0;
+  a.inner = (int)inner0(c);
+  a.fuse = fuse;
+  a.g = normal_geo(c);
+  a.plan = p0->p;
+  a.tw = tw_of<T>(p0);
+  a.sc = sc;
+  ColShape sh;
+  if ((e = col_shape(p0->p, c->N[0], a.inner, sizeof(cpx<T>), &sh)) != hipSuccess) return e;
+  a.W = sh.W;
+  return launch_col_expand<T>(a, items, sh.lds, c->stream);
+}
+
+// axis-1 pass (3-D): inverse with padding N1 -> G1, or forward with truncation G1 -> N1
+template <class T>
+static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int G0, int G1,
+                              const cpx<T>* in, cpx<T>* out, ItemScal* sc) {
+  const DevPlan* p1;
+  hipError_t e = get_dev_plan(G1, &p1);
+  if (e != hipSuccess) return e;
+  (void)w;
+  ColPlainArgs<T> a{};
+  a.in = in;
+  a.out = out;
+  a.in_stride = a.out_stride = (long)c->dd * c->Xe;
+  a.in_cstride = a.out_cstride = c->Xe;
+  a.outer = G0;
+  a.n_fft = G1;
+  a.n_in = (sign > 0) ? c->N[1] : G1;
+  a.n_out = (sign > 0) ? G1 : c->N[1];
+  a.inner = c->H;
+  a.d = c->dd;
+  a.scale = (sign > 0) ? T(1) : T(1.0 / (double)G1);
+  a.plan = p1->p;
+  a.tw = tw_of<T>(p1);
+  a.sc = sc;
+  ColShape sh;
+  if ((e = col_shape(p1->p, std::max(a.n_in, a.n_out), a.inner, sizeof(cpx<T>), &sh)) !=
+      hipSuccess)
+    return e;
+  a.W = sh.W;
+  return launch_col_plain<T>(a, items, sign, sh.lds, c->stream);
+}
+
+template <class T>
+static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, cpx<T>* out,
+                            int G0, int G1, int Glast, const double* ureal, double* oreal,
+                            const double* dE, ItemScal* sc) {
+  const DevPlan* pl;
+  hipError_t e = get_dev_plan(Glast, &pl);
+  if (e != hipSuccess) return e;
+  RowArgs<T> a{};
+  a.in = in;
+  a.out = out;
+  a.in_stride = a.out_stride = (long)c->dd * c->Xe;
+  a.in_cstride = a.out_cstride = c->Xe;
+  const long rows = (c->dd == 3) ? (long)G0 * G1 : G0;
+  a.ureal = ureal;
+  a.oreal = oreal;
+  a.real_cstride = rows * Glast;
+  a.real_stride = (long)c->dd * a.real_cstride;
+  a.A = (sizeof(T) == 8) ? (const T*)(const void*)c->A64 : (const T*)(const void*)c->A32;
+  a.A_stride = 0;
+  a.A_cstride = c->nQ;
+  a.kind = c->kind;
+  a.E = dE;
+  a.d = c->dd;
+  a.rows = (int)rows;
+  a.n = Glast;
+  a.H = c->H;
+  a.plan = pl->p;
+  a.tw = tw_of<T>(pl);
+  a.sc = sc;
+  size_t lds = 0;
+  int RP = 0;
+  if ((e = row_shape(pl->p, c->dd, rows, sizeof(cpx<T>), &RP, &lds)) != hipSuccess) return e;
+  a.RP = RP;
+  return launch_row<T>(a, items, mode, lds, c->stream);
+}
+
+template <class T>
+static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>* X, int G0,
+                                int epi, cpx<T>* out, const cpx<T>* pdot, cpx<T>* r, cpx<T>* pp,
+                                cpx<T>* x, const cpx<T>* b, double* partials, ItemScal* sc,
+                                int* tiles) {
+  const DevPlan* p0;
+  hipError_t e = get_dev_plan(G0, &p0);
+  if (e != hipSuccess) return e;
+  (void)w;
+  ColProjectArgs<T> a{};
+  a.X = X;
+  a.X_stride = (long)c->dd * c->Xe;
+  a.X_cstride = c->Xe;
+  a.q = out;
+  a.s_stride = c->S;
+  a.p = pdot;
+  a.r = r;
+  a.pp = pp;
+  a.x = x;
+  a.b = b;
+  a.partials = partials;
+  a.P = partial_slots(c);
+  a.n_fft = G0;
+  a.n_out = c->N[0];
+  a.inner = (int)inner0(c);
+  a.epi = epi;
+  a.d = c->dd;
+  a.scale = T(1.0 / (double)G0);
+  a.g = normal_geo(c);
+  a.plan = p0->p;
+  a.tw = tw_of<T>(p0);
+  a.sc = sc;
+  ColShape sh;
+  if ((e = col_shape(p0->p, c->N[0], a.inner, sizeof(cpx<T>), &sh)) != hipSuccess) return e;
+  a.W = sh.W;
+  if (tiles) *tiles = (a.inner + sh.W - 1) / sh.W;
+  return launch_col_project<T>(a, items, sh.lds, c->stream);
+}
+
+template <class T>
+static int project_tiles(CellImpl* c) {
+  const DevPlan* p0;
+  if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
+  ColShape sh;
+  const int inner = (int)inner0(c);
+  if (col_shape(p0->p, c->N[0], inner, sizeof(cpx<T>), &sh) != hipSuccess) return 0;
+  return (inner + sh.W - 1) / sh.W;
+}
+
+// q = Op(in) on the quadrature grid
+template <class T>
+hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse, int epi,
+                      cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
+                      double* partials) {
+  hipError_t e;
+  const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
+  if ((e = stage_expand<T>(c, w, items, in, fuse, Q0, sc)) != hipSuccess) return e;
+  if (c->dd == 3) {
+    if ((e = stage_axis1<T>(c, w, items, +1, Q0, Q1, w.X1, w.X2, sc)) != hipSuccess) return e;
+    if ((e = stage_row<T>(c, items, ROW_APPLY, w.X2, w.X2, Q0, Q1, Q2, nullptr, nullptr, nullptr,
+                          sc)) != hipSuccess)
+      return e;
+    if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc)) != hipSuccess) return e;
+  } else {
+    if ((e = stage_row<T>(c, items, ROW_APPLY, w.X1, w.X1, Q0, 1, Q1, nullptr, nullptr, nullptr,
+                          sc)) != hipSuccess)
+      return e;
+  }
+  cpx<T>* rr = (epi == EPI_RESID) ? out : nullptr;
+  return stage_project<T>(c, w, items, w.X1, Q0, epi, out, pdot, rr, nullptr, nullptr, b,
+                          partials, sc, nullptr);
+}
+
+template <class T>
+hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemScal* sc) {
+  hipError_t e;
+  const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
+  if (c->dd == 3) {
+    if ((e = stage_row<T>(c, items, ROW_CONST, nullptr, w.X2, Q0, Q1, Q2, nullptr, nullptr, dE,
+                          sc)) != hipSuccess)
+      return e;
+    if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc)) != hipSuccess) return e;
+  } else {
+    if ((e = stage_row<T>(c, items, ROW_CONST, nullptr, w.X1, Q0, 1, Q1, nullptr, nullptr, dE,
+                          sc)) != hipSuccess)
+      return e;
+  }
+  return stage_project<T>(c, w, items, w.X1, Q0, EPI_RHS, w.b, nullptr, w.r, w.p, w.x, nullptr,
+                          w.part, sc, nullptr);
+}
+
+hipError_t pipe_synth(CellImpl* c, int items, const cpx<double>* cin, const double* dE, bool onQ,
+                      double* out) {
+  hipError_t e;
+  Work<double>& w = c->w64;
+  const int G0 = onQ ? c->Q[0] : c->N[0];
+  const int G1 = onQ ? c->Q[1] : c->N[1];
+  const int G2 = onQ ? c->Q[2] : c->N[2];
+  if ((e = stage_expand<double>(c, w, items, cin, 0, G0, nullptr)) != hipSuccess) return e;
+  if (c->dd == 3) {
+    if ((e = stage_axis1<double>(c, w, items, +1, G0, G1, w.X1, w.X2, nullptr)) != hipSuccess)
+      return e;
+    return stage_row<double>(c, items, ROW_SYNTH, w.X2, nullptr, G0, G1, G2, nullptr, out, dE,
+                             nullptr);
+  }
+  return stage_row<double>(c, items, ROW_SYNTH, w.X1, nullptr, G0, 1, G1, nullptr, out, dE,
+                           nullptr);
+}
+
+hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double>* cout) {
+  hipError_t e;
+  Work<double>& w = c->w64;
+  const int N0 = c->N[0], N1 = c->N[1], N2 = c->N[2];
+  cpx<double>* X = w.X1;
+  if (c->dd == 3) {
+    if ((e = stage_row<double>(c, items, ROW_FWD, nullptr, w.X2, N0, N1, N2, u, nullptr, nullptr,
+                               nullptr)) != hipSuccess)
+      return e;
+    // forward along axis 1 without truncation (N1 -> N1)
+    const DevPlan* p1;
+    if ((e = get_dev_plan(N1, &p1)) != hipSuccess) return e;
+    ColPlainArgs<double> a{};
+    a.in = w.X2;
+    a.out = w.X1;
+    a.in_stride = a.out_stride = (long)c->dd * c->Xe;
+    a.in_cstride = a.out_cstride = c->Xe;
+    a.outer = N0;
+    a.n_in = a.n_fft = a.n_out = N1;
+    a.inner = c->H;
+    a.d = c->dd;
+    a.scale = 1.0 / (double)N1;
+    a.plan = p1->p;
+    a.tw = p1->tw64;
+    ColShape sh;
+    if ((e = col_shape(p1->p, N1, a.inner, sizeof(cpx<double>), &sh)) != hipSuccess) return e;
+    a.W = sh.W;
+    if ((e = launch_col_plain<double>(a, items, -1, sh.lds, c->stream)) != hipSuccess) return e;
+  } else {
+    if ((e = stage_row<double>(c, items, ROW_FWD, nullptr, w.X1, N0, 1, N1, u, nullptr, nullptr,
+                               nullptr)) != hipSuccess)
+      return e;
+  }
+  return stage_project<double>(c, w, items, X, N0, EPI_STORE, cout, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+template hipError_t pipe_apply<float>(CellImpl*, Work<float>&, int, const cpx<float>*, int, int,
+                                      cpx<float>*, const cpx<float>*, const cpx<float>*, ItemScal*,
+                                      double*);
+template hipError_t pipe_apply<double>(CellImpl*, Work<double>&, int, const cpx<double>*, int, int,
+                                       cpx<double>*, const cpx<double>*, const cpx<double>*,
+                                       ItemScal*, double*);
+template hipError_t pipe_rhs<float>(CellImpl*, Work<float>&, int, const double*, ItemScal*);
+template hipError_t pipe_rhs<double>(CellImpl*, Work<double>&, int, const double*, ItemScal*);
+
+// ---------------------------------------------------------------------------
+// CG iterations, captured K at a time into a HIP graph
+// ---------------------------------------------------------------------------
+template <class T>
+static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K) {
+  hipError_t e = hipSuccess;
+  const int P = partial_slots(c);
+  const int tiles = project_tiles<T>(c);
+  const int ub = update_blocks(c->S);
+  for (int k = 0; k < K && e == hipSuccess; ++k) {
+    e = pipe_apply<T>(c, w, items, w.p, 1, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part);
+    if (e == hipSuccess) e = launch_cg_alpha(w.sc, w.part, P, tiles, items, c->stream);
+    if (e == hipSuccess) {
+      CgUpdateArgs<T> u{};
+      u.x = w.x;
+      u.r = w.r;
+      u.p = w.p;
+      u.q = w.q;
+      u.stride = c->S;
+      u.count = c->S;
+      u.H = c->H;
+      u.partials = w.part2;
+      u.P = P;
+      u.sc = w.sc;
+      e = launch_cg_update<T>(u, items, ub, c->stream);
+    }
+    if (e == hipSuccess) e = launch_cg_beta(w.sc, w.part2, P, ub, items, c->stream);
+  }
+  return e;
+}
+
+template <class T>
+static hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
+  GraphKey key{(int)sizeof(T), items, K};
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t eb = cg_body<T>(c, work_of<T>(c), items, K);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->stream, &g);
+  if (eb != hipSuccess) e = eb;
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return e;
+  c->graphs[key] = ex;
+  *out = ex;
+  return hipSuccess;
+}
+
+// run CG until every item is inactive; returns max iterations
+template <class T>
+static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemScal>& hs) {
+  Work<T>& w = work_of<T>(c);
+  const int K = std::max(1, c->opt.check_every);
+  hipGraphExec_t g = nullptr;
+  hipError_t e = cg_graph<T>(c, items, K, &g);
+  if (e != hipSuccess) return e;
+  hs.resize(items);
+  if ((e = hipMemcpyAsync(hs.data(), w.sc, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
+                          c->stream)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  long launched = 0;
+  for (;;) {
+    bool any = false;
+    for (auto& s : hs) any = any || s.active;
+    if (!any) break;
+    if (launched > (long)max_iter + K) break;  // the device also stops at max_iter
+    if ((e = hipGraphLaunch(g, c->stream)) != hipSuccess) return e;
+    launched += K;
+    if ((e = hipMemcpyAsync(hs.data(), w.sc, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static hipError_t upload_E(CellImpl* c, int L, const double* E, double** dE) {
+  // [L][dd] with zero padding for d = 1
+  std::vector<double> h((size_t)L * c->dd, 0.0);
+  for (int l = 0; l < L; ++l)
+    for (int a = 0; a < c->d; ++a) h[(size_t)l * c->dd + a] = E[(size_t)l * c->d + a];
+  hipError_t e = hipMalloc(dE, sizeof(double) * h.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(*dE, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
+static hipError_t sum_partials_host(CellImpl* c, const double* dpart, int items, int nparts,
+                                    std::vector<double>& out) {
+  const int P = partial_slots(c);
+  std::vector<double> h((size_t)items * P);
+  hipError_t e = hipMemcpyAsync(h.data(), dpart, sizeof(double) * h.size(),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  out.assign(items, 0.0);
+  for (int i = 0; i < items; ++i)
+    for (int t = 0; t < nparts; ++t) out[i] += h[(size_t)i * P + t];
+  return hipSuccess;
+}
+
+static hipError_t ensure_ebuf(CellImpl* c, int items) {
+  if (c->ebuf_items >= items) return hipSuccess;
+  if (c->ebuf) (void)hipFree(c->ebuf);
+  c->ebuf = nullptr;
+  c->ebuf_items = 0;
+  hipError_t e = hipMalloc(&c->ebuf, sizeof(double) * (size_t)items * c->dd * c->nQ);
+  if (e == hipSuccess) c->ebuf_items = items;
+  return e;
+}
+
+// W [L][L], J [L][d] from the FP64 potentials x of L items
+static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strain_user,
+                             double* W, double* J) {
+  hipError_t e;
+  const cpx<double>* x = c->w64.x;
+  double* eQ = nullptr;
+  const bool gani = (c->scheme == HOM_GANI);
+  if (gani && strain_user && c->d == c->dd) {
+    eQ = strain_user;
+  } else {
+    if ((e = ensure_ebuf(c, L)) != hipSuccess) return e;
+    eQ = c->ebuf;
+  }
+  if ((e = pipe_synth(c, L, x, dE, true, eQ)) != hipSuccess) return e;
+  if (!c->quad) {
+    if ((e = hipMalloc(&c->quad, sizeof(double) * (1024 * 18 + 64))) != hipSuccess) return e;
+  }
+  const int blocks = (int)std::min<long>(1024, (c->nQ + kThreads - 1) / kThreads);
+  std::vector<double> hW((size_t)L * L, 0.0), hJ((size_t)L * c->dd, 0.0);
+  for (int l0 = 0; l0 < L; l0 += 3) {
+    const int nl = std::min(3, L - l0);
+    for (int m0 = 0; m0 < L; m0 += 3) {
+      const int nm = std::min(3, L - m0);
+      if ((e = launch_quad(eQ, (long)c->dd * c->nQ, c->nQ, c->A64, c->nQ, c->kind, c->dd, c->nQ,
+                           l0, nl, m0, nm, c->quad, blocks, c->stream)) != hipSuccess)
+        return e;
+      double* outp = c->quad + (size_t)1024 * 18;
+      if ((e = launch_quad_final(c->quad, blocks, nl, nm, c->dd, c->nQ, outp, c->stream)) !=
+          hipSuccess)
+        return e;
+      double h[18];
+      if ((e = hipMemcpyAsync(h, outp, sizeof(h), hipMemcpyDeviceToHost, c->stream)) !=
+          hipSuccess)
+        return e;
+      if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+      for (int l = 0; l < nl; ++l)
+        for (int m = 0; m < nm; ++m) hW[(size_t)(l0 + l) * L + m0 + m] = h[l * 3 + m];
+      if (l0 == 0)
+        for (int m = 0; m < nm; ++m)
+          for (int a = 0; a < c->dd; ++a) hJ[(size_t)(m0 + m) * c->dd + a] = h[9 + m * 3 + a];
+    }
+  }
+  if (W) std::memcpy(W, hW.data(), sizeof(double) * hW.size());
+  if (J)
+    for (int l = 0; l < L; ++l)
+      for (int a = 0; a < c->d; ++a) J[(size_t)l * c->d + a] = hJ[(size_t)l * c->dd + a];
+  if (strain_user && eQ != strain_user) {
+    if (gani && c->d == c->dd) {
+      // unreachable: handled above
+    } else if (c->d == c->dd) {
+      if ((e = pipe_synth(c, L, x, dE, false, strain_user)) != hipSuccess) return e;
+    } else {
+      // d = 1 run as 2-D with one point along axis 1: copy component 0 of each item
+      if (!gani) {
+        if ((e = pipe_synth(c, L, x, dE, false, c->ebuf)) != hipSuccess) return e;
+      }
+      for (int l = 0; l < L; ++l) {
+        const double* src = c->ebuf + (size_t)l * c->dd * (gani ? c->nQ : c->nN);
+        if ((e = hipMemcpyAsync(strain_user + (size_t)l * c->nN, src, sizeof(double) * c->nN,
+                                hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+          return e;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+static hipError_t warm_start(CellImpl* c, int L, const double* strain0) {
+  // x0 = n . F_N[strain0] (its E_N part); r = b - Op x0 with partials of
+  // (r, r) in part; p = r
+  Work<double>& w = c->w64;
+  hipError_t e = pipe_project_real(c, L, strain0, w.x);
+  if (e != hipSuccess) return e;
+  if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, nullptr,
+                              w.part)) != hipSuccess)
+    return e;
+  return hipMemcpyAsync(w.p, w.r, sizeof(cpx<double>) * (size_t)c->S * L,
+                        hipMemcpyDeviceToDevice, c->stream);
+}
+
+}  // namespace hom
+
+using namespace hom;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hom_status_str(hom_status s) {
+  switch (s) {
+    case HOM_OK: return "ok";
+    case HOM_EINVAL: return "invalid argument";
+    case HOM_ENOTSPD: return "coefficient not symmetric positive definite";
+    case HOM_ENOMEM: return "out of memory";
+    case HOM_ENOTCONV: return "not converged";
+    case HOM_EBREAKDOWN: return "CG breakdown";
+    case HOM_EDEVICE: return "device error";
+    case HOM_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+hom_status hom_options_default(hom_options* o) {
+  if (!o) return HOM_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->scheme = HOM_GANI;
+  o->prec = HOM_FP64;
+  o->Y[0] = o->Y[1] = o->Y[2] = 0.5;
+  o->max_iter = 10000;
+  o->max_outer = 30;
+  o->inner_tol = 1e-4;
+  o->check_every = 16;
+  o->stream = nullptr;
+  return HOM_OK;
+}
+
+static hom_status dev_status(hipError_t e) {
+  if (e == hipSuccess) return HOM_OK;
+  if (e == hipErrorOutOfMemory) return HOM_ENOMEM;
+  return HOM_EDEVICE;
+}
+
+// eigenvalue range of the coefficient at one point; false if not SPD or not finite
+static bool point_range(int d, int kind, const double* v, double* lo, double* hi) {
+  for (int t = 0; t < (kind == 0 ? 1 : kind == 1 ? d : d * (d + 1) / 2); ++t)
+    if (!std::isfinite(v[t])) return false;
+  if (kind == 0) {
+    *lo = *hi = v[0];
+    return v[0] > 0;
+  }
+  if (kind == 1) {
+    *lo = *hi = v[0];
+    for (int a = 0; a < d; ++a) {
+      *lo = std::min(*lo, v[a]);
+      *hi = std::max(*hi, v[a]);
+    }
+    return *lo > 0;
+  }
+  if (d == 1) {
+    *lo = *hi = v[0];
+    return v[0] > 0;
+  }
+  if (d == 2) {
+    const double a = v[0], b = v[1], c = v[2];
+    const double m = 0.5 * (a + b), r = std::sqrt(0.25 * (a - b) * (a - b) + c * c);
+    *lo = m - r;
+    *hi = m + r;
+    return *lo > 0;
+  }
+  // 3x3 symmetric: closed-form eigenvalues (trigonometric method)
+  const double a00 = v[0], a11 = v[1], a22 = v[2], a12 = v[3], a02 = v[4], a01 = v[5];
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  if (p1 == 0.0) {
+    *lo = std::min(a00, std::min(a11, a22));
+    *hi = std::max(a00, std::max(a11, a22));
+    return *lo > 0;
+  }
+  const double p2 = (a00 - q) * (a00 - q) + (a11 - q) * (a11 - q) + (a22 - q) * (a22 - q) + 2 * p1;
+  const double p = std::sqrt(p2 / 6.0);
+  const double b00 = (a00 - q) / p, b11 = (a11 - q) / p, b22 = (a22 - q) / p;
+  const double b01 = a01 / p, b02 = a02 / p, b12 = a12 / p;
+  const double detB = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
+                      b02 * (b01 * b12 - b11 * b02);
+  double rr = detB / 2.0;
+  rr = std::max(-1.0, std::min(1.0, rr));
+  const double phi = std::acos(rr) / 3.0;
+  const double e1 = q + 2 * p * std::cos(phi);
+  const double e3 = q + 2 * p * std::cos(phi + 2.0 * M_PI / 3.0);
+  *lo = e3;
+  *hi = e1;
+  // Sylvester criterion as the definiteness test (robust against rounding of e3)
+  const double m1 = a00, m2 = a00 * a11 - a01 * a01;
+  const double m3 = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
+                    a02 * (a01 * a12 - a11 * a02);
+  return m1 > 0 && m2 > 0 && m3 > 0 && e3 > 0;
+}
+
+hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const double* A,
+                           int A_on_device, const hom_options* opt, hom_cell** out) {
+  if (!out || !N || !A || d < 1 || d > 3) return HOM_EINVAL;
+  if (kind < HOM_A_ISO || kind > HOM_A_FULLSYM) return HOM_EINVAL;
+  *out = nullptr;
+  hom_options o;
+  if (opt)
+    o = *opt;
+  else
+    hom_options_default(&o);
+  if (o.scheme != HOM_GANI && o.scheme != HOM_GA) return HOM_EINVAL;
+  if (o.prec != HOM_FP64 && o.prec != HOM_MIXED) return HOM_EINVAL;
+  if (o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1) return HOM_EINVAL;
+  if (!(o.inner_tol > 0 && o.inner_tol < 1)) return HOM_EINVAL;
+  for (int a = 0; a < d; ++a) {
+    if (N[a] < 1 || (N[a] % 2) == 0 || N[a] > (1 << 20)) return HOM_EINVAL;
+    if (!(o.Y[a] > 0) || !std::isfinite(o.Y[a])) return HOM_EINVAL;
+  }
+  hom_cell* hc = new (std::nothrow) hom_cell();
+  if (!hc) return HOM_ENOMEM;
+  CellImpl* c = &hc->impl;
+  c->d = d;
+  c->dd = d < 2 ? 2 : d;
+  c->scheme = o.scheme;
+  c->opt = o;
+  const int nA_user = (kind == HOM_A_ISO) ? 1 : (kind == HOM_A_DIAG) ? d : d * (d + 1) / 2;
+  // d = 1 runs as a 2-D cell with a single grid point along the second axis;
+  // its one coefficient acts as an isotropic one (e_2 vanishes identically)
+  c->kind = (d == 1) ? HOM_A_ISO : kind;
+  c->nA = (d == 1) ? 1 : nA_user;
+  for (int a = 0; a < c->dd; ++a) {
+    c->N[a] = (a < d) ? N[a] : 1;
+    c->Q[a] = (o.scheme == HOM_GA) ? 2 * c->N[a] - 1 : c->N[a];
+    c->Y[a] = (a < d) ? o.Y[a] : 0.5;
+  }
+  long nQ = 1;
+  for (int a = 0; a < c->dd; ++a) nQ *= c->Q[a];
+  // host copy of A for validation
+  std::vector<double> hA((size_t)nA_user * nQ);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete hc;
+    return dev_status(e);
+  }
+  if (A_on_device) {
+    e = hipMemcpy(hA.data(), A, sizeof(double) * hA.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      delete hc;
+      return dev_status(e);
+    }
+  } else {
+    std::memcpy(hA.data(), A, sizeof(double) * hA.size());
+  }
+  double lo = INFINITY, hi = 0.0;
+  std::vector<double> v(6);
+  for (long p = 0; p < nQ; ++p) {
+    for (int t = 0; t < nA_user; ++t) v[t] = hA[(size_t)t * nQ + p];
+    double l, h;
+    bool ok = point_range(d, kind, v.data(), &l, &h);
+    if (!ok) {
+      bool finite = true;
+      for (int t = 0; t < nA_user; ++t) finite = finite && std::isfinite(v[t]);
+      delete hc;
+      return finite ? HOM_ENOTSPD : HOM_EINVAL;
+    }
+    lo = std::min(lo, l);
+    hi = std::max(hi, h);
+  }
+  c->rhoA = hi / lo;
+  if (d == 1 && kind == HOM_A_DIAG) {
+    // nothing to do: one plane
+  }
+  // device copies: FP64 and FP32
+  const size_t nAd = (size_t)c->nA * nQ;
+  std::vector<float> hA32(nAd);
+  for (size_t i = 0; i < nAd; ++i) hA32[i] = (float)hA[i];
+  e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&c->A64, sizeof(double) * nAd);
+  if (e == hipSuccess) e = hipMalloc(&c->A32, sizeof(float) * nAd);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->A64, hA.data(), sizeof(double) * nAd, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->A32, hA32.data(), sizeof(float) * nAd, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = cell_setup(c);
+  if (e != hipSuccess) {
+    delete hc;
+    return dev_status(e);
+  }
+  *out = hc;
+  return HOM_OK;
+}
+
+void hom_destroy_cell(hom_cell* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->impl.stream);
+  delete c;
+}
+
+hom_status hom_cell_dims(const hom_cell* c, int32_t* d, int32_t* N, int32_t* Q) {
+  if (!c) return HOM_EINVAL;
+  const CellImpl& i = c->impl;
+  if (d) *d = i.d;
+  for (int a = 0; a < 3; ++a) {
+    if (N) N[a] = (a < i.d) ? i.N[a] : 1;
+    if (Q) Q[a] = (a < i.d) ? i.Q[a] : 1;
+  }
+  return HOM_OK;
+}
+
+static void wait_user_stream(CellImpl* c) {
+  if (!c->opt.stream) return;
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+  (void)hipEventRecord(ev, (hipStream_t)c->opt.stream);
+  (void)hipStreamWaitEvent(c->stream, ev, 0);
+  (void)hipEventDestroy(ev);
+}
+
+hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* strain, double* W,
+                     double* J, const double* strain0, hom_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!hc || L < 1 || !E || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
+  for (int i = 0; i < L * hc->impl.d; ++i)
+    if (!std::isfinite(E[i])) return HOM_EINVAL;
+  CellImpl* c = &hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  const bool mixed = (c->opt.prec == HOM_MIXED);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = ensure_work(c, L, mixed);
+  if (e != hipSuccess) return dev_status(e);
+  wait_user_stream(c);
+  double* dE = nullptr;
+  if ((e = upload_E(c, L, E, &dE)) != hipSuccess) return dev_status(e);
+  hom_status st = HOM_OK;
+  int it_inner = 0, it_outer = 0;
+  double relres = 0.0;
+  std::vector<ItemScal> hs;
+  std::vector<int> inner_sum(L, 0);
+  Work<double>& w = c->w64;
+  const int P = partial_slots(c);
+  do {
+    // right-hand side b = -n . F[A E], r = p = b, x = 0; partials of (b, b)
+    if ((e = launch_set_scal(w.sc, L, tol, mixed ? c->opt.max_outer : c->opt.max_iter, 1,
+                             c->stream)) != hipSuccess)
+      break;
+    if ((e = pipe_rhs<double>(c, w, L, dE, nullptr)) != hipSuccess) break;
+    const int tiles64 = project_tiles<double>(c);
+    std::vector<double> bb;   // (b, b) per load case, for the true relative residual
+    if ((e = sum_partials_host(c, w.part, L, tiles64, bb)) != hipSuccess) break;
+    if (!mixed) {
+      if (strain0 && (e = warm_start(c, L, strain0)) != hipSuccess) break;
+      // rho0 = (r0, r0): of b, or of the warm residual written by warm_start
+      if ((e = launch_cg_init(w.sc, w.part, P, tiles64, L, c->stream)) != hipSuccess) break;
+      if ((e = cg_run<double>(c, L, c->opt.max_iter, hs)) != hipSuccess) break;
+      for (auto& s : hs) {
+        it_inner = std::max(it_inner, s.iters);
+        if (s.status == -5) st = HOM_EBREAKDOWN;
+        else if (!s.conv && st == HOM_OK) st = HOM_ENOTCONV;
+      }
+    } else {
+      // outer FP64 refinement around inner FP32 CG; rho0 = (b, b)
+      Work<float>& w32 = c->w32;
+      ItemScal* outer = w.sc;
+      if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 1, c->stream)) != hipSuccess) break;
+      if (strain0) {
+        if ((e = warm_start(c, L, strain0)) != hipSuccess) break;
+        if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream)) != hipSuccess)
+          break;
+      }
+      const int ub = update_blocks(c->S);
+      std::vector<ItemScal> ho(L);
+      for (;;) {
+        if ((e = hipMemcpyAsync(ho.data(), outer, sizeof(ItemScal) * L, hipMemcpyDeviceToHost,
+                                c->stream)) != hipSuccess)
+          break;
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) break;
+        bool any = false;
+        for (auto& s : ho) any = any || s.active;
+        if (!any) break;
+        if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, outer, w32.sc,
+                                    c->opt.inner_tol, c->opt.max_iter, w32.part, P, ub, L,
+                                    c->stream)) != hipSuccess)
+          break;
+        if ((e = launch_cg_init(w32.sc, w32.part, P, ub, L, c->stream)) != hipSuccess) break;
+        if ((e = cg_run<float>(c, L, c->opt.max_iter, hs)) != hipSuccess) break;
+        for (int i = 0; i < L; ++i) {
+          if (!ho[i].active) continue;
+          inner_sum[i] += hs[i].iters;
+          if (hs[i].status == -5) st = HOM_EBREAKDOWN;
+        }
+        if ((e = launch_inner_accumulate(w.x, w32.x, c->S, c->S, outer, ub, L, c->stream)) !=
+            hipSuccess)
+          break;
+        if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, outer,
+                                    w.part)) != hipSuccess)
+          break;
+        if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream)) != hipSuccess)
+          break;
+      }
+      if (e != hipSuccess) break;
+      for (int i = 0; i < L; ++i) it_inner = std::max(it_inner, inner_sum[i]);
+      for (auto& s : ho) {
+        it_outer = std::max(it_outer, s.iters);
+        if (s.status == -5) st = HOM_EBREAKDOWN;
+        else if (!s.conv && st == HOM_OK) st = HOM_ENOTCONV;
+      }
+    }
+    // true residual with the FP64 operator
+    if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.q, nullptr, w.b, nullptr,
+                                w.part2)) != hipSuccess)
+      break;
+    std::vector<double> rr;
+    if ((e = sum_partials_host(c, w.part2, L, tiles64, rr)) != hipSuccess) break;
+    for (int i = 0; i < L; ++i) {
+      const double v = (bb[i] > 0) ? std::sqrt(rr[i] / bb[i]) : std::sqrt(rr[i]);
+      relres = std::max(relres, v);
+    }
+    if ((e = homogenize(c, L, dE, strain, W, J)) != hipSuccess) break;
+    e = hipStreamSynchronize(c->stream);
+  } while (false);
+  (void)hipFree(dE);
+  if (e != hipSuccess) return dev_status(e);
+  if (info) {
+    info->iters_inner = it_inner;
+    info->iters_outer = it_outer;
+    info->rel_resid_true = relres;
+    info->rho_A = c->rhoA;
+    info->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double* out) {
+  if (!hc || L < 1 || !u || !out || (prec != HOM_FP64 && prec != HOM_MIXED)) return HOM_EINVAL;
+  CellImpl* c = &hc->impl;
+  if (c->d != c->dd) return HOM_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = ensure_work(c, L, prec == HOM_MIXED);
+  if (e != hipSuccess) return dev_status(e);
+  wait_user_stream(c);
+  Work<double>& w = c->w64;
+  double* dE = nullptr;
+  std::vector<double> zero((size_t)L * c->d, 0.0);
+  do {
+    if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
+    if ((e = pipe_project_real(c, L, u, w.x)) != hipSuccess) break;
+    if (prec == HOM_FP64) {
+      if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_STORE, w.q, nullptr, nullptr, nullptr,
+                                  nullptr)) != hipSuccess)
+        break;
+    } else {
+      Work<float>& w32 = c->w32;
+      const long n = 2 * c->S * L;
+      if ((e = launch_convert((const double*)w.x, (float*)w32.x, n, c->stream)) != hipSuccess) break;
+      if ((e = pipe_apply<float>(c, w32, L, w32.x, 0, EPI_STORE, w32.q, nullptr, nullptr, nullptr,
+                                 nullptr)) != hipSuccess)
+        break;
+      if ((e = launch_widen((const float*)w32.q, (double*)w.q, n, c->stream)) != hipSuccess) break;
+    }
+    if ((e = pipe_synth(c, L, w.q, dE, false, out)) != hipSuccess) break;
+    e = hipStreamSynchronize(c->stream);
+  } while (false);
+  if (dE) (void)hipFree(dE);
+  return dev_status(e);
+}
+
+hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
+  if (!hc || L < 1 || !u || !out) return HOM_EINVAL;
+  CellImpl* c = &hc->impl;
+  if (c->d != c->dd) return HOM_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = ensure_work(c, L, false);
+  if (e != hipSuccess) return dev_status(e);
+  wait_user_stream(c);
+  double* dE = nullptr;
+  std::vector<double> zero((size_t)L * c->d, 0.0);
+  do {
+    if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
+    if ((e = pipe_project_real(c, L, u, c->w64.x)) != hipSuccess) break;
+    if ((e = pipe_synth(c, L, c->w64.x, dE, false, out)) != hipSuccess) break;
+    e = hipStreamSynchronize(c->stream);
+  } while (false);
+  if (dE) (void)hipFree(dE);
+  return dev_status(e);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// per-kernel timing of one CG iteration
+// ---------------------------------------------------------------------------
+namespace hom {
+
+template <class T>
+static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double* bytes) {
+  Work<T>& w = work_of<T>(c);
+  hipError_t e;
+  std::vector<double> hE((size_t)L * c->dd, 0.0);
+  for (int l = 0; l < L; ++l) hE[(size_t)l * c->dd + (l % c->dd)] = 1.0;
+  double* dE = nullptr;
+  if ((e = hipMalloc(&dE, sizeof(double) * hE.size())) != hipSuccess) return e;
+  if ((e = hipMemcpy(dE, hE.data(), sizeof(double) * hE.size(), hipMemcpyHostToDevice)) !=
+      hipSuccess) {
+    (void)hipFree(dE);
+    return e;
+  }
+  const int P = partial_slots(c);
+  const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
+  const int tiles = project_tiles<T>(c);
+  const int ub = update_blocks(c->S);
+  auto reset = [&]() -> hipError_t {
+    hipError_t e2 = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
+    if (e2 == hipSuccess) e2 = pipe_rhs<T>(c, w, L, dE, nullptr);
+    if (e2 == hipSuccess) e2 = launch_cg_init(w.sc, w.part, P, tiles, L, c->stream);
+    return e2;
+  };
+  hipEvent_t ev0, ev1;
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  auto timed = [&](int slot, auto&& fn) -> hipError_t {
+    hipError_t e2 = reset();
+    if (e2 == hipSuccess) e2 = fn();  // warm-up
+    if (e2 != hipSuccess) return e2;
+    (void)hipEventRecord(ev0, c->stream);
+    for (int i = 0; i < reps && e2 == hipSuccess; ++i) e2 = fn();
+    (void)hipEventRecord(ev1, c->stream);
+    if (e2 == hipSuccess) e2 = hipEventSynchronize(ev1);
+    float t = 0.f;
+    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&t, ev0, ev1);
+    ms[slot] = (double)t / reps;
+    return e2;
+  };
+  for (int i = 0; i < 8; ++i) ms[i] = bytes[i] = 0.0;
+  const double esz = sizeof(cpx<T>), Ts = sizeof(T);
+  const long inner = inner0(c);
+  const long rows = (c->dd == 3) ? (long)Q0 * Q1 : Q0;
+  const double S = (double)c->S;
+  cpx<T>* Xrow = (c->dd == 3) ? w.X2 : w.X1;
+  do {
+    e = timed(0, [&]() { return stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc); });
+    if (e != hipSuccess) break;
+    bytes[0] = L * (3.0 * S * esz + (double)c->dd * Q0 * inner * esz);
+    if (c->dd == 3) {
+      e = timed(1, [&]() { return stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc); });
+      if (e != hipSuccess) break;
+      bytes[1] = L * (double)c->dd * Q0 * c->H * esz * (c->N[1] + Q1);
+      e = timed(3, [&]() { return stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc); });
+      if (e != hipSuccess) break;
+      bytes[3] = bytes[1];
+    }
+    e = timed(2, [&]() {
+      return stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, c->dd == 3 ? Q1 : 1,
+                          c->dd == 3 ? Q2 : Q1, nullptr, nullptr, nullptr, w.sc);
+    });
+    if (e != hipSuccess) break;
+    bytes[2] = L * 2.0 * c->dd * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
+    e = timed(4, [&]() {
+      return stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr, nullptr, nullptr,
+                              nullptr, w.part, w.sc, nullptr);
+    });
+    if (e != hipSuccess) break;
+    bytes[4] = L * ((double)c->dd * Q0 * inner * esz + 2.0 * S * esz);
+    e = timed(5, [&]() {
+      CgUpdateArgs<T> u{};
+      u.x = w.x;
+      u.r = w.r;
+      u.p = w.p;
+      u.q = w.q;
+      u.stride = c->S;
+      u.count = c->S;
+      u.H = c->H;
+      u.partials = w.part2;
+      u.P = P;
+      u.sc = w.sc;
+      return launch_cg_update<T>(u, L, ub, c->stream);
+    });
+    if (e != hipSuccess) break;
+    bytes[5] = L * 6.0 * S * esz;
+    e = timed(6, [&]() {
+      hipError_t e2 = launch_cg_alpha(w.sc, w.part, P, tiles, L, c->stream);
+      if (e2 == hipSuccess) e2 = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
+      if (e2 == hipSuccess) e2 = launch_cg_beta(w.sc, w.part2, P, ub, L, c->stream);
+      return e2;
+    });
+    if (e != hipSuccess) break;
+    e = timed(7, [&]() { return cg_body<T>(c, w, L, 1); });
+    if (e != hipSuccess) break;
+    for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
+  } while (false);
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(dE);
+  return e;
+}
+
+}  // namespace hom
+
+extern "C" hom_status hom_profile_iteration(hom_cell* hc, hom_prec prec, int L, int reps,
+                                            double* ms, double* bytes) {
+  if (!hc || L < 1 || reps < 1 || !ms || !bytes) return HOM_EINVAL;
+  if (prec != HOM_FP64 && prec != HOM_MIXED) return HOM_EINVAL;
+  CellImpl* c = &hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = ensure_work(c, L, prec == HOM_MIXED);
+  if (e != hipSuccess) return dev_status(e);
+  if (prec == HOM_FP64) e = profile_impl<double>(c, L, reps, ms, bytes);
+  else e = profile_impl<float>(c, L, reps, ms, bytes);
+  return dev_status(e);
+}
