@@ -130,6 +130,11 @@ hom_status hom_project(hom_cell* c, int L, const double* u, double* out);
 hom_status hom_profile_iteration(hom_cell* c, hom_prec prec, int L, int reps, double* ms,
                                  double* bytes);
 
+/* Enable (default, 1) or disable (0) the compile-time specialised kernels of
+ * the sizes they exist for; disabled, every size runs the generic kernels.
+ * Process-wide; for A/B timing and testing. */
+hom_status hom_set_specialized(int enable);
+
 void hom_destroy_cell(hom_cell* c);
 const char* hom_status_str(hom_status s);
 /* Grid sizes of a cell: N[3], Q[3] (unused axes 1), d. */

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhom.so")
-SOURCES = ["kernels.hip", "solver.hip", "plan.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "kernels_static_f32.hip", "kernels_static_f64.hip", "solver.hip",
+           "plan.cpp", "server.cpp"]
 ARCH = os.environ.get("HOM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay disabled (see the project's design notes)

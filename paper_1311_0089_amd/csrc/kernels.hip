@@ -4,375 +4,39 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 
+#include "kernel_bodies.hpp"
 #include "kernels.hpp"
 
 namespace hom {
 
-__device__ __forceinline__ int kof(int i, int n) { return (i <= (n - 1) / 2) ? i : i - n; }
-__device__ __forceinline__ int posk(int k, int n) { return k < 0 ? k + n : k; }
 
-// unit normal n(k) = xi / |xi| (0 at k = 0); column index -> (k1, h) in 3-D, h in 2-D
-template <class T>
-__device__ __forceinline__ void unit_normal(const NormalGeo& g, int k0, int col, T* nv) {
-  T xi0 = T(k0) * T(g.invY[0]), xi1, xi2 = T(0);
-  if (g.d == 3) {
-    const int k1 = kof(col / g.H, g.N1);
-    const int h = col % g.H;
-    xi1 = T(k1) * T(g.invY[1]);
-    xi2 = T(h) * T(g.invY[2]);
-  } else {
-    xi1 = T(col) * T(g.invY[1]);
-  }
-  const T s = xi0 * xi0 + xi1 * xi1 + xi2 * xi2;
-  const T inv = s > T(0) ? T(1) / sqrt(s) : T(0);
-  nv[0] = xi0 * inv;
-  nv[1] = xi1 * inv;
-  nv[2] = xi2 * inv;
-}
-
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double red[kThreads / 64];
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  if (wid == 0) {
-    v = (lane < (int)(blockDim.x >> 6)) ? red[lane] : 0.0;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  }
-  __syncthreads();
+// ---------------------------------------------------------------------------
+// registry of compile-time specialised kernels
+// ---------------------------------------------------------------------------
+std::vector<StaticKernel>& static_registry() {
+  static std::vector<StaticKernel> v;
   return v;
 }
-
-// fixed-order sum of nparts partials, result valid in thread 0
-__device__ __forceinline__ double sum_partials(const double* p, int nparts) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += p[i];
-  return block_sum(v);
-}
-
-// ---------------------------------------------------------------------------
-// axis 0 from the scalar potential (optionally fusing p <- r + beta p)
-// ---------------------------------------------------------------------------
-template <class T, int PMAX>
-__global__ __launch_bounds__(kThreads) void k_col_expand(ColExpandArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
-  const int col0 = blockIdx.x * a.W;
-  const int ncols = min(a.W, a.inner - col0);
-  const long ibase = (long)item * a.c_stride;
-  const T beta = a.fuse ? T(a.sc[item].beta) : T(0);
-  const int npos = a.n_in * a.W;
-  cpx<T> s[PMAX];
-  int row[PMAX];
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    const int f = threadIdx.x + it * blockDim.x;
-    s[it] = cpx<T>{T(0), T(0)};
-    row[it] = -1;
-    if (f < npos) {
-      const int i = f / a.W, w = f % a.W;
-      const int k0 = kof(i, a.n_in);
-      row[it] = (a.n_fft == a.n_in) ? i : posk(k0, a.n_fft);
-      if (w < ncols) {
-        const long idx = ibase + (long)i * a.inner + col0 + w;
-        if (a.fuse) {
-          cpx<T> rv = a.r[idx], pv = a.p[idx];
-          pv = cpx<T>{rv.x + beta * pv.x, rv.y + beta * pv.y};
-          a.p[idx] = pv;
-          s[it] = pv;
-        } else {
-          s[it] = a.c[idx];
-        }
-      }
-    }
+void register_static(const StaticKernel& k) { static_registry().push_back(k); }
+static bool g_static_on = true;
+static size_t g_static_max_lds = 0;
+void set_static_enabled(bool on) { g_static_on = on; }
+bool static_enabled() { return g_static_on; }
+const StaticKernel* find_static(int kind, int esz, int n, int ntrial, int d, const FftPlan& p) {
+  if (!g_static_on) return nullptr;
+  for (const StaticKernel& k : static_registry()) {
+    if (k.kind != kind || k.esz != esz || k.n != n || k.ntrial != ntrial || k.d != d) continue;
+    if (k.lds > g_static_max_lds) continue;
+    // the compile-time plan must describe the same tables the host uploaded
+    if (k.len != p.len || k.blue != p.blue || k.nst != p.nst) continue;
+    bool same = true;
+    for (int i = 0; i < p.nst; ++i) same = same && (k.rad[i] == p.rad[i]);
+    if (!same) continue;
+    return &k;
   }
-  const LdsLines L{a.W, 1, a.W, true};
-  for (int al = 0; al < a.g.d; ++al) {
-    if (a.n_fft != a.n_in) {
-      for (int f = threadIdx.x; f < a.n_fft * a.W; f += blockDim.x) lds[f] = cpx<T>{T(0), T(0)};
-      __syncthreads();
-    }
-#pragma unroll
-    for (int it = 0; it < PMAX; ++it) {
-      if (row[it] >= 0) {
-        const int f = threadIdx.x + it * blockDim.x;
-        const int w = f % a.W;
-        T nv[3];
-        unit_normal<T>(a.g, kof(f / a.W, a.n_in), min(col0 + w, a.inner - 1), nv);
-        lds[row[it] * a.W + w] = cscale(s[it], nv[al]);
-      }
-    }
-    __syncthreads();
-    line_fft<T, +1>(lds, a.plan, L, a.tw);
-    cpx<T>* X = a.X + (long)item * a.X_stride + (long)al * a.X_cstride;
-    for (int f = threadIdx.x; f < a.n_fft * a.W; f += blockDim.x) {
-      const int i = f / a.W, w = f % a.W;
-      if (w < ncols) X[(long)i * a.inner + col0 + w] = lds[i * a.W + w];
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// plain pass along a middle axis; zero-pad (inverse) or truncate (forward)
-// ---------------------------------------------------------------------------
-template <class T, int S>
-__global__ __launch_bounds__(kThreads) void k_col_plain(ColPlainArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int item = blockIdx.z / a.d, comp = blockIdx.z % a.d;
-  if (a.sc && !a.sc[item].active) return;
-  const int o = blockIdx.y;
-  const int col0 = blockIdx.x * a.W;
-  const int ncols = min(a.W, a.inner - col0);
-  const cpx<T>* in = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride +
-                     (long)o * a.n_in * a.inner + col0;
-  cpx<T>* out = a.out + (long)item * a.out_stride + (long)comp * a.out_cstride +
-                (long)o * a.n_out * a.inner + col0;
-  if (a.n_in != a.n_fft) {
-    for (int f = threadIdx.x; f < a.n_fft * a.W; f += blockDim.x) lds[f] = cpx<T>{T(0), T(0)};
-    __syncthreads();
-  }
-  for (int f = threadIdx.x; f < a.n_in * a.W; f += blockDim.x) {
-    const int i = f / a.W, w = f % a.W;
-    const int rrow = (a.n_in == a.n_fft) ? i : posk(kof(i, a.n_in), a.n_fft);
-    lds[rrow * a.W + w] = (w < ncols) ? in[(long)i * a.inner + w] : cpx<T>{T(0), T(0)};
-  }
-  __syncthreads();
-  const LdsLines L{a.W, 1, a.W, true};
-  line_fft<T, S>(lds, a.plan, L, a.tw);
-  for (int f = threadIdx.x; f < a.n_out * a.W; f += blockDim.x) {
-    const int i = f / a.W, w = f % a.W;
-    const int rrow = (a.n_out == a.n_fft) ? i : posk(kof(i, a.n_out), a.n_fft);
-    if (w < ncols) out[(long)i * a.inner + w] = cscale(lds[rrow * a.W + w], a.scale);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// axis 0 forward + truncation + projection, with CG epilogues
-// ---------------------------------------------------------------------------
-template <class T, int PMAX>
-__global__ __launch_bounds__(kThreads) void k_col_project(ColProjectArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
-  const int col0 = blockIdx.x * a.W;
-  const int ncols = min(a.W, a.inner - col0);
-  const int npos = a.n_out * a.W;
-  cpx<T> acc[PMAX];
-  int row[PMAX];
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    acc[it] = cpx<T>{T(0), T(0)};
-    const int f = threadIdx.x + it * blockDim.x;
-    row[it] = -1;
-    if (f < npos) {
-      const int i = f / a.W;
-      row[it] = (a.n_out == a.n_fft) ? i : posk(kof(i, a.n_out), a.n_fft);
-    }
-  }
-  const LdsLines L{a.W, 1, a.W, true};
-  for (int al = 0; al < a.d; ++al) {
-    const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al * a.X_cstride + col0;
-    for (int f = threadIdx.x; f < a.n_fft * a.W; f += blockDim.x) {
-      const int i = f / a.W, w = f % a.W;
-      lds[f] = (w < ncols) ? X[(long)i * a.inner + w] : cpx<T>{T(0), T(0)};
-    }
-    __syncthreads();
-    line_fft<T, -1>(lds, a.plan, L, a.tw);
-#pragma unroll
-    for (int it = 0; it < PMAX; ++it) {
-      if (row[it] >= 0) {
-        const int f = threadIdx.x + it * blockDim.x;
-        const int i = f / a.W, w = f % a.W;
-        T nv[3];
-        unit_normal<T>(a.g, kof(i, a.n_out), min(col0 + w, a.inner - 1), nv);
-        const cpx<T> v = lds[row[it] * a.W + w];
-        acc[it].x += nv[al] * v.x;
-        acc[it].y += nv[al] * v.y;
-      }
-    }
-    __syncthreads();
-  }
-  // epilogue
-  double part = 0.0;
-  const long sb = (long)item * a.s_stride;
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    const int f = threadIdx.x + it * blockDim.x;
-    if (row[it] >= 0 && (f % a.W) < ncols) {
-      const int i = f / a.W, w = f % a.W;
-      const int col = col0 + w;
-      const long idx = sb + (long)i * a.inner + col;
-      const double wt = ((col % a.g.H) == 0) ? 1.0 : 2.0;
-      cpx<T> qv = cscale(acc[it], a.scale);
-      if (a.epi == EPI_STORE) {
-        a.q[idx] = qv;
-        if (a.p) {
-          const cpx<T> pv = a.p[idx];
-          part += wt * ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
-        }
-      } else if (a.epi == EPI_RHS) {
-        qv = cpx<T>{-qv.x, -qv.y};
-        a.q[idx] = qv;
-        if (a.r) a.r[idx] = qv;
-        if (a.pp) a.pp[idx] = qv;
-        if (a.x) a.x[idx] = cpx<T>{T(0), T(0)};
-        part += wt * ((double)qv.x * (double)qv.x + (double)qv.y * (double)qv.y);
-      } else {  // EPI_RESID: r = b - q
-        const cpx<T> bv = a.b[idx];
-        const cpx<T> rv = cpx<T>{bv.x - qv.x, bv.y - qv.y};
-        a.r[idx] = rv;
-        part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
-      }
-    }
-  }
-  if (a.partials) {
-    part = block_sum(part);
-    if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// last (contiguous) axis: pairs of rows packed as one complex line
-// ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void flux_point(int kind, int d, const T* A, long Acs, long off,
-                                           const T* e, T* j) {
-  if (kind == 0) {
-    const T a = A[off];
-    for (int q = 0; q < d; ++q) j[q] = a * e[q];
-  } else if (kind == 1) {
-    for (int q = 0; q < d; ++q) j[q] = A[q * Acs + off] * e[q];
-  } else {
-    if (d == 1) {
-      j[0] = A[off] * e[0];
-    } else if (d == 2) {
-      const T a00 = A[off], a11 = A[Acs + off], a01 = A[2 * Acs + off];
-      j[0] = a00 * e[0] + a01 * e[1];
-      j[1] = a01 * e[0] + a11 * e[1];
-    } else {
-      const T a00 = A[off], a11 = A[Acs + off], a22 = A[2 * Acs + off];
-      const T a12 = A[3 * Acs + off], a02 = A[4 * Acs + off], a01 = A[5 * Acs + off];
-      j[0] = a00 * e[0] + a01 * e[1] + a02 * e[2];
-      j[1] = a01 * e[0] + a11 * e[1] + a12 * e[2];
-      j[2] = a02 * e[0] + a12 * e[1] + a22 * e[2];
-    }
-  }
-}
-
-template <class T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_row(RowArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
-  const int n = a.n, H = a.H, RP = a.RP, d = a.d;
-  const int ls = a.plan.len;
-  const int pair0 = blockIdx.x * RP;
-  const LdsLines L{d * RP, ls, 1, false};
-
-  if (MODE == ROW_APPLY || MODE == ROW_SYNTH) {
-    // Z(h) = X_a(h) + i X_b(h), Z(n-h) = conj X_a(h) + i conj X_b(h)
-    if (n > 2 * H - 1) {
-      const int gap = n - (2 * H - 1);
-      for (int f = threadIdx.x; f < d * RP * gap; f += blockDim.x) {
-        const int line = f / gap, x = H + f % gap;
-        lds[line * ls + x] = cpx<T>{T(0), T(0)};
-      }
-    }
-    for (int f = threadIdx.x; f < d * RP * H; f += blockDim.x) {
-      const int line = f / H, h = f % H;
-      const int comp = line / RP, lp = line % RP;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      cpx<T> xa = {T(0), T(0)}, xb = {T(0), T(0)};
-      if (r0 < a.rows) {
-        const cpx<T>* src = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride;
-        xa = src[(long)r0 * H + h];
-        if (r1 < a.rows) xb = src[(long)r1 * H + h];
-      }
-      lds[line * ls + h] = cpx<T>{xa.x - xb.y, xa.y + xb.x};
-      if (h > 0) lds[line * ls + n - h] = cpx<T>{xa.x + xb.y, xb.x - xa.y};
-    }
-    __syncthreads();
-    line_fft<T, +1>(lds, a.plan, L, a.tw);
-  } else if (MODE == ROW_FWD) {
-    for (int f = threadIdx.x; f < d * RP * n; f += blockDim.x) {
-      const int line = f / n, x = f % n;
-      const int comp = line / RP, lp = line % RP;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      T ua = T(0), ub = T(0);
-      if (r0 < a.rows) {
-        const double* src = a.ureal + (long)item * a.real_stride + (long)comp * a.real_cstride;
-        ua = T(src[(long)r0 * n + x]);
-        if (r1 < a.rows) ub = T(src[(long)r1 * n + x]);
-      }
-      lds[line * ls + x] = cpx<T>{ua, ub};
-    }
-    __syncthreads();
-  }
-
-  if (MODE == ROW_SYNTH) {
-    const double* E = a.E + (long)item * d;
-    for (int f = threadIdx.x; f < d * RP * n; f += blockDim.x) {
-      const int line = f / n, x = f % n;
-      const int comp = line / RP, lp = line % RP;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      if (r0 >= a.rows) continue;
-      double* dst = a.oreal + (long)item * a.real_stride + (long)comp * a.real_cstride;
-      const cpx<T> z = lds[line * ls + x];
-      dst[(long)r0 * n + x] = (double)z.x + E[comp];
-      if (r1 < a.rows) dst[(long)r1 * n + x] = (double)z.y + E[comp];
-    }
-    return;
-  }
-
-  if (MODE == ROW_APPLY || MODE == ROW_CONST) {
-    const T* A = a.A + (long)item * a.A_stride;
-    for (int f = threadIdx.x; f < RP * n; f += blockDim.x) {
-      const int lp = f / n, x = f % n;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      if (r0 >= a.rows) continue;
-      T e0[3], e1[3], j0[3], j1[3];
-      if (MODE == ROW_CONST) {
-        const double* E = a.E + (long)item * d;
-        for (int q = 0; q < d; ++q) e0[q] = e1[q] = T(E[q]);
-      } else {
-        for (int q = 0; q < d; ++q) {
-          const cpx<T> z = lds[(q * RP + lp) * ls + x];
-          e0[q] = z.x;
-          e1[q] = z.y;
-        }
-      }
-      flux_point<T>(a.kind, d, A, a.A_cstride, (long)r0 * n + x, e0, j0);
-      flux_point<T>(a.kind, d, A, a.A_cstride, (long)((r1 < a.rows) ? r1 : r0) * n + x, e1, j1);
-      for (int q = 0; q < d; ++q) lds[(q * RP + lp) * ls + x] = cpx<T>{j0[q], j1[q]};
-    }
-    __syncthreads();
-  }
-
-  // forward transform and split of the two packed real lines
-  line_fft<T, -1>(lds, a.plan, L, a.tw);
-  const T half = T(0.5) / T(n);
-  for (int f = threadIdx.x; f < d * RP * H; f += blockDim.x) {
-    const int line = f / H, h = f % H;
-    const int comp = line / RP, lp = line % RP;
-    const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-    if (r0 >= a.rows) continue;
-    const cpx<T> zh = lds[line * ls + h];
-    const cpx<T> zm = lds[line * ls + (h == 0 ? 0 : n - h)];
-    // A = (Z(h) + conj Z(n-h)) / 2,  B = (Z(h) - conj Z(n-h)) / (2 i)
-    const cpx<T> va = {(zh.x + zm.x) * half, (zh.y - zm.y) * half};
-    const cpx<T> vb = {(zh.y + zm.y) * half, (zm.x - zh.x) * half};
-    cpx<T>* dst = a.out + (long)item * a.out_stride + (long)comp * a.out_cstride;
-    dst[(long)r0 * H + h] = va;
-    if (r1 < a.rows) dst[(long)r1 * H + h] = vb;
-  }
+  return nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -398,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
     const double wt = ((e % a.H) == 0) ? 1.0 : 2.0;
     part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
   }
-  part = block_sum(part);
+  part = block_sum<kThreads>(part);
   if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
 }
 
@@ -512,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
     const double wt = ((e % H) == 0) ? 1.0 : 2.0;
     part += wt * ((double)w.x * (double)w.x + (double)w.y * (double)w.y);
   }
-  part = block_sum(part);
+  part = block_sum<kThreads>(part);
   if (threadIdx.x == 0) partials[(long)item * P + blockIdx.x] = part;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     inner[item].tol = eta;
@@ -578,11 +242,11 @@ __global__ __launch_bounds__(kThreads) void k_quad(const double* e, long es, lon
       }
   }
   for (int t = 0; t < 9; ++t) {
-    const double v = block_sum(accW[t]);
+    const double v = block_sum<kThreads>(accW[t]);
     if (threadIdx.x == 0) partials[(long)blockIdx.x * 18 + t] = v;
   }
   for (int t = 0; t < 9; ++t) {
-    const double v = block_sum(accJ[t]);
+    const double v = block_sum<kThreads>(accJ[t]);
     if (threadIdx.x == 0) partials[(long)blockIdx.x * 18 + 9 + t] = v;
   }
 }
@@ -593,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_quad_final(const double* partials,
   for (int t = 0; t < 18; ++t) {
     double v = 0.0;
     for (int b = threadIdx.x; b < blocks; b += blockDim.x) v += partials[(long)b * 18 + t];
-    v = block_sum(v);
+    v = block_sum<kThreads>(v);
     if (threadIdx.x == 0) out[t] = v / (double)npts;
   }
 }
@@ -614,15 +278,21 @@ __global__ void k_widen(const float* in, double* out, long n) {
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 template <class T>
-hipError_t launch_col_expand(const ColExpandArgs<T>& a, int items, size_t lds, hipStream_t s) {
+hipError_t launch_col_expand(const ColExpandArgs<T>& a, int items, size_t lds, hipStream_t s,
+                             const StaticKernel* sk) {
   dim3 grid(ceil_div(a.inner, a.W), items);
+  if (sk) {
+    auto fn = reinterpret_cast<void (*)(ColExpandArgs<T>)>(const_cast<void*>(sk->fn));
+    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    return hipGetLastError();
+  }
   const long npos = (long)a.n_in * a.W;
   if (npos <= 8L * kThreads)
-    hipLaunchKernelGGL((k_col_expand<T, 8>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_expand<T, ColGen, 8>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 16L * kThreads)
-    hipLaunchKernelGGL((k_col_expand<T, 16>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_expand<T, ColGen, 16>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 32L * kThreads)
-    hipLaunchKernelGGL((k_col_expand<T, 32>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_expand<T, ColGen, 32>), grid, dim3(kThreads), lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -630,39 +300,57 @@ hipError_t launch_col_expand(const ColExpandArgs<T>& a, int items, size_t lds, h
 
 template <class T>
 hipError_t launch_col_plain(const ColPlainArgs<T>& a, int items, int sign, size_t lds,
-                            hipStream_t s) {
+                            hipStream_t s, const StaticKernel* sk) {
   dim3 grid(ceil_div(a.inner, a.W), a.outer, items * a.d);
+  if (sk) {
+    auto fn = reinterpret_cast<void (*)(ColPlainArgs<T>)>(const_cast<void*>(sk->fn));
+    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    return hipGetLastError();
+  }
   if (sign < 0)
-    hipLaunchKernelGGL((k_col_plain<T, -1>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_plain<T, ColGen, -1>), grid, dim3(kThreads), lds, s, a);
   else
-    hipLaunchKernelGGL((k_col_plain<T, +1>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_plain<T, ColGen, +1>), grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_col_project(const ColProjectArgs<T>& a, int items, size_t lds, hipStream_t s) {
+hipError_t launch_col_project(const ColProjectArgs<T>& a, int items, size_t lds, hipStream_t s,
+                              const StaticKernel* sk) {
   dim3 grid(ceil_div(a.inner, a.W), items);
+  if (sk) {
+    auto fn = reinterpret_cast<void (*)(ColProjectArgs<T>)>(const_cast<void*>(sk->fn));
+    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    return hipGetLastError();
+  }
   const long npos = (long)a.n_out * a.W;
   if (npos <= 8L * kThreads)
-    hipLaunchKernelGGL((k_col_project<T, 8>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_project<T, ColGen, 8>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 16L * kThreads)
-    hipLaunchKernelGGL((k_col_project<T, 16>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_project<T, ColGen, 16>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 32L * kThreads)
-    hipLaunchKernelGGL((k_col_project<T, 32>), grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_col_project<T, ColGen, 32>), grid, dim3(kThreads), lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipStream_t s) {
+hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipStream_t s,
+                      const StaticKernel* sk) {
   const long pairs = (a.rows + 1) / 2;
   dim3 grid(ceil_div(pairs, a.RP), items);
+  if (sk) {
+    if (mode != ROW_APPLY) return hipErrorInvalidValue;
+    auto fn = reinterpret_cast<void (*)(RowArgs<T>)>(const_cast<void*>(sk->fn));
+    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    return hipGetLastError();
+  }
   switch (mode) {
-    case ROW_APPLY: hipLaunchKernelGGL((k_row<T, ROW_APPLY>), grid, dim3(kThreads), lds, s, a); break;
-    case ROW_CONST: hipLaunchKernelGGL((k_row<T, ROW_CONST>), grid, dim3(kThreads), lds, s, a); break;
-    case ROW_SYNTH: hipLaunchKernelGGL((k_row<T, ROW_SYNTH>), grid, dim3(kThreads), lds, s, a); break;
-    case ROW_FWD: hipLaunchKernelGGL((k_row<T, ROW_FWD>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_APPLY: hipLaunchKernelGGL((k_row<T, RowGen, ROW_APPLY>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_CONST: hipLaunchKernelGGL((k_row<T, RowGen, ROW_CONST>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_SYNTH: hipLaunchKernelGGL((k_row<T, RowGen, ROW_SYNTH>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_FWD: hipLaunchKernelGGL((k_row<T, RowGen, ROW_FWD>), grid, dim3(kThreads), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -759,42 +447,49 @@ hipError_t configure_kernels(size_t max_lds) {
     hipError_t e2 = set_lds((k), max_lds);    \
     if (e2 != hipSuccess) e = e2;             \
   } while (0)
-  HOM_SET((k_col_expand<float, 8>));
-  HOM_SET((k_col_expand<float, 16>));
-  HOM_SET((k_col_expand<float, 32>));
-  HOM_SET((k_col_expand<double, 8>));
-  HOM_SET((k_col_expand<double, 16>));
-  HOM_SET((k_col_expand<double, 32>));
-  HOM_SET((k_col_project<float, 8>));
-  HOM_SET((k_col_project<float, 16>));
-  HOM_SET((k_col_project<float, 32>));
-  HOM_SET((k_col_project<double, 8>));
-  HOM_SET((k_col_project<double, 16>));
-  HOM_SET((k_col_project<double, 32>));
-  HOM_SET((k_col_plain<float, -1>));
-  HOM_SET((k_col_plain<float, 1>));
-  HOM_SET((k_col_plain<double, -1>));
-  HOM_SET((k_col_plain<double, 1>));
-  HOM_SET((k_row<float, ROW_APPLY>));
-  HOM_SET((k_row<float, ROW_CONST>));
-  HOM_SET((k_row<float, ROW_SYNTH>));
-  HOM_SET((k_row<float, ROW_FWD>));
-  HOM_SET((k_row<double, ROW_APPLY>));
-  HOM_SET((k_row<double, ROW_CONST>));
-  HOM_SET((k_row<double, ROW_SYNTH>));
-  HOM_SET((k_row<double, ROW_FWD>));
+  HOM_SET((k_col_expand<float, ColGen, 8>));
+  HOM_SET((k_col_expand<float, ColGen, 16>));
+  HOM_SET((k_col_expand<float, ColGen, 32>));
+  HOM_SET((k_col_expand<double, ColGen, 8>));
+  HOM_SET((k_col_expand<double, ColGen, 16>));
+  HOM_SET((k_col_expand<double, ColGen, 32>));
+  HOM_SET((k_col_project<float, ColGen, 8>));
+  HOM_SET((k_col_project<float, ColGen, 16>));
+  HOM_SET((k_col_project<float, ColGen, 32>));
+  HOM_SET((k_col_project<double, ColGen, 8>));
+  HOM_SET((k_col_project<double, ColGen, 16>));
+  HOM_SET((k_col_project<double, ColGen, 32>));
+  HOM_SET((k_col_plain<float, ColGen, -1>));
+  HOM_SET((k_col_plain<float, ColGen, 1>));
+  HOM_SET((k_col_plain<double, ColGen, -1>));
+  HOM_SET((k_col_plain<double, ColGen, 1>));
+  HOM_SET((k_row<float, RowGen, ROW_APPLY>));
+  HOM_SET((k_row<float, RowGen, ROW_CONST>));
+  HOM_SET((k_row<float, RowGen, ROW_SYNTH>));
+  HOM_SET((k_row<float, RowGen, ROW_FWD>));
+  HOM_SET((k_row<double, RowGen, ROW_APPLY>));
+  HOM_SET((k_row<double, RowGen, ROW_CONST>));
+  HOM_SET((k_row<double, RowGen, ROW_SYNTH>));
+  HOM_SET((k_row<double, RowGen, ROW_FWD>));
 #undef HOM_SET
+  for (const StaticKernel& k : static_registry()) {
+    if (k.lds > max_lds) continue;  // never selected on this device (see find_static)
+    hipError_t e2 = hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)max_lds);
+    if (e2 != hipSuccess) e = e2;
+  }
+  g_static_max_lds = max_lds;
   return e;
 }
 
-template hipError_t launch_col_expand<float>(const ColExpandArgs<float>&, int, size_t, hipStream_t);
-template hipError_t launch_col_expand<double>(const ColExpandArgs<double>&, int, size_t, hipStream_t);
-template hipError_t launch_col_plain<float>(const ColPlainArgs<float>&, int, int, size_t, hipStream_t);
-template hipError_t launch_col_plain<double>(const ColPlainArgs<double>&, int, int, size_t, hipStream_t);
-template hipError_t launch_col_project<float>(const ColProjectArgs<float>&, int, size_t, hipStream_t);
-template hipError_t launch_col_project<double>(const ColProjectArgs<double>&, int, size_t, hipStream_t);
-template hipError_t launch_row<float>(const RowArgs<float>&, int, int, size_t, hipStream_t);
-template hipError_t launch_row<double>(const RowArgs<double>&, int, int, size_t, hipStream_t);
+template hipError_t launch_col_expand<float>(const ColExpandArgs<float>&, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_col_expand<double>(const ColExpandArgs<double>&, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_col_plain<float>(const ColPlainArgs<float>&, int, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_col_plain<double>(const ColPlainArgs<double>&, int, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_col_project<float>(const ColProjectArgs<float>&, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_col_project<double>(const ColProjectArgs<double>&, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_row<float>(const RowArgs<float>&, int, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_row<double>(const RowArgs<double>&, int, int, size_t, hipStream_t, const StaticKernel*);
 template hipError_t launch_cg_update<float>(const CgUpdateArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_cg_update<double>(const CgUpdateArgs<double>&, int, int, hipStream_t);
 

@@ -15,6 +15,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "fft_device.hpp"
 
 namespace hom {
@@ -126,15 +128,38 @@ struct CgUpdateArgs {
   ItemScal* sc;
 };
 
-// launchers (defined in kernels.hip); all return hipError_t of the launch
+// compile-time specialised pass kernels, registered by kernels_static*.hip
+enum { KK_EXPAND = 0, KK_PROJECT = 1, KK_PLAIN_INV = 2, KK_PLAIN_FWD = 3, KK_ROW = 4 };
+struct StaticKernel {
+  int kind, esz, n, ntrial, d;  // d: component count (row kernels), else 0
+  const void* fn;
+  int W;                        // tile width (column kernels) or row pairs (row kernels)
+  int NT;                       // workgroup size
+  size_t lds;                   // dynamic LDS bytes
+  int len, blue, nst, rad[kMaxStages];  // the compile-time FFT plan
+};
+std::vector<StaticKernel>& static_registry();
+void register_static(const StaticKernel& k);
+void set_static_enabled(bool on);
+bool static_enabled();
+// entry for (kind, element size, FFT length, trial length, d) whose plan
+// matches p, or nullptr (then the generic kernel runs)
+const StaticKernel* find_static(int kind, int esz, int n, int ntrial, int d, const FftPlan& p);
+
+// launchers (defined in kernels.hip); sk selects a specialised kernel (its W /
+// row pairs must already be in the arguments); all return the launch status
 template <class T>
-hipError_t launch_col_expand(const ColExpandArgs<T>& a, int items, size_t lds, hipStream_t s);
+hipError_t launch_col_expand(const ColExpandArgs<T>& a, int items, size_t lds, hipStream_t s,
+                             const StaticKernel* sk = nullptr);
 template <class T>
-hipError_t launch_col_plain(const ColPlainArgs<T>& a, int items, int sign, size_t lds, hipStream_t s);
+hipError_t launch_col_plain(const ColPlainArgs<T>& a, int items, int sign, size_t lds,
+                            hipStream_t s, const StaticKernel* sk = nullptr);
 template <class T>
-hipError_t launch_col_project(const ColProjectArgs<T>& a, int items, size_t lds, hipStream_t s);
+hipError_t launch_col_project(const ColProjectArgs<T>& a, int items, size_t lds, hipStream_t s,
+                              const StaticKernel* sk = nullptr);
 template <class T>
-hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipStream_t s);
+hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipStream_t s,
+                      const StaticKernel* sk = nullptr);
 template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s);
 

@@ -1,0 +1,41 @@
+// kernels_static_f64.hip -- FP64 specialised pass kernels (see static_table.hpp)
+#include "static_table.hpp"
+
+namespace hom {
+namespace {
+using T = double;
+RegCol<T, P1023, 1023, 4, 512> c1023;
+RegCol<T, P255, 255, 8, 256> c255;
+RegCol<T, P127, 127, 8, 256> c127;
+RegCol<T, P63, 63, 16, 256> c63;
+RegCol<T, P31, 31, 16, 256> c31;
+RegCol<T, P15, 15, 16, 256> c15;
+RegCol<T, P253, 127, 8, 256> c253;
+RegCol<T, P125, 63, 16, 256> c125;
+RegCol<T, P61, 31, 16, 256> c61;
+RegCol<T, P29, 15, 16, 256> c29;
+RegCol<T, P509, 255, 4, 512> c509;
+RegRow<T, P1023, 1023, 2, 2, 512> r1023_2;
+RegRow<T, P1023, 1023, 3, 1, 256> r1023_3;
+RegRow<T, P255, 255, 2, 4, 256> r255_2;
+RegRow<T, P255, 255, 3, 4, 256> r255_3;
+RegRow<T, P127, 127, 2, 4, 256> r127_2;
+RegRow<T, P127, 127, 3, 4, 256> r127_3;
+RegRow<T, P63, 63, 2, 8, 256> r63_2;
+RegRow<T, P63, 63, 3, 8, 256> r63_3;
+RegRow<T, P31, 31, 2, 8, 256> r31_2;
+RegRow<T, P31, 31, 3, 8, 256> r31_3;
+RegRow<T, P15, 15, 2, 8, 256> r15_2;
+RegRow<T, P15, 15, 3, 8, 256> r15_3;
+RegRow<T, P253, 127, 2, 4, 256> r253_2;
+RegRow<T, P253, 127, 3, 4, 256> r253_3;
+RegRow<T, P125, 63, 2, 8, 256> r125_2;
+RegRow<T, P125, 63, 3, 8, 256> r125_3;
+RegRow<T, P61, 31, 2, 8, 256> r61_2;
+RegRow<T, P61, 31, 3, 8, 256> r61_3;
+RegRow<T, P29, 15, 2, 8, 256> r29_2;
+RegRow<T, P29, 15, 3, 8, 256> r29_3;
+RegRow<T, P509, 255, 2, 2, 512> r509_2;
+RegRow<T, P509, 255, 3, 1, 256> r509_3;
+}  // namespace
+}  // namespace hom

@@ -215,6 +215,11 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
+  const StaticKernel* sk = find_static(KK_EXPAND, sizeof(cpx<T>), G0, c->N[0], 0, p0->p);
+  if (sk) {
+    a.W = sk->W;
+    return launch_col_expand<T>(a, items, sk->lds, c->stream, sk);
+  }
   ColShape sh;
   if ((e = col_shape(p0->p, c->N[0], a.inner, sizeof(cpx<T>), &sh)) != hipSuccess) return e;
   a.W = sh.W;
@@ -244,6 +249,12 @@ static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int 
   a.plan = p1->p;
   a.tw = tw_of<T>(p1);
   a.sc = sc;
+  const StaticKernel* sk = find_static(sign > 0 ? KK_PLAIN_INV : KK_PLAIN_FWD, sizeof(cpx<T>),
+                                       G1, c->N[1], 0, p1->p);
+  if (sk) {
+    a.W = sk->W;
+    return launch_col_plain<T>(a, items, sign, sk->lds, c->stream, sk);
+  }
   ColShape sh;
   if ((e = col_shape(p1->p, std::max(a.n_in, a.n_out), a.inner, sizeof(cpx<T>), &sh)) !=
       hipSuccess)
@@ -281,6 +292,13 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   a.plan = pl->p;
   a.tw = tw_of<T>(pl);
   a.sc = sc;
+  const int Nlast = c->N[c->dd - 1];
+  const StaticKernel* sk =
+      (mode == ROW_APPLY) ? find_static(KK_ROW, sizeof(cpx<T>), Glast, Nlast, c->dd, pl->p) : nullptr;
+  if (sk) {
+    a.RP = sk->W;
+    return launch_row<T>(a, items, mode, sk->lds, c->stream, sk);
+  }
   size_t lds = 0;
   int RP = 0;
   if ((e = row_shape(pl->p, c->dd, rows, sizeof(cpx<T>), &RP, &lds)) != hipSuccess) return e;
@@ -320,6 +338,12 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
+  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), G0, c->N[0], 0, p0->p);
+  if (sk) {
+    a.W = sk->W;
+    if (tiles) *tiles = (a.inner + sk->W - 1) / sk->W;
+    return launch_col_project<T>(a, items, sk->lds, c->stream, sk);
+  }
   ColShape sh;
   if ((e = col_shape(p0->p, c->N[0], a.inner, sizeof(cpx<T>), &sh)) != hipSuccess) return e;
   a.W = sh.W;
@@ -331,8 +355,10 @@ template <class T>
 static int project_tiles(CellImpl* c) {
   const DevPlan* p0;
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
-  ColShape sh;
   const int inner = (int)inner0(c);
+  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), c->Q[0], c->N[0], 0, p0->p);
+  if (sk) return (inner + sk->W - 1) / sk->W;
+  ColShape sh;
   if (col_shape(p0->p, c->N[0], inner, sizeof(cpx<T>), &sh) != hipSuccess) return 0;
   return (inner + sh.W - 1) / sh.W;
 }
@@ -421,10 +447,17 @@ hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double
     a.scale = 1.0 / (double)N1;
     a.plan = p1->p;
     a.tw = p1->tw64;
-    ColShape sh;
-    if ((e = col_shape(p1->p, N1, a.inner, sizeof(cpx<double>), &sh)) != hipSuccess) return e;
-    a.W = sh.W;
-    if ((e = launch_col_plain<double>(a, items, -1, sh.lds, c->stream)) != hipSuccess) return e;
+    const StaticKernel* sk = find_static(KK_PLAIN_FWD, sizeof(cpx<double>), N1, N1, 0, p1->p);
+    if (sk) {
+      a.W = sk->W;
+      e = launch_col_plain<double>(a, items, -1, sk->lds, c->stream, sk);
+    } else {
+      ColShape sh;
+      if ((e = col_shape(p1->p, N1, a.inner, sizeof(cpx<double>), &sh)) != hipSuccess) return e;
+      a.W = sh.W;
+      e = launch_col_plain<double>(a, items, -1, sh.lds, c->stream);
+    }
+    if (e != hipSuccess) return e;
   } else {
     if ((e = stage_row<double>(c, items, ROW_FWD, nullptr, w.X1, N0, 1, N1, u, nullptr, nullptr,
                                nullptr)) != hipSuccess)
@@ -1161,4 +1194,9 @@ extern "C" hom_status hom_profile_iteration(hom_cell* hc, hom_prec prec, int L, 
   if (prec == HOM_FP64) e = profile_impl<double>(c, L, reps, ms, bytes);
   else e = profile_impl<float>(c, L, reps, ms, bytes);
   return dev_status(e);
+}
+
+extern "C" hom_status hom_set_specialized(int enable) {
+  hom::set_static_enabled(enable != 0);
+  return HOM_OK;
 }

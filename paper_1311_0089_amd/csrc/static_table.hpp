@@ -1,0 +1,89 @@
+// static_table.hpp -- the transform lengths that get compile-time
+// specialised pass kernels, with their launch shapes.
+//
+// Each entry: FFT length n, trial length (n for GaNi, (n+1)/2 for the doubled
+// Ga grid), radix plan (must equal the host planner's factorisation: odd
+// radices largest first, then 8, 4, 2; Bluestein grids for primes above 31),
+// column tile width W and workgroup size for FP32 and for FP64, and row pairs
+// per workgroup for 2 and 3 components.  Shapes keep dynamic LDS <= 66 KiB
+// (two or more workgroups per CU) and each Stockham stage within the per-
+// thread register budget (checked at compile time below).
+#pragma once
+#include "kernel_bodies.hpp"
+
+namespace hom {
+
+template <class T, class SP, int NTRIAL, int W, int NT>
+struct RegCol {
+  static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
+  static constexpr size_t lds = (size_t)SP::len * W * sizeof(cpx<T>);
+  static_assert(lds <= 66 * 1024 + 512, "column tile exceeds the LDS budget");
+  static_assert(PMAX <= 32, "too many positions per thread");
+  RegCol() {
+    using P = ColStat<SP, NTRIAL, W, NT>;
+    add(KK_EXPAND, (const void*)&k_col_expand<T, P, PMAX>);
+    add(KK_PROJECT, (const void*)&k_col_project<T, P, PMAX>);
+    add(KK_PLAIN_INV, (const void*)&k_col_plain<T, P, +1>);
+    add(KK_PLAIN_FWD, (const void*)&k_col_plain<T, P, -1>);
+  }
+  template <int... Rs>
+  static void fill(StaticKernel& k, Rad<Rs...>) {
+    const int r[] = {Rs...};
+    k.nst = (int)sizeof...(Rs);
+    for (int i = 0; i < k.nst; ++i) k.rad[i] = r[i];
+  }
+  static void add(int kind, const void* fn) {
+    StaticKernel k{};
+    k.kind = kind;
+    k.esz = (int)sizeof(cpx<T>);
+    k.n = SP::n;
+    k.ntrial = NTRIAL;
+    k.d = 0;
+    k.fn = fn;
+    k.W = W;
+    k.NT = NT;
+    k.lds = lds;
+    k.len = SP::len;
+    k.blue = SP::blue;
+    fill(k, typename SP::radices{});
+    register_static(k);
+  }
+};
+
+template <class T, class SP, int NTRIAL, int D, int RP, int NT>
+struct RegRow {
+  static constexpr size_t lds = (size_t)D * RP * SP::len * sizeof(cpx<T>);
+  static_assert(lds <= 66 * 1024 + 512, "row tile exceeds the LDS budget");
+  RegRow() {
+    using P = RowStat<SP, NTRIAL, D, RP, NT>;
+    StaticKernel k{};
+    k.kind = KK_ROW;
+    k.esz = (int)sizeof(cpx<T>);
+    k.n = SP::n;
+    k.ntrial = NTRIAL;
+    k.d = D;
+    k.fn = (const void*)&k_row<T, P, ROW_APPLY>;
+    k.W = RP;
+    k.NT = NT;
+    k.lds = lds;
+    k.len = SP::len;
+    k.blue = SP::blue;
+    RegCol<T, SP, NTRIAL, 1, 256>::fill(k, typename SP::radices{});
+    register_static(k);
+  }
+};
+
+// plans
+using P1023 = SPlan<1023, 1023, 0, Rad<31, 11, 3>>;
+using P255 = SPlan<255, 255, 0, Rad<17, 5, 3>>;
+using P127 = SPlan<127, 256, 1, Rad<8, 8, 4>>;
+using P63 = SPlan<63, 63, 0, Rad<9, 7>>;
+using P31 = SPlan<31, 31, 0, Rad<31>>;
+using P15 = SPlan<15, 15, 0, Rad<5, 3>>;
+using P253 = SPlan<253, 253, 0, Rad<23, 11>>;
+using P125 = SPlan<125, 125, 0, Rad<5, 5, 5>>;
+using P61 = SPlan<61, 128, 1, Rad<8, 8, 2>>;
+using P29 = SPlan<29, 29, 0, Rad<29>>;
+using P509 = SPlan<509, 1024, 1, Rad<8, 8, 8, 2>>;
+
+}  // namespace hom

@@ -20,7 +20,7 @@ ISO, DIAG, FULLSYM = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "hom_options_default", "hom_create_cell", "hom_solve", "hom_apply", "hom_project",
-    "hom_profile_iteration", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
+    "hom_profile_iteration", "hom_set_specialized", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
     "hom_server_create", "hom_server_submit", "hom_server_poll", "hom_server_times",
     "hom_server_destroy",
 ]
@@ -70,6 +70,7 @@ def lib():
         L.hom_apply.argtypes = [vp, ip, ip, vp, vp]
         L.hom_project.argtypes = [vp, ip, vp, vp]
         L.hom_profile_iteration.argtypes = [vp, ip, ip, ip, dp, dp]
+        L.hom_set_specialized.argtypes = [ip]
         L.hom_destroy_cell.argtypes = [vp]
         L.hom_destroy_cell.restype = None
         L.hom_cell_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
@@ -97,6 +98,11 @@ def _dptr(a: np.ndarray):
 def _current_stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def set_specialized(enable: bool) -> None:
+    """Use (True, default) or bypass (False) the compile-time specialised kernels."""
+    _check(lib().hom_set_specialized(1 if enable else 0), "hom_set_specialized")
 
 
 def make_options(scheme=GANI, prec=FP64, Y=None, max_iter=10000, max_outer=30, inner_tol=1e-4,

@@ -81,6 +81,52 @@ def test_operator_matches_oracle(hom, oracle, torch_cuda, N, kind, scheme):
     assert rel(out32, ref) < 2e-5
 
 
+# shapes whose passes run the compile-time specialised kernels (FFT lengths
+# 15, 29, 31, 61, 63, 125, 127, 253, 255, 509, 1023 with their trial lengths)
+SPECIALISED = [((15, 15), 0, 0), ((63, 63), 2, 0), ((127, 15), 0, 0), ((255, 15), 0, 0),
+               ((1023, 15), 0, 0), ((15, 1023), 0, 0), ((31, 15), 0, 1), ((15, 31), 2, 1),
+               ((15, 31, 15), 0, 0), ((15, 15, 31), 1, 0), ((15, 31, 15), 0, 1),
+               ((15, 15, 63), 2, 0), ((63, 15, 15), 0, 1), ((15, 63, 15), 1, 1)]
+# the same with a Bluestein length on the last (row) axis
+SPECIALISED_ROW_BLUESTEIN = [((15, 127), 1, 0), ((15, 15, 127), 0, 0), ((15, 15, 255), 0, 1)]
+
+
+def _apply_case(hom, oracle, torch, N, kind, scheme, specialised):
+    d = len(N)
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    A = hi.random_spd_field(Q, kind, seed=7 + kind, contrast=30.0)
+    ocell = oracle.Cell(A, N, kind=kind, scheme=scheme)
+    hom.set_specialized(specialised)
+    try:
+        gcell = hom.Cell(A, N, kind=kind, scheme=scheme)
+        u = np.stack([ocell.apply_G(rand_field((d,) + N, 200 + l)) for l in range(2)])
+        ref = np.stack([ocell.apply_GA(u[l]) for l in range(2)])
+        ut = torch.from_numpy(u).cuda()
+        out64 = gcell.apply(ut, prec=hom.FP64).cpu().numpy()
+        out32 = gcell.apply(ut, prec=hom.MIXED).cpu().numpy()
+    finally:
+        hom.set_specialized(True)
+    assert rel(out64, ref) < 1e-12
+    assert rel(out32, ref) < 2e-5
+    return out64
+
+
+@gpu
+@pytest.mark.parametrize("N,kind,scheme", SPECIALISED)
+def test_specialised_operator_matches_oracle(hom, oracle, torch_cuda, N, kind, scheme):
+    """Operator parity through the specialised kernels, and agreement of the
+    specialised and generic kernels on the same input."""
+    a = _apply_case(hom, oracle, torch_cuda, N, kind, scheme, True)
+    b = _apply_case(hom, oracle, torch_cuda, N, kind, scheme, False)
+    assert rel(a, b) < 1e-13
+
+
+@gpu
+@pytest.mark.parametrize("N,kind,scheme", SPECIALISED_ROW_BLUESTEIN)
+def test_specialised_row_bluestein_matches_oracle(hom, oracle, torch_cuda, N, kind, scheme):
+    _apply_case(hom, oracle, torch_cuda, N, kind, scheme, True)
+
+
 @gpu
 def test_square_inclusion_fp64(hom, oracle, torch_cuda):
     """2-D 15x15 square inclusion (contrast 10), both load cases: fields and
