@@ -135,6 +135,19 @@ hom_status hom_profile_iteration(hom_cell* c, hom_prec prec, int L, int reps, do
  * Process-wide; for A/B timing and testing. */
 hom_status hom_set_specialized(int enable);
 
+/* Autotuner: for each pass of c's CG iteration (L load cases, precision
+ * prec), time every compile-time variant and the generic kernel (reps
+ * launches each, HIP events) and keep the fastest, process-wide, keyed by
+ * (pass, FFT length, trial length, precision, components).  best_us
+ * (nullable, 5 entries) receives the winning times in pass order.  Not to be
+ * run while other threads solve. */
+hom_status hom_autotune(hom_cell* c, hom_prec prec, int L, int reps, double* best_us);
+/* Write / read the tuned choices as JSON ({"arch": ..., "choices": [[pass,
+ * element bytes, FFT length, trial length, components, variant], ...]});
+ * loading a file tuned on another GPU architecture returns HOM_EINVAL. */
+hom_status hom_tune_save(const char* path);
+hom_status hom_tune_load(const char* path);
+
 void hom_destroy_cell(hom_cell* c);
 const char* hom_status_str(hom_status s);
 /* Grid sizes of a cell: N[3], Q[3] (unused axes 1), d. */

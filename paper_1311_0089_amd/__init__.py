@@ -6,7 +6,7 @@ binding over it.  Importing the package does not load the library; the first
 use does, and fails loudly if it has not been built.
 """
 from .hom import (Cell, HomError, Server, lib, GANI, GA, FP64, MIXED, ISO, DIAG, FULLSYM,
-                  EXPORTED_SYMBOLS, set_specialized)
+                  EXPORTED_SYMBOLS, set_specialized, tune_save, tune_load)
 
 __all__ = ["Cell", "Server", "HomError", "lib", "GANI", "GA", "FP64", "MIXED", "ISO", "DIAG",
-           "FULLSYM", "EXPORTED_SYMBOLS", "set_specialized"]
+           "FULLSYM", "EXPORTED_SYMBOLS", "set_specialized", "tune_save", "tune_load"]

@@ -62,10 +62,34 @@ struct CellImpl {
   double* ebuf = nullptr;     // FP64 real strain scratch [items][d][Q]
   long ebuf_items = 0;
   double* quad = nullptr;     // quadrature partials / outputs
+  int A_group = 1 << 30;      // items sharing one coefficient block (batched cells: d)
+  long A_block = 0;           // elements per coefficient block (0: one shared block)
   std::map<GraphKey, hipGraphExec_t> graphs;
   std::mutex mu;
   ~CellImpl();
 };
+
+// non-owning view of items [i0, items) of a workspace
+template <class T>
+Work<T> work_view(const Work<T>& w, int i0, long S, long Xe, int d, int P) {
+  Work<T> v;
+  v.items = w.items - i0;
+  v.x = w.x + (long)i0 * S;
+  v.r = w.r + (long)i0 * S;
+  v.p = w.p + (long)i0 * S;
+  v.q = w.q + (long)i0 * S;
+  v.b = w.b + (long)i0 * S;
+  v.X1 = w.X1 + (long)i0 * d * Xe;
+  v.X2 = w.X2 + (long)i0 * d * Xe;
+  v.part = w.part + (long)i0 * P;
+  v.part2 = w.part2 + (long)i0 * P;
+  v.sc = w.sc + i0;
+  return v;
+}
+
+// engine pool (solver.hip): reuse the device state of destroyed cells
+CellImpl* pool_take(int device, const CellImpl& key);
+void pool_put(CellImpl* c);
 
 // pipeline entry points (solver.hip)
 hipError_t cell_setup(CellImpl* c);
@@ -82,9 +106,20 @@ hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int 
                       cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
                       double* partials);
 // real strain on grid G (G = N or Q) from the potential: e = E + F_G^-1 Pad(n c)
-hipError_t pipe_synth(CellImpl* c, int items, const cpx<double>* cin, const double* dE,
-                      bool onQ, double* out);
+hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>* cin,
+                      const double* dE, bool onQ, double* out);
+// launch helpers shared with the serving runtime
+int update_blocks(long S);
+int partial_slots(const CellImpl* c);
+template <class T>
+int project_tiles(CellImpl* c);
+template <class T>
+hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out);
 // scalar potential of a real field u on the N grid: c = n . F_N[u]
 hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double>* cout);
 
 }  // namespace hom
+
+struct hom_cell {
+  hom::CellImpl* impl;
+};

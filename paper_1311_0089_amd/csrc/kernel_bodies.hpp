@@ -13,6 +13,15 @@
 
 namespace hom {
 
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (block b
+// goes to XCD b mod 8).  Give each XCD a contiguous run of tiles so that
+// neighbouring tiles, which share cache lines, meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  if (n % 8) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
+
 struct ColGen {
   static constexpr int NT = kThreads;
   __device__ static int W(int w) { return w; }
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
   const int item = blockIdx.y;
   if (a.sc && !a.sc[item].active) return;
   const int W = P::W(a.W), n_in = P::ntrial(a.n_in), n_fft = P::nfft(a.n_fft);
-  const int col0 = blockIdx.x * W;
+  const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
   const int ncols = min(W, a.inner - col0);
   const long ibase = (long)item * a.c_stride;
   const T beta = a.fuse ? T(a.sc[item].beta) : T(0);
@@ -189,7 +198,7 @@ __global__ __launch_bounds__(P::NT) void k_col_plain(ColPlainArgs<T> a) {
   const int n_in = (S > 0) ? P::ntrial(a.n_in) : P::nfft(a.n_in);
   const int n_out = (S > 0) ? P::nfft(a.n_out) : P::ntrial(a.n_out);
   const int o = blockIdx.y;
-  const int col0 = blockIdx.x * W;
+  const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
   const int ncols = min(W, a.inner - col0);
   const cpx<T>* in = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride +
                      (long)o * n_in * a.inner + col0;
@@ -224,7 +233,8 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   const int item = blockIdx.y;
   if (a.sc && !a.sc[item].active) return;
   const int W = P::W(a.W), n_fft = P::nfft(a.n_fft), n_out = P::ntrial(a.n_out);
-  const int col0 = blockIdx.x * W;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int col0 = tile * W;
   const int ncols = min(W, a.inner - col0);
   const int npos = n_out * W;
   cpx<T> acc[PMAX];
@@ -295,7 +305,7 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   }
   if (a.partials) {
     part = block_sum<NT>(part);
-    if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
+    if (threadIdx.x == 0) a.partials[(long)item * a.P + tile] = part;
   }
 }
 
@@ -336,7 +346,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   if (a.sc && !a.sc[item].active) return;
   const int n = P::n(a.n), H = P::H(a.H), RP = P::RP(a.RP), d = P::D(a.d);
   const int ls = P::ls(a.plan.len);
-  const int pair0 = blockIdx.x * RP;
+  const int pair0 = xcd_tile(blockIdx.x, gridDim.x) * RP;
 
   if (MODE == ROW_APPLY || MODE == ROW_SYNTH) {
     // Z(h) = X_a(h) + i X_b(h), Z(n-h) = conj X_a(h) + i conj X_b(h)
@@ -394,7 +404,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   }
 
   if (MODE == ROW_APPLY || MODE == ROW_CONST) {
-    const T* A = a.A + (long)item * a.A_stride;
+    const T* A = a.A + (long)(item / a.A_group) * a.A_stride;
     for (int f = threadIdx.x; f < RP * n; f += NT) {
       const int lp = f / n, x = f % n;
       const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;

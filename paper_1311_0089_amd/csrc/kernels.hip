@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "kernel_bodies.hpp"
@@ -24,19 +26,52 @@ static bool g_static_on = true;
 static size_t g_static_max_lds = 0;
 void set_static_enabled(bool on) { g_static_on = on; }
 bool static_enabled() { return g_static_on; }
-const StaticKernel* find_static(int kind, int esz, int n, int ntrial, int d, const FftPlan& p) {
-  if (!g_static_on) return nullptr;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_choice;   // -1: generic kernel, v >= 0: v-th variant
+
+std::vector<const StaticKernel*> static_variants(int kind, int esz, int n, int ntrial, int d,
+                                                 const FftPlan& p) {
+  std::vector<const StaticKernel*> out;
   for (const StaticKernel& k : static_registry()) {
     if (k.kind != kind || k.esz != esz || k.n != n || k.ntrial != ntrial || k.d != d) continue;
-    if (k.lds > g_static_max_lds) continue;
+    // static LDS of the block reductions sits on top of the dynamic size
+    if (k.lds + 1024 > g_static_max_lds) continue;
     // the compile-time plan must describe the same tables the host uploaded
     if (k.len != p.len || k.blue != p.blue || k.nst != p.nst) continue;
     bool same = true;
     for (int i = 0; i < p.nst; ++i) same = same && (k.rad[i] == p.rad[i]);
     if (!same) continue;
-    return &k;
+    out.push_back(&k);
   }
-  return nullptr;
+  return out;
+}
+
+void set_choice(const TuneKey& key, int v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_choice[key] = v;
+}
+bool get_choice(const TuneKey& key, int* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_choice.find(key);
+  if (it == g_choice.end()) return false;
+  *v = it->second;
+  return true;
+}
+std::map<TuneKey, int> all_choices() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_choice;
+}
+
+const StaticKernel* find_static(int kind, int esz, int n, int ntrial, int d, const FftPlan& p) {
+  if (!g_static_on) return nullptr;
+  std::vector<const StaticKernel*> v = static_variants(kind, esz, n, ntrial, d, p);
+  if (v.empty()) return nullptr;
+  int c = 0;
+  if (get_choice(TuneKey{kind, esz, n, ntrial, d}, &c)) {
+    if (c < 0) return nullptr;
+    if (c < (int)v.size()) return v[c];
+  }
+  return v[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -67,9 +102,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg_init(ItemScal* sc, const double* partials, int P,
-                                                      int nparts) {
+                                                      int nparts, const ItemScal* mask) {
   const int item = blockIdx.x;
-  if (!sc[item].active) return;
+  if (!sc[item].active || (mask && !mask[item].active)) return;
   const double s = sum_partials(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
     ItemScal& q = sc[item];
@@ -128,9 +163,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_beta(ItemScal* sc, const double
 }
 
 __global__ __launch_bounds__(kThreads) void k_outer_check(ItemScal* sc, const double* partials,
-                                                          int P, int nparts, int init) {
+                                                          int P, int nparts, int init,
+                                                          const ItemScal* mask) {
   const int item = blockIdx.x;
-  if (!sc[item].active) return;
+  if (!sc[item].active || (mask && !mask[item].active)) return;
   const double s = sum_partials(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
     ItemScal& q = sc[item];
@@ -157,8 +193,10 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
                                                           long stride, long count, int H,
                                                           ItemScal* outer, ItemScal* inner,
                                                           double eta, int max_iter,
-                                                          double* partials, int P) {
+                                                          double* partials, int P,
+                                                          const ItemScal* mask) {
   const int item = blockIdx.y;
+  if (mask && !mask[item].active) return;
   if (!outer[item].active) {
     if (blockIdx.x == 0 && threadIdx.x == 0) inner[item].active = 0;
     return;
@@ -188,9 +226,10 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
 
 __global__ __launch_bounds__(kThreads) void k_inner_accumulate(cpx<double>* x64,
                                                                const cpx<float>* x32, long stride,
-                                                               long count, const ItemScal* outer) {
+                                                               long count, const ItemScal* outer,
+                                                               const ItemScal* mask) {
   const int item = blockIdx.y;
-  if (!outer[item].active) return;
+  if (!outer[item].active || (mask && !mask[item].active)) return;
   const double sc = sqrt(outer[item].rho);
   const long base = (long)item * stride;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -363,8 +402,8 @@ hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hip
 }
 
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
+                          hipStream_t s, const ItemScal* mask) {
+  hipLaunchKernelGGL(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask);
   return hipGetLastError();
 }
 hipError_t launch_cg_alpha(ItemScal* sc, const double* partials, int P, int nparts, int items,
@@ -378,23 +417,24 @@ hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int npart
   return hipGetLastError();
 }
 hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                              int init, hipStream_t s) {
+                              int init, hipStream_t s, const ItemScal* mask) {
   hipLaunchKernelGGL(k_outer_check, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts,
-                     init);
+                     init, mask);
   return hipGetLastError();
 }
 hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float>* p32,
                               cpx<float>* x32, long stride, long count, int H, ItemScal* outer,
                               ItemScal* inner, double eta, int max_iter, double* partials, int P,
-                              int blocks, int items, hipStream_t s) {
+                              int blocks, int items, hipStream_t s, const ItemScal* mask) {
   hipLaunchKernelGGL(k_inner_start, dim3(blocks, items), dim3(kThreads), 0, s, r64, r32, p32, x32,
-                     stride, count, H, outer, inner, eta, max_iter, partials, P);
+                     stride, count, H, outer, inner, eta, max_iter, partials, P, mask);
   return hipGetLastError();
 }
 hipError_t launch_inner_accumulate(cpx<double>* x64, const cpx<float>* x32, long stride, long count,
-                                   const ItemScal* outer, int blocks, int items, hipStream_t s) {
+                                   const ItemScal* outer, int blocks, int items, hipStream_t s,
+                                   const ItemScal* mask) {
   hipLaunchKernelGGL(k_inner_accumulate, dim3(blocks, items), dim3(kThreads), 0, s, x64, x32,
-                     stride, count, outer);
+                     stride, count, outer, mask);
   return hipGetLastError();
 }
 hipError_t launch_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active,

@@ -15,6 +15,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <vector>
 
 #include "fft_device.hpp"
@@ -105,8 +106,9 @@ struct RowArgs {
   const double* ureal;  // ROW_FWD input  [item][d][rows][n]
   double* oreal;        // ROW_SYNTH output [item][d][rows][n]
   long real_stride, real_cstride;
-  const T* A;           // [nA][rows][n] (+ A_stride per item)
+  const T* A;           // [block][nA][rows][n]; item i uses block i / A_group
   long A_stride, A_cstride;
+  int A_group;          // items sharing one coefficient block (>= 1)
   int kind;             // 0 iso, 1 diag, 2 full symmetric (Voigt)
   const double* E;      // [item][d] (ROW_CONST, ROW_SYNTH)
   int d, rows, n, H, RP;
@@ -143,8 +145,24 @@ void register_static(const StaticKernel& k);
 void set_static_enabled(bool on);
 bool static_enabled();
 // entry for (kind, element size, FFT length, trial length, d) whose plan
-// matches p, or nullptr (then the generic kernel runs)
+// matches p, or nullptr (then the generic kernel runs); follows the tuned
+// choice when one is recorded, else the first registered variant
 const StaticKernel* find_static(int kind, int esz, int n, int ntrial, int d, const FftPlan& p);
+std::vector<const StaticKernel*> static_variants(int kind, int esz, int n, int ntrial, int d,
+                                                 const FftPlan& p);
+struct TuneKey {
+  int kind, esz, n, ntrial, d;
+  bool operator<(const TuneKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (esz != o.esz) return esz < o.esz;
+    if (n != o.n) return n < o.n;
+    if (ntrial != o.ntrial) return ntrial < o.ntrial;
+    return d < o.d;
+  }
+};
+void set_choice(const TuneKey& key, int v);  // -1 generic, v >= 0 the v-th variant
+bool get_choice(const TuneKey& key, int* v);
+std::map<TuneKey, int> all_choices();
 
 // launchers (defined in kernels.hip); sk selects a specialised kernel (its W /
 // row pairs must already be in the arguments); all return the launch status
@@ -163,8 +181,9 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
 template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s);
 
+// mask (nullable): only items active in the mask are touched
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                          hipStream_t s);
+                          hipStream_t s, const ItemScal* mask = nullptr);
 hipError_t launch_cg_alpha(ItemScal* sc, const double* partials, int P, int nparts, int items,
                            hipStream_t s);
 hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int nparts, int items,
@@ -173,16 +192,17 @@ hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int npart
 // sqrt(rho / rho0) <= tol or after max_iter refinement steps; the first call
 // (init != 0) sets rho0.
 hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                              int init, hipStream_t s);
+                              int init, hipStream_t s, const ItemScal* mask = nullptr);
 // inner FP32 start: r32 = p32 = r64 / sqrt(rho_out), x32 = 0, inner scalars
 // reset, outer step counter incremented
 hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float>* p32,
                               cpx<float>* x32, long stride, long count, int H, ItemScal* outer,
                               ItemScal* inner, double eta, int max_iter, double* partials, int P,
-                              int blocks, int items, hipStream_t s);
+                              int blocks, int items, hipStream_t s, const ItemScal* mask = nullptr);
 // x64 += sqrt(rho_out) * x32
 hipError_t launch_inner_accumulate(cpx<double>* x64, const cpx<float>* x32, long stride, long count,
-                                   const ItemScal* outer, int blocks, int items, hipStream_t s);
+                                   const ItemScal* outer, int blocks, int items, hipStream_t s,
+                                   const ItemScal* mask = nullptr);
 // x = 0, active flags etc.
 hipError_t launch_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active,
                            hipStream_t s);

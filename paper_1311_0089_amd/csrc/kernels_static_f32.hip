@@ -5,8 +5,10 @@ namespace hom {
 namespace {
 using T = float;
 // columns: plan, trial length, W, workgroup size
-RegCol<T, P1023, 1023, 8, 512> c1023;
+RegCol<T, P1023, 1023, 4, 256> c1023;
+RegCol<T, P1023, 1023, 8, 512> c1023w;
 RegCol<T, P255, 255, 16, 256> c255;
+RegCol<T, P255, 255, 8, 256> c255n;
 RegCol<T, P127, 127, 16, 256> c127;
 RegCol<T, P63, 63, 16, 256> c63;
 RegCol<T, P31, 31, 16, 256> c31;
@@ -17,7 +19,8 @@ RegCol<T, P61, 31, 16, 256> c61;
 RegCol<T, P29, 15, 16, 256> c29;
 RegCol<T, P509, 255, 8, 512> c509;
 // rows: plan, trial length, components, row pairs, workgroup size
-RegRow<T, P1023, 1023, 2, 4, 512> r1023_2;
+RegRow<T, P1023, 1023, 2, 2, 256> r1023_2;
+RegRow<T, P1023, 1023, 2, 4, 512> r1023_2w;
 RegRow<T, P1023, 1023, 3, 2, 512> r1023_3;
 RegRow<T, P255, 255, 2, 8, 256> r255_2;
 RegRow<T, P255, 255, 3, 8, 512> r255_3;

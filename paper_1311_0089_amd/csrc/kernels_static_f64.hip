@@ -4,7 +4,8 @@
 namespace hom {
 namespace {
 using T = double;
-RegCol<T, P1023, 1023, 4, 512> c1023;
+RegCol<T, P1023, 1023, 2, 256> c1023;
+RegCol<T, P1023, 1023, 4, 512> c1023w;
 RegCol<T, P255, 255, 8, 256> c255;
 RegCol<T, P127, 127, 8, 256> c127;
 RegCol<T, P63, 63, 16, 256> c63;
@@ -15,7 +16,8 @@ RegCol<T, P125, 63, 16, 256> c125;
 RegCol<T, P61, 31, 16, 256> c61;
 RegCol<T, P29, 15, 16, 256> c29;
 RegCol<T, P509, 255, 4, 512> c509;
-RegRow<T, P1023, 1023, 2, 2, 512> r1023_2;
+RegRow<T, P1023, 1023, 2, 1, 256> r1023_2;
+RegRow<T, P1023, 1023, 2, 2, 512> r1023_2w;
 RegRow<T, P1023, 1023, 3, 1, 256> r1023_3;
 RegRow<T, P255, 255, 2, 4, 256> r255_2;
 RegRow<T, P255, 255, 3, 4, 256> r255_3;

@@ -5,14 +5,15 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <string>
 #include <vector>
 
 #include "cell.hpp"
 
-struct hom_cell {
-  hom::CellImpl impl;
-};
 
 namespace hom {
 
@@ -120,14 +121,14 @@ const cpx<double>* tw_of<double>(const DevPlan* p) { return p->tw64; }
 template <>
 const cpx<float>* tw_of<float>(const DevPlan* p) { return p->tw32; }
 
-static int update_blocks(long S) {
+int update_blocks(long S) {
   long b = (S + kThreads - 1) / kThreads;
   if (b > 512) b = 512;
   if (b < 1) b = 1;
   return (int)b;
 }
 
-static int partial_slots(const CellImpl* c) {
+int partial_slots(const CellImpl* c) {
   // enough for every producer: column tiles (<= inner) and update blocks
   long inner = (c->dd == 3) ? (long)c->N[1] * c->H : c->H;
   long P = std::max<long>(inner, 512);
@@ -281,7 +282,8 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   a.real_cstride = rows * Glast;
   a.real_stride = (long)c->dd * a.real_cstride;
   a.A = (sizeof(T) == 8) ? (const T*)(const void*)c->A64 : (const T*)(const void*)c->A32;
-  a.A_stride = 0;
+  a.A_stride = c->A_block;
+  a.A_group = c->A_group;
   a.A_cstride = c->nQ;
   a.kind = c->kind;
   a.E = dE;
@@ -352,7 +354,7 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
 }
 
 template <class T>
-static int project_tiles(CellImpl* c) {
+int project_tiles(CellImpl* c) {
   const DevPlan* p0;
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
   const int inner = (int)inner0(c);
@@ -405,10 +407,9 @@ hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemSc
                           w.part, sc, nullptr);
 }
 
-hipError_t pipe_synth(CellImpl* c, int items, const cpx<double>* cin, const double* dE, bool onQ,
-                      double* out) {
+hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>* cin,
+                      const double* dE, bool onQ, double* out) {
   hipError_t e;
-  Work<double>& w = c->w64;
   const int G0 = onQ ? c->Q[0] : c->N[0];
   const int G1 = onQ ? c->Q[1] : c->N[1];
   const int G2 = onQ ? c->Q[2] : c->N[2];
@@ -474,6 +475,8 @@ template hipError_t pipe_apply<double>(CellImpl*, Work<double>&, int, const cpx<
                                        cpx<double>*, const cpx<double>*, const cpx<double>*,
                                        ItemScal*, double*);
 template hipError_t pipe_rhs<float>(CellImpl*, Work<float>&, int, const double*, ItemScal*);
+template int project_tiles<float>(CellImpl*);
+template int project_tiles<double>(CellImpl*);
 template hipError_t pipe_rhs<double>(CellImpl*, Work<double>&, int, const double*, ItemScal*);
 
 // ---------------------------------------------------------------------------
@@ -508,7 +511,7 @@ static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K) {
 }
 
 template <class T>
-static hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
+hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
   GraphKey key{(int)sizeof(T), items, K};
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
@@ -533,6 +536,9 @@ static hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
   *out = ex;
   return hipSuccess;
 }
+
+template hipError_t cg_graph<float>(CellImpl*, int, int, hipGraphExec_t*);
+template hipError_t cg_graph<double>(CellImpl*, int, int, hipGraphExec_t*);
 
 // run CG until every item is inactive; returns max iterations
 template <class T>
@@ -615,7 +621,7 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
     if ((e = ensure_ebuf(c, L)) != hipSuccess) return e;
     eQ = c->ebuf;
   }
-  if ((e = pipe_synth(c, L, x, dE, true, eQ)) != hipSuccess) return e;
+  if ((e = pipe_synth(c, c->w64, L, x, dE, true, eQ)) != hipSuccess) return e;
   if (!c->quad) {
     if ((e = hipMalloc(&c->quad, sizeof(double) * (1024 * 18 + 64))) != hipSuccess) return e;
   }
@@ -652,11 +658,11 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
     if (gani && c->d == c->dd) {
       // unreachable: handled above
     } else if (c->d == c->dd) {
-      if ((e = pipe_synth(c, L, x, dE, false, strain_user)) != hipSuccess) return e;
+      if ((e = pipe_synth(c, c->w64, L, x, dE, false, strain_user)) != hipSuccess) return e;
     } else {
       // d = 1 run as 2-D with one point along axis 1: copy component 0 of each item
       if (!gani) {
-        if ((e = pipe_synth(c, L, x, dE, false, c->ebuf)) != hipSuccess) return e;
+        if ((e = pipe_synth(c, c->w64, L, x, dE, false, c->ebuf)) != hipSuccess) return e;
       }
       for (int l = 0; l < L; ++l) {
         const double* src = c->ebuf + (size_t)l * c->dd * (gani ? c->nQ : c->nN);
@@ -680,6 +686,54 @@ static hipError_t warm_start(CellImpl* c, int L, const double* strain0) {
     return e;
   return hipMemcpyAsync(w.p, w.r, sizeof(cpx<double>) * (size_t)c->S * L,
                         hipMemcpyDeviceToDevice, c->stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// engine pool: device buffers, stream and captured graphs of destroyed cells
+// are kept (a few per process) and handed to new cells of the same shape, so
+// that creating such a cell costs only the upload of its coefficient field
+// ---------------------------------------------------------------------------
+static std::mutex g_pool_mu;
+static std::vector<CellImpl*> g_pool;
+static const size_t kPoolMax = 4;
+
+static bool same_shape(const CellImpl* a, const CellImpl& b) {
+  if (a->dd != b.dd || a->scheme != b.scheme || a->kind != b.kind || a->nA != b.nA) return false;
+  for (int i = 0; i < 3; ++i)
+    if (a->N[i] != b.N[i] || a->Q[i] != b.Q[i] || a->Y[i] != b.Y[i]) return false;
+  return true;
+}
+
+CellImpl* pool_take(int device, const CellImpl& key) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (size_t i = g_pool.size(); i-- > 0;) {
+    CellImpl* c = g_pool[i];
+    if (c->device == device && same_shape(c, key)) {
+      g_pool.erase(g_pool.begin() + (long)i);
+      return c;
+    }
+  }
+  return nullptr;
+}
+
+void pool_put(CellImpl* c) {
+  CellImpl* evict = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back(c);
+    if (g_pool.size() > kPoolMax) {
+      evict = g_pool.front();
+      g_pool.erase(g_pool.begin());
+    }
+  }
+  if (evict) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(evict->device);
+    delete evict;
+    (void)hipSetDevice(cur);
+  }
 }
 
 }  // namespace hom
@@ -799,89 +853,120 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
     if (N[a] < 1 || (N[a] % 2) == 0 || N[a] > (1 << 20)) return HOM_EINVAL;
     if (!(o.Y[a] > 0) || !std::isfinite(o.Y[a])) return HOM_EINVAL;
   }
-  hom_cell* hc = new (std::nothrow) hom_cell();
-  if (!hc) return HOM_ENOMEM;
-  CellImpl* c = &hc->impl;
-  c->d = d;
-  c->dd = d < 2 ? 2 : d;
-  c->scheme = o.scheme;
-  c->opt = o;
+  // everything shape-related first; the device engine may come from the pool
+  CellImpl key;
+  key.d = d;
+  key.dd = d < 2 ? 2 : d;
+  key.scheme = o.scheme;
   const int nA_user = (kind == HOM_A_ISO) ? 1 : (kind == HOM_A_DIAG) ? d : d * (d + 1) / 2;
   // d = 1 runs as a 2-D cell with a single grid point along the second axis;
   // its one coefficient acts as an isotropic one (e_2 vanishes identically)
-  c->kind = (d == 1) ? HOM_A_ISO : kind;
-  c->nA = (d == 1) ? 1 : nA_user;
-  for (int a = 0; a < c->dd; ++a) {
-    c->N[a] = (a < d) ? N[a] : 1;
-    c->Q[a] = (o.scheme == HOM_GA) ? 2 * c->N[a] - 1 : c->N[a];
-    c->Y[a] = (a < d) ? o.Y[a] : 0.5;
+  key.kind = (d == 1) ? HOM_A_ISO : kind;
+  key.nA = (d == 1) ? 1 : nA_user;
+  for (int a = 0; a < key.dd; ++a) {
+    key.N[a] = (a < d) ? N[a] : 1;
+    key.Q[a] = (o.scheme == HOM_GA) ? 2 * key.N[a] - 1 : key.N[a];
+    key.Y[a] = (a < d) ? o.Y[a] : 0.5;
   }
   long nQ = 1;
-  for (int a = 0; a < c->dd; ++a) nQ *= c->Q[a];
-  // host copy of A for validation
+  for (int a = 0; a < key.dd; ++a) nQ *= key.Q[a];
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return dev_status(e);
+  // host copy of A for validation (A2: finite, symmetric positive definite)
   std::vector<double> hA((size_t)nA_user * nQ);
-  hipError_t e = hipGetDevice(&c->device);
-  if (e != hipSuccess) {
-    delete hc;
-    return dev_status(e);
-  }
   if (A_on_device) {
     e = hipMemcpy(hA.data(), A, sizeof(double) * hA.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
-      delete hc;
-      return dev_status(e);
-    }
+    if (e != hipSuccess) return dev_status(e);
   } else {
     std::memcpy(hA.data(), A, sizeof(double) * hA.size());
   }
   double lo = INFINITY, hi = 0.0;
-  std::vector<double> v(6);
-  for (long p = 0; p < nQ; ++p) {
-    for (int t = 0; t < nA_user; ++t) v[t] = hA[(size_t)t * nQ + p];
-    double l, h;
-    bool ok = point_range(d, kind, v.data(), &l, &h);
-    if (!ok) {
-      bool finite = true;
-      for (int t = 0; t < nA_user; ++t) finite = finite && std::isfinite(v[t]);
-      delete hc;
-      return finite ? HOM_ENOTSPD : HOM_EINVAL;
+  if (kind != HOM_A_FULLSYM || d == 1) {
+    // every plane holds eigenvalues directly
+    bool finite = true;
+    for (size_t i = 0; i < hA.size(); ++i) {
+      const double x = hA[i];
+      finite = finite && std::isfinite(x);
+      lo = std::min(lo, x);
+      hi = std::max(hi, x);
     }
-    lo = std::min(lo, l);
-    hi = std::max(hi, h);
+    if (!finite) return HOM_EINVAL;
+    if (!(lo > 0)) return HOM_ENOTSPD;
+  } else {
+    std::vector<double> v(6);
+    for (long p = 0; p < nQ; ++p) {
+      for (int t = 0; t < nA_user; ++t) v[t] = hA[(size_t)t * nQ + p];
+      double l, h;
+      if (!point_range(d, kind, v.data(), &l, &h)) {
+        bool finite = true;
+        for (int t = 0; t < nA_user; ++t) finite = finite && std::isfinite(v[t]);
+        return finite ? HOM_ENOTSPD : HOM_EINVAL;
+      }
+      lo = std::min(lo, l);
+      hi = std::max(hi, h);
+    }
   }
+  CellImpl* c = pool_take(device, key);
+  if (!c) {
+    c = new (std::nothrow) CellImpl();
+    if (!c) return HOM_ENOMEM;
+    c->device = device;
+    c->d = key.d;
+    c->dd = key.dd;
+    c->scheme = key.scheme;
+    c->kind = key.kind;
+    c->nA = key.nA;
+    for (int a = 0; a < 3; ++a) {
+      c->N[a] = key.N[a];
+      c->Q[a] = key.Q[a];
+      c->Y[a] = key.Y[a];
+    }
+    const size_t nAd = (size_t)c->nA * nQ;
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&c->A64, sizeof(double) * nAd);
+    if (e == hipSuccess) e = hipMalloc(&c->A32, sizeof(float) * nAd);
+    if (e == hipSuccess) e = cell_setup(c);
+    if (e != hipSuccess) {
+      delete c;
+      return dev_status(e);
+    }
+  }
+  c->d = d;
+  c->opt = o;
   c->rhoA = hi / lo;
-  if (d == 1 && kind == HOM_A_DIAG) {
-    // nothing to do: one plane
-  }
-  // device copies: FP64 and FP32
   const size_t nAd = (size_t)c->nA * nQ;
   std::vector<float> hA32(nAd);
   for (size_t i = 0; i < nAd; ++i) hA32[i] = (float)hA[i];
-  e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc(&c->A64, sizeof(double) * nAd);
-  if (e == hipSuccess) e = hipMalloc(&c->A32, sizeof(float) * nAd);
+  e = hipMemcpyAsync(c->A64, hA.data(), sizeof(double) * nAd, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpy(c->A64, hA.data(), sizeof(double) * nAd, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(c->A32, hA32.data(), sizeof(float) * nAd, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = cell_setup(c);
+    e = hipMemcpyAsync(c->A32, hA32.data(), sizeof(float) * nAd, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
-    delete hc;
+    delete c;
     return dev_status(e);
   }
+  hom_cell* hc = new (std::nothrow) hom_cell();
+  if (!hc) {
+    pool_put(c);
+    return HOM_ENOMEM;
+  }
+  hc->impl = c;
   *out = hc;
   return HOM_OK;
 }
 
-void hom_destroy_cell(hom_cell* c) {
-  if (!c) return;
-  (void)hipStreamSynchronize(c->impl.stream);
-  delete c;
+void hom_destroy_cell(hom_cell* hc) {
+  if (!hc) return;
+  CellImpl* c = hc->impl;
+  (void)hipStreamSynchronize(c->stream);
+  delete hc;
+  pool_put(c);
 }
 
 hom_status hom_cell_dims(const hom_cell* c, int32_t* d, int32_t* N, int32_t* Q) {
   if (!c) return HOM_EINVAL;
-  const CellImpl& i = c->impl;
+  const CellImpl& i = *c->impl;
   if (d) *d = i.d;
   for (int a = 0; a < 3; ++a) {
     if (N) N[a] = (a < i.d) ? i.N[a] : 1;
@@ -903,9 +988,9 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
                      double* J, const double* strain0, hom_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   if (!hc || L < 1 || !E || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
-  for (int i = 0; i < L * hc->impl.d; ++i)
+  for (int i = 0; i < L * hc->impl->d; ++i)
     if (!std::isfinite(E[i])) return HOM_EINVAL;
-  CellImpl* c = &hc->impl;
+  CellImpl* c = hc->impl;
   std::lock_guard<std::mutex> lk(c->mu);
   const bool mixed = (c->opt.prec == HOM_MIXED);
   hipError_t e = hipSetDevice(c->device);
@@ -1016,7 +1101,7 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
 
 hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double* out) {
   if (!hc || L < 1 || !u || !out || (prec != HOM_FP64 && prec != HOM_MIXED)) return HOM_EINVAL;
-  CellImpl* c = &hc->impl;
+  CellImpl* c = hc->impl;
   if (c->d != c->dd) return HOM_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipSetDevice(c->device);
@@ -1042,7 +1127,7 @@ hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double
         break;
       if ((e = launch_widen((const float*)w32.q, (double*)w.q, n, c->stream)) != hipSuccess) break;
     }
-    if ((e = pipe_synth(c, L, w.q, dE, false, out)) != hipSuccess) break;
+    if ((e = pipe_synth(c, c->w64, L, w.q, dE, false, out)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (false);
   if (dE) (void)hipFree(dE);
@@ -1051,7 +1136,7 @@ hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double
 
 hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
   if (!hc || L < 1 || !u || !out) return HOM_EINVAL;
-  CellImpl* c = &hc->impl;
+  CellImpl* c = hc->impl;
   if (c->d != c->dd) return HOM_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipSetDevice(c->device);
@@ -1063,7 +1148,7 @@ hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
   do {
     if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
     if ((e = pipe_project_real(c, L, u, c->w64.x)) != hipSuccess) break;
-    if ((e = pipe_synth(c, L, c->w64.x, dE, false, out)) != hipSuccess) break;
+    if ((e = pipe_synth(c, c->w64, L, c->w64.x, dE, false, out)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (false);
   if (dE) (void)hipFree(dE);
@@ -1186,7 +1271,7 @@ extern "C" hom_status hom_profile_iteration(hom_cell* hc, hom_prec prec, int L, 
                                             double* ms, double* bytes) {
   if (!hc || L < 1 || reps < 1 || !ms || !bytes) return HOM_EINVAL;
   if (prec != HOM_FP64 && prec != HOM_MIXED) return HOM_EINVAL;
-  CellImpl* c = &hc->impl;
+  CellImpl* c = hc->impl;
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess) e = ensure_work(c, L, prec == HOM_MIXED);
@@ -1198,5 +1283,171 @@ extern "C" hom_status hom_profile_iteration(hom_cell* hc, hom_prec prec, int L, 
 
 extern "C" hom_status hom_set_specialized(int enable) {
   hom::set_static_enabled(enable != 0);
+  return HOM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time every variant of each pass of a cell's CG iteration
+// ---------------------------------------------------------------------------
+namespace hom {
+
+template <class T>
+static hipError_t autotune_impl(CellImpl* c, int L, int reps, double* best_us) {
+  Work<T>& w = work_of<T>(c);
+  hipError_t e;
+  std::vector<double> hE((size_t)L * c->dd, 0.0);
+  for (int l = 0; l < L; ++l) hE[(size_t)l * c->dd + (l % c->dd)] = 1.0;
+  double* dE = nullptr;
+  if ((e = hipMalloc(&dE, sizeof(double) * hE.size())) != hipSuccess) return e;
+  e = hipMemcpy(dE, hE.data(), sizeof(double) * hE.size(), hipMemcpyHostToDevice);
+  const int P = partial_slots(c);
+  const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
+  const int dd = c->dd, esz = (int)sizeof(cpx<T>);
+  const int Glast = (dd == 3) ? Q2 : Q1;
+  cpx<T>* Xrow = (dd == 3) ? w.X2 : w.X1;
+  if (e == hipSuccess) e = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
+  if (e == hipSuccess) e = pipe_rhs<T>(c, w, L, dE, nullptr);
+  if (e == hipSuccess) e = launch_cg_init(w.sc, w.part, P, project_tiles<T>(c), L, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipEvent_t ev0, ev1;
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  struct Stage {
+    TuneKey key;
+    int fft_len;
+    std::function<hipError_t()> run;
+  };
+  std::vector<Stage> stages;
+  stages.push_back({TuneKey{KK_EXPAND, esz, Q0, c->N[0], 0}, Q0,
+                    [&]() { return stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc); }});
+  if (dd == 3) {
+    stages.push_back({TuneKey{KK_PLAIN_INV, esz, Q1, c->N[1], 0}, Q1,
+                      [&]() { return stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc); }});
+    stages.push_back({TuneKey{KK_PLAIN_FWD, esz, Q1, c->N[1], 0}, Q1,
+                      [&]() { return stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc); }});
+  }
+  stages.push_back({TuneKey{KK_ROW, esz, Glast, c->N[dd - 1], dd}, Glast, [&]() {
+                      return stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, dd == 3 ? Q1 : 1, Glast,
+                                          nullptr, nullptr, nullptr, w.sc);
+                    }});
+  stages.push_back({TuneKey{KK_PROJECT, esz, Q0, c->N[0], 0}, Q0, [&]() {
+                      return stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr,
+                                              nullptr, nullptr, nullptr, w.part, w.sc, nullptr);
+                    }});
+  int si = 0;
+  for (Stage& st : stages) {
+    if (e != hipSuccess) break;
+    const DevPlan* pl = nullptr;
+    if ((e = get_dev_plan(st.fft_len, &pl)) != hipSuccess) break;
+    const int nvar = (int)static_variants(st.key.kind, st.key.esz, st.key.n, st.key.ntrial,
+                                          st.key.d, pl->p).size();
+    double best = 1e30;
+    int best_v = nvar > 0 ? 0 : -1;
+    for (int v = -1; v < nvar; ++v) {
+      set_choice(st.key, v);
+      hipError_t e2 = st.run();  // warm-up; fails when no generic shape fits
+      if (e2 != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      (void)hipEventRecord(ev0, c->stream);
+      for (int i = 0; i < reps && e2 == hipSuccess; ++i) e2 = st.run();
+      (void)hipEventRecord(ev1, c->stream);
+      if (e2 == hipSuccess) e2 = hipEventSynchronize(ev1);
+      float ms = 0.f;
+      if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e2 != hipSuccess) {
+        e = e2;
+        break;
+      }
+      const double us = 1e3 * ms / reps;
+      if (us < best) {
+        best = us;
+        best_v = v;
+      }
+    }
+    set_choice(st.key, best_v);
+    if (best_us && si < 5) best_us[si] = best;
+    ++si;
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(dE);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return e;
+}
+
+static std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+}  // namespace hom
+
+extern "C" hom_status hom_autotune(hom_cell* hc, hom_prec prec, int L, int reps, double* best_us) {
+  if (!hc || L < 1 || reps < 1 || (prec != HOM_FP64 && prec != HOM_MIXED)) return HOM_EINVAL;
+  CellImpl* c = hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = ensure_work(c, L, prec == HOM_MIXED);
+  if (e != hipSuccess) return dev_status(e);
+  if (best_us)
+    for (int i = 0; i < 5; ++i) best_us[i] = 0.0;
+  e = (prec == HOM_FP64) ? autotune_impl<double>(c, L, reps, best_us)
+                         : autotune_impl<float>(c, L, reps, best_us);
+  return dev_status(e);
+}
+
+extern "C" hom_status hom_tune_save(const char* path) {
+  if (!path) return HOM_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return HOM_EINVAL;
+  std::fprintf(f, "{\"arch\": \"%s\", \"choices\": [", hom::arch_name().c_str());
+  bool first = true;
+  for (const auto& kv : hom::all_choices()) {
+    const hom::TuneKey& k = kv.first;
+    std::fprintf(f, "%s\n  [%d, %d, %d, %d, %d, %d]", first ? "" : ",", k.kind, k.esz, k.n,
+                 k.ntrial, k.d, kv.second);
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  return HOM_OK;
+}
+
+extern "C" hom_status hom_tune_load(const char* path) {
+  if (!path) return HOM_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return HOM_EINVAL;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, n);
+  std::fclose(f);
+  const size_t a = s.find("\"arch\"");
+  const size_t q1 = (a == std::string::npos) ? a : s.find('"', s.find(':', a) + 1);
+  const size_t q2 = (q1 == std::string::npos) ? q1 : s.find('"', q1 + 1);
+  if (q2 == std::string::npos) return HOM_EINVAL;
+  if (s.substr(q1 + 1, q2 - q1 - 1) != hom::arch_name()) return HOM_EINVAL;  // tuned elsewhere
+  size_t p = s.find("\"choices\"");
+  if (p == std::string::npos) return HOM_EINVAL;
+  std::vector<long> v;
+  for (p = s.find('[', p); p < s.size(); ++p) {
+    if ((s[p] >= '0' && s[p] <= '9') || s[p] == '-') {
+      char* end = nullptr;
+      v.push_back(std::strtol(s.c_str() + p, &end, 10));
+      p = (size_t)(end - s.c_str()) - 1;
+    }
+  }
+  if (v.size() % 6) return HOM_EINVAL;
+  for (size_t i = 0; i < v.size(); i += 6)
+    hom::set_choice(hom::TuneKey{(int)v[i], (int)v[i + 1], (int)v[i + 2], (int)v[i + 3], (int)v[i + 4]},
+                    (int)v[i + 5]);
   return HOM_OK;
 }

@@ -20,7 +20,8 @@ ISO, DIAG, FULLSYM = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "hom_options_default", "hom_create_cell", "hom_solve", "hom_apply", "hom_project",
-    "hom_profile_iteration", "hom_set_specialized", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
+    "hom_profile_iteration", "hom_set_specialized", "hom_autotune", "hom_tune_save",
+    "hom_tune_load", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
     "hom_server_create", "hom_server_submit", "hom_server_poll", "hom_server_times",
     "hom_server_destroy",
 ]
@@ -71,6 +72,9 @@ def lib():
         L.hom_project.argtypes = [vp, ip, vp, vp]
         L.hom_profile_iteration.argtypes = [vp, ip, ip, ip, dp, dp]
         L.hom_set_specialized.argtypes = [ip]
+        L.hom_autotune.argtypes = [vp, ip, ip, ip, dp]
+        L.hom_tune_save.argtypes = [ctypes.c_char_p]
+        L.hom_tune_load.argtypes = [ctypes.c_char_p]
         L.hom_destroy_cell.argtypes = [vp]
         L.hom_destroy_cell.restype = None
         L.hom_cell_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
@@ -103,6 +107,15 @@ def _current_stream():
 def set_specialized(enable: bool) -> None:
     """Use (True, default) or bypass (False) the compile-time specialised kernels."""
     _check(lib().hom_set_specialized(1 if enable else 0), "hom_set_specialized")
+
+
+def tune_save(path: str) -> None:
+    _check(lib().hom_tune_save(path.encode()), "hom_tune_save")
+
+
+def tune_load(path: str) -> bool:
+    """Load tuned choices; False if the file is missing or from another GPU."""
+    return lib().hom_tune_load(path.encode()) == 0
 
 
 def make_options(scheme=GANI, prec=FP64, Y=None, max_iter=10000, max_outer=30, inner_tol=1e-4,
@@ -206,6 +219,12 @@ class Cell:
         _check(lib().hom_project(self._h, u.shape[0], ctypes.c_void_p(u.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr())), "hom_project")
         return out
+
+    def autotune(self, prec=FP64, L=1, reps=10):
+        """Pick the fastest kernel variant of every pass (see hom_autotune)."""
+        best = np.zeros(5)
+        _check(lib().hom_autotune(self._h, prec, L, reps, _dptr(best)), "hom_autotune")
+        return best
 
     def profile(self, prec=FP64, L=1, reps=20):
         ms = np.zeros(8)
