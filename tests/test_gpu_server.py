@@ -77,8 +77,8 @@ def test_served_equals_alone_and_oracle(hom, oracle):
 def test_out_of_order_completion(hom):
     """Small requests submitted after a large one are admitted into their own
     class at once and finish first; results equal the solves alone."""
-    big = hom.Cell(hi.random_spd_field((63, 63, 63), 0, seed=1, contrast=100.0), (63, 63, 63),
-                   prec=hom.MIXED)
+    big = hom.Cell(hi.bernoulli_majority((127, 127, 127), 0.4, 3, 1000.0, 1.0, seed=1),
+                   (127, 127, 127), prec=hom.MIXED)
     small = [hom.Cell(hi.random_spd_field((15, 15), 0, seed=10 + i, contrast=10.0), (15, 15),
                       prec=hom.MIXED) for i in range(4)]
     ref_big = big.solve(np.eye(3), tol=1e-7)["W"]
