@@ -1,6 +1,6 @@
 """Benchmark: cell solves of the FFT-Galerkin cell problem on one MI355X.
 
-Workload (default): 2-D random two-phase pixel microstructure, N = 1023 x 1023
+Default workload: 2-D random two-phase pixel microstructure, N = 1023 x 1023
 (Bernoulli(0.4) pixels smoothed by 3 majority passes, conductivities 100 / 1,
 seed 2), load cases E = e1, e2 solved together, tol 1e-6, FP32-FFT inner CG
 with FP64 refinement.  One step = create the cell (validate + upload A) and
@@ -9,9 +9,12 @@ solve both load cases to A_H.
 Printed (one JSON line): voxel-iters/s as `value` (|N| x load cases x CG
 iterations / s), operator applies/s, cell solves/s with p50/p99 step latency,
 A_H error of the mixed path against the FP64 GPU path at tol 1e-10 (itself
-parity-tested against the FP64 oracle), the roofline of the dominant kernel
-(HIP-event timing of one CG iteration, algorithmic bytes) and the FP64 CPU
-oracle timed on a bounded sample on this host.
+parity-tested against the FP64 oracle), the FP64 path's own solve time at the
+same tolerance, the roofline of the dominant kernel (HIP events around each
+kernel of the CG iteration, algorithmic bytes) and the FP64 CPU oracle timed
+on a bounded sample on this host.  --extra adds the 3-D workloads (spheres
+255^3, lognormal Ga 127^3 on 253^3); --serving N adds N requests of the
+Poisson request stream through the continuous-batching server.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import json
 import os
 import statistics
 import sys
+import threading
 import time
 
 import numpy as np
@@ -39,13 +43,20 @@ def parse():
     ap.add_argument("--n", type=int, default=1023, help="grid size per axis (odd)")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-ref", action="store_true", help="skip the FP64 reference solve")
+    ap.add_argument("--no-ref", action="store_true", help="skip the FP64 reference solves")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tune", choices=["cache", "run", "off"], default="cache",
                     help="kernel variants: committed tuning cache (tune if absent), "
                          "re-tune now, or first registered variant")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+    ap.add_argument("--extra", action="store_true", help="also measure the 3-D workloads")
+    ap.add_argument("--serving", type=int, default=0, help="requests of the serving stream")
+    ap.add_argument("--serving-rate", type=float, default=500.0)
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(w, budget_s: float):
@@ -54,8 +65,8 @@ def cpu_baseline(w, budget_s: float):
     budget_s, scaled to voxel-iters/s."""
     from oracle import oracle
     c = oracle.Cell(w.A, w.N)
-    u = c.apply_G(np.stack([np.full(w.N, 1.0), np.zeros(w.N)]) +
-                  np.stack([w.A / w.A.max(), w.A / w.A.max()]))
+    d = len(w.N)
+    u = c.apply_G(np.stack([w.A / w.A.max()] * d))
     n_apply = 0
     t0 = time.perf_counter()
     while True:
@@ -66,10 +77,149 @@ def cpu_baseline(w, budget_s: float):
     dt = time.perf_counter() - t0
     npts = int(np.prod(w.N))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    shape = "x".join(str(n) for n in w.N)
     return {"value": npts * n_apply / dt, "unit": "voxel-iters/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{n_apply} FP64 operator applies (G A, naive DFT) on the {w.N[0]}x{w.N[1]} "
-                      f"cell, one load case, {dt:.1f} s"}
+            "sample": f"{n_apply} FP64 operator applies (G A, naive DFT) on the {shape} cell, "
+                      f"one load case, {dt:.1f} s"}
+
+
+def tune(hom, w, prec, L, mode, out_path):
+    cache = os.path.join(ROOT, "paper_1311_0089_amd", "tune_cache.json")
+    if mode == "off":
+        return "off"
+    if mode == "cache" and hom.tune_load(cache):
+        return "cache"
+    tc = hom.Cell(w.A, w.N, kind=w.kind, scheme=w.scheme, prec=prec)
+    for p in ((hom.MIXED, hom.FP64) if prec == hom.MIXED else (hom.FP64,)):
+        best = tc.autotune(prec=p, L=L, reps=10)
+        log(f"autotune {w.name} prec={p}: best pass times us {np.round(best, 1).tolist()}")
+    tc.close()
+    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    hom.tune_save(out_path)
+    return "run"
+
+
+def measure(hom, w, prec, steps, warmup, ref=True):
+    """Time create+solve steps of workload w; profile one CG iteration."""
+    L = w.E.shape[0]
+
+    def step():
+        cell = hom.Cell(w.A, w.N, kind=w.kind, scheme=w.scheme, prec=prec)
+        res = cell.solve(w.E, tol=w.tol)
+        cell.close()
+        return res
+
+    import torch
+    for i in range(warmup):
+        r = step()
+        log(f"{w.name} warmup {i}: iters {r['info']['iters_inner']}/{r['info']['iters_outer']} "
+            f"solve {r['info']['seconds'] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        r = step()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    it_in, it_out = r["info"]["iters_inner"], r["info"]["iters_outer"]
+    W = r["W"]
+    npts = int(np.prod(w.N))
+    out = {"ms_per_step": dt * 1e3, "iters_inner": it_in, "iters_outer": it_out,
+           "voxel_iters_per_s": npts * L * it_in / dt,
+           "operator_applies_per_s": L * (1 + it_in + it_out + 1) / dt,
+           "cell_solves_per_s": 1.0 / dt,
+           "latency_ms": {"p50": statistics.median(lat) * 1e3,
+                          "p99": float(np.percentile(np.array(lat) * 1e3, 99))},
+           "A_H": W.tolist(), "rel_resid_true": r["info"]["rel_resid_true"],
+           "status": r["status"]}
+    if ref:
+        # the FP64 path: at the same tolerance (timed) and at 1e-10 (the A_H reference)
+        c64 = hom.Cell(w.A, w.N, kind=w.kind, scheme=w.scheme, prec=hom.FP64)
+        c64.solve(w.E, tol=w.tol)
+        t1 = time.perf_counter()
+        r64 = c64.solve(w.E, tol=w.tol)
+        out["fp64_same_tol_ms"] = (time.perf_counter() - t1) * 1e3
+        out["fp64_same_tol_iters"] = r64["info"]["iters_inner"]
+        out["fp64_same_tol_A_H_rel_err"] = float(np.abs(r64["W"] - W).max() / np.abs(W).max())
+        rr = c64.solve(w.E, tol=1e-10)
+        c64.close()
+        out["A_H_rel_err_vs_fp64_1e-10"] = float(np.abs(W - rr["W"]).max() / np.abs(rr["W"]).max())
+        out["fp64_same_tol_A_H_rel_err"] = float(np.abs(r64["W"] - rr["W"]).max()
+                                                 / np.abs(rr["W"]).max())
+    cell = hom.Cell(w.A, w.N, kind=w.kind, scheme=w.scheme, prec=prec)
+    prof = cell.profile(prec=prec, L=L, reps=20)
+    cell.close()
+    kernels = {k: v for k, v in prof.items() if k not in ("iteration", "scalars") and v["ms"] > 0}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    achieved = kernels[dom]["bytes"] / (kernels[dom]["ms"] * 1e-3) / 1e9
+    out["iteration_profile_us"] = {k: round(v["ms"] * 1e3, 2) for k, v in prof.items()}
+    out["iteration_GBps"] = prof["iteration"]["bytes"] / (prof["iteration"]["ms"] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    log(f"{w.name}: {dt * 1e3:.2f} ms/step, iters {it_in}/{it_out}, profile " +
+        ", ".join(f"{k} {v['ms'] * 1e3:.1f}us" for k, v in prof.items()))
+    return out
+
+
+def serving(hom, n_req, rate, budget):
+    """Submit n_req requests of the seeded stream at their Poisson arrival
+    times; report served rate and p50/p99 latency (submit -> done)."""
+    import hom_inputs as hi
+    reqs = hi.serving_stream(n_req, rate=rate, seed=5, geometry_pool=16)
+    kinds = {}
+    for r in reqs:
+        kinds[(r.d, r.N[0])] = kinds.get((r.d, r.N[0]), 0) + 1
+    # geometries come from a pool of 16 per (d, N, type); fields are built before
+    # the arrivals start (the contrast is per request)
+    cache = {}
+    fields = []
+    for r in reqs:
+        key = (r.kind_micro, r.N, r.geometry_seed, r.count)
+        if key not in cache:
+            cache[key] = r.field() > 1.0
+        fields.append(np.where(cache[key], r.contrast, 1.0))
+    log(f"serving: {len(reqs)} requests, {len(cache)} distinct geometries")
+    srv = hom.Server(hbm_budget_bytes=budget, prec=hom.MIXED, check_every=8)
+    cells = [None] * len(reqs)
+    tickets = {}
+    done = {}
+    errors = []
+
+    def poller():
+        while len(done) < len(reqs) and not errors:
+            for i, (t, L, d) in list(tickets.items()):
+                if i in done:
+                    continue
+                res = srv.poll(t, L, d)
+                if res is not None:
+                    done[i] = res
+                    cells[i] = None
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        while time.perf_counter() - t0 < r.arrival:
+            time.sleep(0.0002)
+        c = hom.Cell(fields[i], r.N, prec=hom.MIXED)
+        fields[i] = None
+        cells[i] = c
+        tickets[i] = (srv.submit(c, r.E, tol=r.tol), r.E.shape[0], r.d)
+    th.join(timeout=600)
+    t_end = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([(done[i]["times"][2] - done[i]["times"][0]) * 1e3 for i in done])
+    ok = sum(1 for v in done.values() if v["status"] == 0)
+    return {"requests": len(reqs), "completed": len(done), "ok": ok,
+            "offered_rate_per_s": len(reqs) / reqs[-1].arrival,
+            "served_solves_per_s": len(done) / t_end, "wall_s": t_end,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "mix": {f"{d}D-{n}": c for (d, n), c in sorted(kinds.items())},
+            "budget_bytes": budget}
 
 
 def main():
@@ -88,109 +238,49 @@ def main():
     n = args.n
     w = hi.cfg2_pixels((n, n), seed=2)
     prec = hom.MIXED if args.prec == "mixed" else hom.FP64
-    E = np.eye(2)
-    L = 2
-    tol = w.tol
-    print(f"[bench] workload {w.name} vf={w.info['vf']:.3f} prec={args.prec} tol={tol}",
-          file=sys.stderr, flush=True)
-
-    cache = os.path.join(ROOT, "paper_1311_0089_amd", "tune_cache.json")
-    tuned = "off"
-    if args.tune != "off":
-        if args.tune == "cache" and hom.tune_load(cache):
-            tuned = "cache"
-        else:
-            tc = hom.Cell(w.A, w.N, prec=prec)
-            for p in ((hom.MIXED, hom.FP64) if prec == hom.MIXED else (hom.FP64,)):
-                best = tc.autotune(prec=p, L=L, reps=10)
-                print(f"[bench] autotune prec={p}: best pass times us {np.round(best, 1).tolist()}",
-                      file=sys.stderr, flush=True)
-            tc.close()
-            os.makedirs(os.path.dirname(args.tune_out), exist_ok=True)
-            hom.tune_save(args.tune_out)
-            tuned = "run"
-
-    def step():
-        cell = hom.Cell(w.A, w.N, prec=prec)
-        res = cell.solve(E, tol=tol)
-        cell.close()
-        return res
-
-    for i in range(args.warmup):
-        r = step()
-        print(f"[bench] warmup {i}: iters {r['info']['iters_inner']}/{r['info']['iters_outer']} "
-              f"{r['info']['seconds']*1e3:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    lat = []
-    iters_in = iters_out = 0
-    W = None
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        r = step()
-        lat.append(time.perf_counter() - ts)
-        iters_in = r["info"]["iters_inner"]
-        iters_out = r["info"]["iters_outer"]
-        W = r["W"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    npts = n * n
-    voxel_iters = npts * L * iters_in
-    # operator applies per step: RHS + inner CG + one FP64 residual per refinement step + true residual
-    applies = L * (1 + iters_in + iters_out + 1)
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, iters {iters_in}/{iters_out}",
-          file=sys.stderr, flush=True)
-
-    # A_H accuracy of this path against the FP64 GPU path at a tight tolerance
-    ah_err = None
-    if not args.no_ref:
-        ref = hom.Cell(w.A, w.N, prec=hom.FP64)
-        r64 = ref.solve(E, tol=1e-10)
-        ah_err = float(np.abs(W - r64["W"]).max() / np.abs(r64["W"]).max())
-        ref.close()
-
-    # roofline of the dominant kernel (HIP events on the cell's stream)
-    cell = hom.Cell(w.A, w.N, prec=prec)
-    prof = cell.profile(prec=prec, L=L, reps=20)
-    cell.close()
-    kernels = {k: v for k, v in prof.items() if k not in ("iteration", "scalars") and v["ms"] > 0}
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    achieved = kernels[dom]["bytes"] / (kernels[dom]["ms"] * 1e-3) / 1e9
-    it_ms = prof["iteration"]["ms"]
-    it_gbs = prof["iteration"]["bytes"] / (it_ms * 1e-3) / 1e9
-    print(f"[bench] profile: " + ", ".join(f"{k} {v['ms']*1e3:.1f}us" for k, v in prof.items()),
-          file=sys.stderr, flush=True)
-
+    log(f"workload {w.name} vf={w.info['vf']:.3f} prec={args.prec} tol={w.tol}")
+    tuned = tune(hom, w, prec, w.E.shape[0], args.tune, args.tune_out)
+    m = measure(hom, w, prec, args.steps, args.warmup, ref=not args.no_ref)
     out = {
         "metric": METRIC,
-        "value": voxel_iters / (dt / args.steps),
+        "value": m["voxel_iters_per_s"],
         "unit": "voxel-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if prec == hom.MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": [n, n], "load_cases": L, "tol": tol,
-                   "contrast": 100.0, "volume_fraction": round(w.info["vf"], 4),
+        "config": {"workload": w.name, "N": [n, n], "load_cases": int(w.E.shape[0]),
+                   "tol": w.tol, "contrast": 100.0, "volume_fraction": round(w.info["vf"], 4),
                    "scheme": "GaNi", "precision": args.prec},
-        "operator_applies_per_s": applies / (dt / args.steps),
-        "cell_solves_per_s": 1.0 / (dt / args.steps),
-        "latency_ms": {"p50": statistics.median(lat) * 1e3,
-                       "p99": float(np.percentile(np.array(lat) * 1e3, 99))},
-        "cg_iterations": {"inner": iters_in, "outer": iters_out},
-        "A_H": W.tolist(),
-        "A_H_rel_err_vs_fp64": ah_err,
-        "iteration_profile_us": {k: round(v["ms"] * 1e3, 2) for k, v in prof.items()},
-        "iteration_GBps": it_gbs,
+        "operator_applies_per_s": m["operator_applies_per_s"],
+        "cell_solves_per_s": m["cell_solves_per_s"],
+        "latency_ms": m["latency_ms"],
+        "cg_iterations": {"inner": m["iters_inner"], "outer": m["iters_outer"]},
+        "A_H": m["A_H"],
+        "A_H_rel_err_vs_fp64": m.get("A_H_rel_err_vs_fp64_1e-10"),
+        "fp64_path": {k: m[k] for k in m if k.startswith("fp64_")},
+        "iteration_profile_us": m["iteration_profile_us"],
+        "iteration_GBps": m["iteration_GBps"],
         "kernel_tuning": tuned,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": m["roofline"],
     }
+    if args.extra:
+        extra = {}
+        for make in (hi.cfg3_spheres, hi.cfg4_lognormal):
+            wx = make()
+            t = tune(hom, wx, hom.MIXED, wx.E.shape[0], args.tune, args.tune_out)
+            mx = measure(hom, wx, hom.MIXED, max(2, args.steps // 3), 1, ref=not args.no_ref)
+            mx["kernel_tuning"] = t
+            mx["contrast"] = wx.info.get("contrast")
+            extra[wx.name] = mx
+        out["extra_workloads"] = extra
+    if args.serving:
+        out["serving"] = serving(hom, args.serving, args.serving_rate, budget=64 << 30)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -93,6 +93,18 @@ def square_inclusion(N, half_width=0.25, a_in=10.0, a_out=1.0, Y=None):
     return np.where(inside, a_in, a_out).astype(np.float64)
 
 
+def _neighbour_sum(ph):
+    """Periodic sum over the 3^d Moore neighbourhood (centre included)."""
+    try:
+        from scipy.ndimage import convolve
+        return convolve(ph, np.ones((3,) * ph.ndim, dtype=ph.dtype), mode="wrap")
+    except ImportError:  # pragma: no cover - scipy is part of the image
+        s = np.zeros_like(ph)
+        for shift in np.ndindex(*(3,) * ph.ndim):
+            s += np.roll(ph, tuple(int(t) - 1 for t in shift), axis=tuple(range(ph.ndim)))
+        return s
+
+
 def bernoulli_majority(N, p=0.4, passes=3, a1=100.0, a0=1.0, seed=2):
     """Two-phase pixel field: phase 1 with probability p per pixel (uniform < p,
     FFT-order row-major draws), then ``passes`` synchronous periodic 3^d Moore
@@ -100,13 +112,9 @@ def bernoulli_majority(N, p=0.4, passes=3, a1=100.0, a0=1.0, seed=2):
     included, are phase 1).  Returns the conductivity field."""
     N = tuple(N)
     ph = (uniform(seed, int(np.prod(N))) < p).reshape(N).astype(np.int32)
-    d = len(N)
-    k = 3 ** d
+    k = 3 ** len(N)
     for _ in range(passes):
-        s = np.zeros(N, dtype=np.int32)
-        for shift in np.ndindex(*(3,) * d):
-            s += np.roll(ph, tuple(int(t) - 1 for t in shift), axis=tuple(range(d)))
-        ph = (2 * s > k).astype(np.int32)
+        ph = (2 * _neighbour_sum(ph) > k).astype(np.int32)
     return np.where(ph == 1, a1, a0).astype(np.float64)
 
 
@@ -142,19 +150,31 @@ def rsa_centres(d, count, r, seed, max_draws=10_000_000):
 def inclusions(N, count, r, a_in, a_out=1.0, seed=3):
     """Non-overlapping discs/spheres of radius r (cell of unit size), centres
     by RSA; a grid point is inside when its minimum-image distance to a centre
-    is < r."""
+    is < r.  Only the grid points in each centre's bounding box are tested."""
     N = tuple(N)
     d = len(N)
     C = rsa_centres(d, count, r, seed)
-    X = mesh(N)
+    xs = coords(N)
     inside = np.zeros(N, dtype=bool)
     for c in C:
-        dist2 = np.zeros(N)
+        idx, dxs = [], []
         for a in range(d):
-            dx = X[a] - (c[a] - 0.5)       # centres drawn in [0,1) -> cell [-1/2, 1/2)
+            n = N[a]
+            h = 1.0 / n
+            cx = c[a] - 0.5                       # centres drawn in [0,1) -> cell [-1/2, 1/2)
+            k = np.arange(int(np.floor((cx - r) / h)) - 1, int(np.ceil((cx + r) / h)) + 2)
+            i = np.unique(np.mod(k, n))
+            dx = xs[a][i] - cx
             dx -= np.round(dx)
-            dist2 += dx * dx
-        inside |= dist2 < r * r
+            idx.append(i)
+            dxs.append(dx)
+        dist2 = np.zeros([len(i) for i in idx])
+        for a in range(d):
+            shape = [1] * d
+            shape[a] = -1
+            dist2 = dist2 + (dxs[a] * dxs[a]).reshape(shape)
+        sub = inside[np.ix_(*idx)]
+        inside[np.ix_(*idx)] = sub | (dist2 < r * r)
     return np.where(inside, a_in, a_out).astype(np.float64)
 
 
@@ -273,20 +293,30 @@ class Request:
     arrival: float
     d: int
     N: tuple
-    A: np.ndarray
     E: np.ndarray
     tol: float
     contrast: float
-    kind_micro: str
+    kind_micro: str          # "inclusions" or "pixels"
+    seed: int
+    count: int               # inclusions: number of discs/spheres
+    geometry_seed: int       # seed of the geometry actually drawn (see serving_stream)
+
+    def field(self) -> np.ndarray:
+        """Isotropic two-phase conductivity field of this request."""
+        if self.kind_micro == "inclusions":
+            return inclusions(self.N, self.count, 0.06, self.contrast, 1.0, seed=self.geometry_seed)
+        return bernoulli_majority(self.N, 0.4, 3, self.contrast, 1.0, seed=self.geometry_seed)
 
 
 def serving_stream(n_requests=10_000, rate=500.0, seed=5, sizes2=(63, 127, 255),
-                   sizes3=(31, 63, 127), tol=1e-6, materialize=True):
+                   sizes3=(31, 63, 127), tol=1e-6, geometry_pool=0):
     """Seeded request stream: Poisson arrivals (mean rate), d in {2,3} with
     p = 1/2, N uniform from the size list, half RSA inclusions (count U{5..40}
     in 2-D, U{10..60} in 3-D, r = 0.06), half Bernoulli pixels (p = 0.4, 3
-    majority passes), contrast 10^(1+3u), L = 1 + floor(u d) load cases e_1..e_L.
-    Per-request randomness uses seed_i = splitmix(seed, i)."""
+    majority passes), contrast 10^(1+3u), L = 1 + floor(u d) load cases
+    e_1..e_L.  Request i draws from seed_i = splitmix(seed, i).  With
+    geometry_pool > 0 the geometry (not the contrast) is taken from a pool of
+    that many seeds per (d, N, type), so fields can be cached."""
     t = 0.0
     out = []
     head = uniform(seed, n_requests)
@@ -297,18 +327,13 @@ def serving_stream(n_requests=10_000, rate=500.0, seed=5, sizes2=(63, 127, 255),
         d = 2 if u[0] < 0.5 else 3
         sizes = sizes2 if d == 2 else sizes3
         n = sizes[min(int(u[1] * len(sizes)), len(sizes) - 1)]
-        N = (n,) * d
         contrast = 10.0 ** (1.0 + 3.0 * u[2])
         L = 1 + min(int(u[3] * d), d - 1)
         incl = u[4] < 0.5
-        A = None
-        if materialize:
-            if incl:
-                lo, hi = (5, 40) if d == 2 else (10, 60)
-                cnt = lo + min(int(u[5] * (hi - lo + 1)), hi - lo)
-                A = inclusions(N, cnt, 0.06, contrast, 1.0, seed=si)
-            else:
-                A = bernoulli_majority(N, 0.4, 3, contrast, 1.0, seed=si)
-        out.append(Request(i, t, d, N, A, np.eye(d)[:L], tol, contrast,
-                           "inclusions" if incl else "pixels"))
+        lo, hi = (5, 40) if d == 2 else (10, 60)
+        cnt = lo + min(int(u[5] * (hi - lo + 1)), hi - lo)
+        gseed = si if geometry_pool <= 0 else splitmix_one(seed + 1000 * d + n,
+                                                            1 + int(u[6] * geometry_pool))
+        out.append(Request(i, t, d, (n,) * d, np.eye(d)[:L], tol, contrast,
+                           "inclusions" if incl else "pixels", si, cnt, gseed))
     return out

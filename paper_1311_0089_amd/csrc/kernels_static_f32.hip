@@ -7,13 +7,17 @@ using T = float;
 // columns: plan, trial length, W, workgroup size
 RegCol<T, P1023, 1023, 4, 256> c1023;
 RegCol<T, P1023, 1023, 8, 512> c1023w;
+RegCol<T, P1023, 1023, 2, 128> c1023n2;
+RegCol<T, P1023, 1023, 1, 64> c1023n1;
 RegCol<T, P255, 255, 16, 256> c255;
 RegCol<T, P255, 255, 8, 256> c255n;
+RegCol<T, P255, 255, 4, 128> c255n4;
 RegCol<T, P127, 127, 16, 256> c127;
 RegCol<T, P63, 63, 16, 256> c63;
 RegCol<T, P31, 31, 16, 256> c31;
 RegCol<T, P15, 15, 16, 256> c15;
 RegCol<T, P253, 127, 16, 256> c253;
+RegCol<T, P253, 127, 8, 256> c253n;
 RegCol<T, P125, 63, 16, 256> c125;
 RegCol<T, P61, 31, 16, 256> c61;
 RegCol<T, P29, 15, 16, 256> c29;
@@ -21,9 +25,11 @@ RegCol<T, P509, 255, 8, 512> c509;
 // rows: plan, trial length, components, row pairs, workgroup size
 RegRow<T, P1023, 1023, 2, 2, 256> r1023_2;
 RegRow<T, P1023, 1023, 2, 4, 512> r1023_2w;
+RegRow<T, P1023, 1023, 2, 1, 128> r1023_2n;
 RegRow<T, P1023, 1023, 3, 2, 512> r1023_3;
 RegRow<T, P255, 255, 2, 8, 256> r255_2;
 RegRow<T, P255, 255, 3, 8, 512> r255_3;
+RegRow<T, P255, 255, 3, 4, 256> r255_3n;
 RegRow<T, P127, 127, 2, 8, 256> r127_2;
 RegRow<T, P127, 127, 3, 8, 512> r127_3;
 RegRow<T, P63, 63, 2, 8, 256> r63_2;
@@ -34,6 +40,7 @@ RegRow<T, P15, 15, 2, 8, 256> r15_2;
 RegRow<T, P15, 15, 3, 8, 256> r15_3;
 RegRow<T, P253, 127, 2, 8, 256> r253_2;
 RegRow<T, P253, 127, 3, 8, 512> r253_3;
+RegRow<T, P253, 127, 3, 4, 256> r253_3n;
 RegRow<T, P125, 63, 2, 8, 256> r125_2;
 RegRow<T, P125, 63, 3, 8, 256> r125_3;
 RegRow<T, P61, 31, 2, 8, 256> r61_2;

@@ -6,18 +6,22 @@ namespace {
 using T = double;
 RegCol<T, P1023, 1023, 2, 256> c1023;
 RegCol<T, P1023, 1023, 4, 512> c1023w;
+RegCol<T, P1023, 1023, 1, 128> c1023n1;
 RegCol<T, P255, 255, 8, 256> c255;
+RegCol<T, P255, 255, 4, 256> c255n;
 RegCol<T, P127, 127, 8, 256> c127;
 RegCol<T, P63, 63, 16, 256> c63;
 RegCol<T, P31, 31, 16, 256> c31;
 RegCol<T, P15, 15, 16, 256> c15;
 RegCol<T, P253, 127, 8, 256> c253;
+RegCol<T, P253, 127, 4, 256> c253n;
 RegCol<T, P125, 63, 16, 256> c125;
 RegCol<T, P61, 31, 16, 256> c61;
 RegCol<T, P29, 15, 16, 256> c29;
 RegCol<T, P509, 255, 4, 512> c509;
 RegRow<T, P1023, 1023, 2, 1, 256> r1023_2;
 RegRow<T, P1023, 1023, 2, 2, 512> r1023_2w;
+RegRow<T, P1023, 1023, 2, 1, 128> r1023_2n;
 RegRow<T, P1023, 1023, 3, 1, 256> r1023_3;
 RegRow<T, P255, 255, 2, 4, 256> r255_2;
 RegRow<T, P255, 255, 3, 4, 256> r255_3;

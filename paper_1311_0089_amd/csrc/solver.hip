@@ -1185,53 +1185,38 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     if (e2 == hipSuccess) e2 = launch_cg_init(w.sc, w.part, P, tiles, L, c->stream);
     return e2;
   };
-  hipEvent_t ev0, ev1;
-  (void)hipEventCreate(&ev0);
-  (void)hipEventCreate(&ev1);
-  auto timed = [&](int slot, auto&& fn) -> hipError_t {
-    hipError_t e2 = reset();
-    if (e2 == hipSuccess) e2 = fn();  // warm-up
-    if (e2 != hipSuccess) return e2;
-    (void)hipEventRecord(ev0, c->stream);
-    for (int i = 0; i < reps && e2 == hipSuccess; ++i) e2 = fn();
-    (void)hipEventRecord(ev1, c->stream);
-    if (e2 == hipSuccess) e2 = hipEventSynchronize(ev1);
-    float t = 0.f;
-    if (e2 == hipSuccess) e2 = hipEventElapsedTime(&t, ev0, ev1);
-    ms[slot] = (double)t / reps;
-    return e2;
-  };
   for (int i = 0; i < 8; ++i) ms[i] = bytes[i] = 0.0;
   const double esz = sizeof(cpx<T>), Ts = sizeof(T);
   const long inner = inner0(c);
   const long rows = (c->dd == 3) ? (long)Q0 * Q1 : Q0;
   const double S = (double)c->S;
   cpx<T>* Xrow = (c->dd == 3) ? w.X2 : w.X1;
-  do {
-    e = timed(0, [&]() { return stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc); });
-    if (e != hipSuccess) break;
-    bytes[0] = L * (3.0 * S * esz + (double)c->dd * Q0 * inner * esz);
-    if (c->dd == 3) {
-      e = timed(1, [&]() { return stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc); });
-      if (e != hipSuccess) break;
-      bytes[1] = L * (double)c->dd * Q0 * c->H * esz * (c->N[1] + Q1);
-      e = timed(3, [&]() { return stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc); });
-      if (e != hipSuccess) break;
-      bytes[3] = bytes[1];
-    }
-    e = timed(2, [&]() {
-      return stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, c->dd == 3 ? Q1 : 1,
-                          c->dd == 3 ? Q2 : Q1, nullptr, nullptr, nullptr, w.sc);
-    });
-    if (e != hipSuccess) break;
-    bytes[2] = L * 2.0 * c->dd * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
-    e = timed(4, [&]() {
-      return stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr, nullptr, nullptr,
-                              nullptr, w.part, w.sc, nullptr);
-    });
-    if (e != hipSuccess) break;
-    bytes[4] = L * ((double)c->dd * Q0 * inner * esz + 2.0 * S * esz);
-    e = timed(5, [&]() {
+  // events around every kernel of `reps` consecutive CG iterations, so each
+  // kernel is timed in the context it runs in (caches as left by its predecessor)
+  const int NEV = 9;
+  std::vector<hipEvent_t> ev((size_t)reps * NEV);
+  for (auto& x : ev) (void)hipEventCreate(&x);
+  e = reset();
+  for (int it = 0; it < reps && e == hipSuccess; ++it) {
+    hipEvent_t* E = ev.data() + (size_t)it * NEV;
+    (void)hipEventRecord(E[0], c->stream);
+    e = stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc);
+    (void)hipEventRecord(E[1], c->stream);
+    if (e == hipSuccess && c->dd == 3) e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc);
+    (void)hipEventRecord(E[2], c->stream);
+    if (e == hipSuccess)
+      e = stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, c->dd == 3 ? Q1 : 1, c->dd == 3 ? Q2 : Q1,
+                       nullptr, nullptr, nullptr, w.sc);
+    (void)hipEventRecord(E[3], c->stream);
+    if (e == hipSuccess && c->dd == 3) e = stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc);
+    (void)hipEventRecord(E[4], c->stream);
+    if (e == hipSuccess)
+      e = stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr, nullptr, nullptr,
+                           nullptr, w.part, w.sc, nullptr);
+    (void)hipEventRecord(E[5], c->stream);
+    if (e == hipSuccess) e = launch_cg_alpha(w.sc, w.part, P, tiles, L, c->stream);
+    (void)hipEventRecord(E[6], c->stream);
+    if (e == hipSuccess) {
       CgUpdateArgs<T> u{};
       u.x = w.x;
       u.r = w.r;
@@ -1243,23 +1228,39 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
       u.partials = w.part2;
       u.P = P;
       u.sc = w.sc;
-      return launch_cg_update<T>(u, L, ub, c->stream);
-    });
-    if (e != hipSuccess) break;
-    bytes[5] = L * 6.0 * S * esz;
-    e = timed(6, [&]() {
-      hipError_t e2 = launch_cg_alpha(w.sc, w.part, P, tiles, L, c->stream);
-      if (e2 == hipSuccess) e2 = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
-      if (e2 == hipSuccess) e2 = launch_cg_beta(w.sc, w.part2, P, ub, L, c->stream);
-      return e2;
-    });
-    if (e != hipSuccess) break;
-    e = timed(7, [&]() { return cg_body<T>(c, w, L, 1); });
-    if (e != hipSuccess) break;
-    for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
-  } while (false);
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
+      e = launch_cg_update<T>(u, L, ub, c->stream);
+    }
+    (void)hipEventRecord(E[7], c->stream);
+    if (e == hipSuccess) e = launch_cg_beta(w.sc, w.part2, P, ub, L, c->stream);
+    (void)hipEventRecord(E[8], c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  // slots: 0 expand, 1 axis-1 inverse, 2 row, 3 axis-1 forward, 4 project,
+  // 5 update, 6 alpha + beta, 7 whole iteration
+  const int map_from[8] = {0, 1, 2, 3, 4, 6, -1, 0};
+  for (int it = 0; it < reps && e == hipSuccess; ++it) {
+    hipEvent_t* E = ev.data() + (size_t)it * NEV;
+    float t = 0.f;
+    for (int k = 0; k < 6; ++k) {
+      const int a = map_from[k];
+      if (hipEventElapsedTime(&t, E[a], E[a + 1]) == hipSuccess) ms[k] += t;
+    }
+    if (hipEventElapsedTime(&t, E[5], E[6]) == hipSuccess) ms[6] += t;
+    if (hipEventElapsedTime(&t, E[7], E[8]) == hipSuccess) ms[6] += t;
+    if (hipEventElapsedTime(&t, E[0], E[8]) == hipSuccess) ms[7] += t;
+  }
+  for (int k = 0; k < 8; ++k) ms[k] /= reps;
+  if (c->dd != 3) ms[1] = ms[3] = 0.0;
+  bytes[0] = L * (3.0 * S * esz + (double)c->dd * Q0 * inner * esz);
+  if (c->dd == 3) {
+    bytes[1] = L * (double)c->dd * Q0 * c->H * esz * (c->N[1] + Q1);
+    bytes[3] = bytes[1];
+  }
+  bytes[2] = L * 2.0 * c->dd * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
+  bytes[4] = L * ((double)c->dd * Q0 * inner * esz + 2.0 * S * esz);
+  bytes[5] = L * 6.0 * S * esz;
+  for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
+  for (auto& x : ev) (void)hipEventDestroy(x);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(dE);
   return e;
