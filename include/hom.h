@@ -57,9 +57,12 @@ typedef enum {
 typedef enum { HOM_A_ISO = 0, HOM_A_DIAG = 1, HOM_A_FULLSYM = 2 } hom_a_kind;
 typedef enum { HOM_GANI = 0, HOM_GA = 1 } hom_scheme;
 /* HOM_FP64: FFTs, fields and reductions in FP64.
- * HOM_MIXED: inner CG with FP32 FFTs and fields (FP64 dots and step
- * lengths) inside an FP64 iterative-refinement loop whose residual uses the
- * FP64 operator. */
+ * HOM_MIXED: the CG recursion runs with FP32 FFTs and fields (FP64 dots and
+ * step lengths); the iterate is accumulated in FP64, and each time the
+ * recursive residual has fallen by inner_tol the true residual b - Op x,
+ * computed with the FP64 operator, replaces it while the search direction is
+ * kept (residual replacement, van der Vorst & Ye 2000).  The stopping test
+ * is on that FP64 residual. */
 typedef enum { HOM_FP64 = 0, HOM_MIXED = 1 } hom_prec;
 
 typedef struct {
@@ -67,15 +70,17 @@ typedef struct {
   hom_prec prec;       /* default HOM_FP64 */
   double Y[3];         /* cell half-lengths, default 0.5 (unit cell) */
   int max_iter;        /* CG iterations per (inner) solve, default 10000 */
-  int max_outer;       /* refinement steps (HOM_MIXED), default 30 */
-  double inner_tol;    /* relative residual of each inner FP32 solve, default 1e-4 */
+  int max_outer;       /* FP64 residual replacements (HOM_MIXED), default 100 */
+  double inner_tol;    /* HOM_MIXED: fall of the FP32 recursive residual between
+                          replacements, default 1e-2 */
   int check_every;     /* iterations per captured graph between host checks, default 16 */
   void* stream;        /* hipStream_t the caller orders work against, or NULL */
 } hom_options;
 
 typedef struct {
-  int iters_inner;       /* CG iterations (summed over refinement steps), max over load cases */
-  int iters_outer;       /* refinement steps (HOM_MIXED), 0 for HOM_FP64 */
+  int iters_inner;       /* CG iterations, max over load cases */
+  int iters_outer;       /* FP64 residual evaluations that (re)started the FP32
+                            recursion (HOM_MIXED), 0 for HOM_FP64 */
   double rel_resid_true; /* ||b - Op x|| / ||b|| with the FP64 operator, max over load cases */
   double rho_A;          /* contrast C_A / c_A of the coefficient field (A2) */
   double seconds;        /* wall time of the call */
@@ -98,8 +103,8 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
 
 /* Solve L load cases.
  *  E        [L][d] host, macroscopic gradients (Sec. 1, the split e = E + e~)
- *  tol      stopping test ||r_i|| / ||r_0|| <= tol (HOM_FP64) or the outer
- *           FP64 residual ||b - Op x|| / ||b|| <= tol (HOM_MIXED); tol > 0
+ *  tol      stopping test ||r_i|| / ||r_0|| <= tol (HOM_FP64) or the FP64
+ *           residual ||b - Op x|| / ||b|| <= tol (HOM_MIXED); tol > 0
  *  strain   nullable device pointer, [L][d][N grid] FP64: total strain E + e~
  *  W        nullable host pointer, [L][L] energies (A_H when E = I)
  *  J        nullable host pointer, [L][d] mean fluxes <A (E_l + e~_l)>

@@ -27,6 +27,7 @@ struct Work {
   double* part = nullptr;   // partial sums                 [items][P]
   double* part2 = nullptr;  // second partial buffer        [items][P]
   ItemScal* sc = nullptr;   // solver scalars               [items]
+  ItemScal* mask = nullptr; // per-item selection of masked launches [items]
   std::vector<void*> owned;
   ~Work();
   hipError_t alloc(int items, long S, long Xe, int d, int P);

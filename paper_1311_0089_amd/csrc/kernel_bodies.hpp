@@ -148,7 +148,8 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
         if (a.fuse) {
           const cpx<T> rv = a.r[idx];
           cpx<T> pv = a.p[idx];
-          pv = cpx<T>{rv.x + beta * pv.x, rv.y + beta * pv.y};
+          // beta = 0 restarts the direction: p = r exactly, whatever p held
+          pv = (beta == T(0)) ? rv : cpx<T>{rv.x + beta * pv.x, rv.y + beta * pv.y};
           a.p[idx] = pv;
           s[it] = pv;
         } else {
@@ -366,6 +367,12 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
         const cpx<T>* src = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride;
         xa = src[(long)r0 * H + h];
         if (r1 < a.rows) xb = src[(long)r1 * H + h];
+      }
+      if (h == 0) {
+        // the h = 0 bin of a real line is real: an imaginary part left there by
+        // rounding would otherwise leak into the other line of the pair
+        xa.y = T(0);
+        xb.y = T(0);
       }
       lds[line * ls + h] = cpx<T>{xa.x - xb.y, xa.y + xb.x};
       if (h > 0) lds[line * ls + n - h] = cpx<T>{xa.x + xb.y, xb.x - xa.y};

@@ -1,8 +1,10 @@
 // kernels.hip -- hot-path kernels for gfx950: FFT passes with fused pointwise
 // stages (flux A e, projection on n(k), CG updates and FP64 partial dots),
 // CG scalar kernels and the FP64 energy quadrature.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -150,13 +152,14 @@ __global__ __launch_bounds__(kThreads) void k_cg_beta(ItemScal* sc, const double
       q.active = 0;
       return;
     }
+    // beta is kept also when the item stops: a residual replacement of the
+    // mixed solver rescales it and carries the search direction on
+    q.beta = s / q.rho;
     if (sqrt(s / q.rho0) <= q.tol) {
       q.conv = 1;
       q.active = 0;
-      q.beta = 0.0;
-    } else {
-      q.beta = s / q.rho;
-      if (q.iters >= q.max_iter) q.active = 0;
+    } else if (q.iters >= q.max_iter) {
+      q.active = 0;
     }
     q.rho = s;
   }
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
                                                           cpx<float>* p32, cpx<float>* x32,
                                                           long stride, long count, int H,
                                                           ItemScal* outer, ItemScal* inner,
-                                                          double eta, int max_iter,
+                                                          int max_iter, int keep_dir,
                                                           double* partials, int P,
                                                           const ItemScal* mask) {
   const int item = blockIdx.y;
@@ -201,7 +204,8 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
     if (blockIdx.x == 0 && threadIdx.x == 0) inner[item].active = 0;
     return;
   }
-  const double sc = 1.0 / sqrt(outer[item].rho);
+  // one scale per solve, 1 / ||b||, so a kept direction stays consistent
+  const double sc = 1.0 / sqrt(outer[item].rho0);
   const long base = (long)item * stride;
   double part = 0.0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
     const cpx<double> v = r64[base + e];
     const cpx<float> w = {(float)(v.x * sc), (float)(v.y * sc)};
     r32[base + e] = w;
-    p32[base + e] = w;
+    if (!keep_dir) p32[base + e] = w;
     x32[base + e] = cpx<float>{0.f, 0.f};
     const double wt = ((e % H) == 0) ? 1.0 : 2.0;
     part += wt * ((double)w.x * (double)w.x + (double)w.y * (double)w.y);
@@ -217,10 +221,41 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
   part = block_sum<kThreads>(part);
   if (threadIdx.x == 0) partials[(long)item * P + blockIdx.x] = part;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    inner[item].tol = eta;
     inner[item].max_iter = max_iter;
     inner[item].active = 1;
-    outer[item].iters += 1;   // refinement steps started
+    if (!keep_dir) {
+      inner[item].iters = 0;
+      inner[item].beta = 0.0;
+      inner[item].rho = 0.0;
+    }
+    outer[item].iters += 1;   // FP64 residual evaluations that (re)started the recursion
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_inner_init(ItemScal* inner, const double* partials,
+                                                         int P, int nparts, ItemScal* outer,
+                                                         double eta, double theta,
+                                                         const ItemScal* mask) {
+  const int item = blockIdx.x;
+  if ((mask && !mask[item].active) || !outer[item].active) return;
+  const double s = sum_partials(partials + (long)item * P, nparts);
+  if (threadIdx.x == 0) {
+    ItemScal& q = inner[item];
+    // residual replacement: carry the direction on with beta rescaled to the
+    // replaced residual, beta = (r_new, r_new) / (r_prev, r_prev); a fresh
+    // start has rho = 0 and takes p = r
+    const bool keep = q.rho > 0.0 && isfinite(q.beta) && q.status == 0 && s <= 4.0 * q.rho;
+    q.beta = keep ? q.beta * (s / q.rho) : 0.0;
+    q.rho = q.rho0 = s;
+    // stop the recursion once its residual fell by eta, or earlier when it
+    // predicts the outer tolerance (r32 carries the scale 1 / ||b||)
+    const double rel = sqrt(s);
+    q.tol = (rel > 0.0) ? fmax(eta, theta * outer[item].tol / rel) : eta;
+    q.alpha = 0.0;
+    q.status = isfinite(s) ? 0 : -5;
+    q.conv = (s == 0.0) ? 1 : 0;
+    q.active = (s > 0.0 && isfinite(s) && q.iters < q.max_iter) ? 1 : 0;
+    if (q.iters >= q.max_iter || !isfinite(s)) outer[item].active = 0;
   }
 }
 
@@ -230,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_accumulate(cpx<double>* x64,
                                                                const ItemScal* mask) {
   const int item = blockIdx.y;
   if (!outer[item].active || (mask && !mask[item].active)) return;
-  const double sc = sqrt(outer[item].rho);
+  const double sc = sqrt(outer[item].rho0);
   const long base = (long)item * stride;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (long)gridDim.x * blockDim.x) {
@@ -251,6 +286,79 @@ __global__ void k_set_scal(ItemScal* sc, int items, double tol, int max_iter, in
     q.active = active;
     sc[i] = q;
   }
+}
+
+// ---------------------------------------------------------------------------
+// coefficient validation on the device: eigenvalue range and flags
+// ---------------------------------------------------------------------------
+constexpr int kRangeBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_a_range(const double* A, int d, int kind, long npts,
+                                                      double* out) {
+  const int nA = (kind == 0) ? 1 : (kind == 1) ? d : d * (d + 1) / 2;
+  double lo = INFINITY, hi = 0.0;
+  int flags = 0;
+  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
+       p += (long)gridDim.x * blockDim.x) {
+    double v[6], l = 0.0, h = 0.0;
+    bool finite = true;
+    for (int t = 0; t < nA; ++t) {
+      v[t] = A[(long)t * npts + p];
+      finite = finite && isfinite(v[t]);
+    }
+    if (!finite) {
+      flags |= 1;
+    } else if (!point_range(d, kind, v, &l, &h)) {
+      flags |= 2;
+    } else {
+      lo = fmin(lo, l);
+      hi = fmax(hi, h);
+    }
+  }
+  __shared__ double slo[kThreads], shi[kThreads];
+  __shared__ int sfl[kThreads];
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  sfl[threadIdx.x] = flags;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
+      sfl[threadIdx.x] |= sfl[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[3 * blockIdx.x] = slo[0];
+    out[3 * blockIdx.x + 1] = shi[0];
+    out[3 * blockIdx.x + 2] = (double)sfl[0];
+  }
+}
+
+hipError_t a_field_range(const double* A, int d, int kind, long npts, hipStream_t s, double* lo,
+                         double* hi, int* flags) {
+  const int blocks = (int)std::max(1L, std::min((long)kRangeBlocks, (npts + kThreads - 1) / kThreads));
+  double* dout = nullptr;
+  hipError_t e = hipMalloc(&dout, sizeof(double) * 3 * blocks);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_a_range, dim3(blocks), dim3(kThreads), 0, s, A, d, kind, npts, dout);
+  e = hipGetLastError();
+  std::vector<double> h((size_t)3 * blocks);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return e;
+  *lo = INFINITY;
+  *hi = 0.0;
+  *flags = 0;
+  for (int b = 0; b < blocks; ++b) {
+    *lo = std::min(*lo, h[3 * b]);
+    *hi = std::max(*hi, h[3 * b + 1]);
+    *flags |= (int)h[3 * b + 2];
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -316,22 +424,41 @@ __global__ void k_widen(const float* in, double* out, long n) {
 // ---------------------------------------------------------------------------
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// events armed for the next launch of this thread: the dispatch records them
+// itself, so the interval is the kernel's own, with no marker packet added
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+
+template <class F, class... Args>
+static void launch_k(F fn, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  if (t_ev_start) {
+    hipEvent_t a = t_ev_start, z = t_ev_stop;
+    t_ev_start = t_ev_stop = nullptr;
+    hipExtLaunchKernelGGL(fn, grid, block, (std::uint32_t)lds, s, a, z, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(fn, grid, block, lds, s, args...);
+  }
+}
+
 template <class T>
 hipError_t launch_col_expand(const ColExpandArgs<T>& a, int items, size_t lds, hipStream_t s,
                              const StaticKernel* sk) {
   dim3 grid(ceil_div(a.inner, a.W), items);
   if (sk) {
     auto fn = reinterpret_cast<void (*)(ColExpandArgs<T>)>(const_cast<void*>(sk->fn));
-    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();
   }
   const long npos = (long)a.n_in * a.W;
   if (npos <= 8L * kThreads)
-    hipLaunchKernelGGL((k_col_expand<T, ColGen, 8>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_expand<T, ColGen, 8>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 16L * kThreads)
-    hipLaunchKernelGGL((k_col_expand<T, ColGen, 16>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_expand<T, ColGen, 16>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 32L * kThreads)
-    hipLaunchKernelGGL((k_col_expand<T, ColGen, 32>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_expand<T, ColGen, 32>), grid, dim3(kThreads), lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -343,13 +470,13 @@ hipError_t launch_col_plain(const ColPlainArgs<T>& a, int items, int sign, size_
   dim3 grid(ceil_div(a.inner, a.W), a.outer, items * a.d);
   if (sk) {
     auto fn = reinterpret_cast<void (*)(ColPlainArgs<T>)>(const_cast<void*>(sk->fn));
-    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();
   }
   if (sign < 0)
-    hipLaunchKernelGGL((k_col_plain<T, ColGen, -1>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_plain<T, ColGen, -1>), grid, dim3(kThreads), lds, s, a);
   else
-    hipLaunchKernelGGL((k_col_plain<T, ColGen, +1>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_plain<T, ColGen, +1>), grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -359,16 +486,16 @@ hipError_t launch_col_project(const ColProjectArgs<T>& a, int items, size_t lds,
   dim3 grid(ceil_div(a.inner, a.W), items);
   if (sk) {
     auto fn = reinterpret_cast<void (*)(ColProjectArgs<T>)>(const_cast<void*>(sk->fn));
-    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();
   }
   const long npos = (long)a.n_out * a.W;
   if (npos <= 8L * kThreads)
-    hipLaunchKernelGGL((k_col_project<T, ColGen, 8>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_project<T, ColGen, 8>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 16L * kThreads)
-    hipLaunchKernelGGL((k_col_project<T, ColGen, 16>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_project<T, ColGen, 16>), grid, dim3(kThreads), lds, s, a);
   else if (npos <= 32L * kThreads)
-    hipLaunchKernelGGL((k_col_project<T, ColGen, 32>), grid, dim3(kThreads), lds, s, a);
+    launch_k((k_col_project<T, ColGen, 32>), grid, dim3(kThreads), lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -382,14 +509,14 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
   if (sk) {
     if (mode != ROW_APPLY) return hipErrorInvalidValue;
     auto fn = reinterpret_cast<void (*)(RowArgs<T>)>(const_cast<void*>(sk->fn));
-    hipLaunchKernelGGL(fn, grid, dim3(sk->NT), sk->lds, s, a);
+    launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();
   }
   switch (mode) {
-    case ROW_APPLY: hipLaunchKernelGGL((k_row<T, RowGen, ROW_APPLY>), grid, dim3(kThreads), lds, s, a); break;
-    case ROW_CONST: hipLaunchKernelGGL((k_row<T, RowGen, ROW_CONST>), grid, dim3(kThreads), lds, s, a); break;
-    case ROW_SYNTH: hipLaunchKernelGGL((k_row<T, RowGen, ROW_SYNTH>), grid, dim3(kThreads), lds, s, a); break;
-    case ROW_FWD: hipLaunchKernelGGL((k_row<T, RowGen, ROW_FWD>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_APPLY: launch_k((k_row<T, RowGen, ROW_APPLY>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_CONST: launch_k((k_row<T, RowGen, ROW_CONST>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_SYNTH: launch_k((k_row<T, RowGen, ROW_SYNTH>), grid, dim3(kThreads), lds, s, a); break;
+    case ROW_FWD: launch_k((k_row<T, RowGen, ROW_FWD>), grid, dim3(kThreads), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -397,56 +524,63 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
 
 template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
+  launch_k((k_cg_update<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
                           hipStream_t s, const ItemScal* mask) {
-  hipLaunchKernelGGL(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask);
+  launch_k(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask);
   return hipGetLastError();
 }
 hipError_t launch_cg_alpha(ItemScal* sc, const double* partials, int P, int nparts, int items,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
+  launch_k(k_cg_alpha, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
   return hipGetLastError();
 }
 hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int nparts, int items,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_beta, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
+  launch_k(k_cg_beta, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
   return hipGetLastError();
 }
 hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int nparts, int items,
                               int init, hipStream_t s, const ItemScal* mask) {
-  hipLaunchKernelGGL(k_outer_check, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts,
+  launch_k(k_outer_check, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts,
                      init, mask);
   return hipGetLastError();
 }
 hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float>* p32,
                               cpx<float>* x32, long stride, long count, int H, ItemScal* outer,
-                              ItemScal* inner, double eta, int max_iter, double* partials, int P,
+                              ItemScal* inner, int max_iter, int keep_dir, double* partials, int P,
                               int blocks, int items, hipStream_t s, const ItemScal* mask) {
-  hipLaunchKernelGGL(k_inner_start, dim3(blocks, items), dim3(kThreads), 0, s, r64, r32, p32, x32,
-                     stride, count, H, outer, inner, eta, max_iter, partials, P, mask);
+  launch_k(k_inner_start, dim3(blocks, items), dim3(kThreads), 0, s, r64, r32, p32, x32,
+                     stride, count, H, outer, inner, max_iter, keep_dir, partials, P, mask);
+  return hipGetLastError();
+}
+hipError_t launch_inner_init(ItemScal* inner, const double* partials, int P, int nparts, int items,
+                             ItemScal* outer, double eta, double theta, hipStream_t s,
+                             const ItemScal* mask) {
+  launch_k(k_inner_init, dim3(items), dim3(kThreads), 0, s, inner, partials, P, nparts,
+                     outer, eta, theta, mask);
   return hipGetLastError();
 }
 hipError_t launch_inner_accumulate(cpx<double>* x64, const cpx<float>* x32, long stride, long count,
                                    const ItemScal* outer, int blocks, int items, hipStream_t s,
                                    const ItemScal* mask) {
-  hipLaunchKernelGGL(k_inner_accumulate, dim3(blocks, items), dim3(kThreads), 0, s, x64, x32,
+  launch_k(k_inner_accumulate, dim3(blocks, items), dim3(kThreads), 0, s, x64, x32,
                      stride, count, outer, mask);
   return hipGetLastError();
 }
 hipError_t launch_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_set_scal, dim3(ceil_div(items, 64)), dim3(64), 0, s, sc, items, tol,
+  launch_k(k_set_scal, dim3(ceil_div(items, 64)), dim3(64), 0, s, sc, items, tol,
                      max_iter, active);
   return hipGetLastError();
 }
 hipError_t launch_quad(const double* e, long e_stride, long e_cstride, const double* A,
                        long A_cstride, int kind, int d, long npts, int l0, int nl, int m0, int nm,
                        double* partials, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_quad, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
+  launch_k(k_quad, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
                      A_cstride, kind, d, npts, l0, nl, m0, nm, partials);
   return hipGetLastError();
 }
@@ -455,14 +589,14 @@ hipError_t launch_quad_final(const double* partials, int blocks, int nl, int nm,
   (void)nl;
   (void)nm;
   (void)d;
-  hipLaunchKernelGGL(k_quad_final, dim3(1), dim3(kThreads), 0, s, partials, blocks, npts, out);
+  launch_k(k_quad_final, dim3(1), dim3(kThreads), 0, s, partials, blocks, npts, out);
   return hipGetLastError();
 }
 hipError_t launch_convert(const double* in, float* out, long n, hipStream_t s) {
   int blocks = ceil_div(n, kThreads);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_convert, dim3(blocks), dim3(kThreads), 0, s, in, out, n);
+  launch_k(k_convert, dim3(blocks), dim3(kThreads), 0, s, in, out, n);
   return hipGetLastError();
 }
 
@@ -470,7 +604,7 @@ hipError_t launch_widen(const float* in, double* out, long n, hipStream_t s) {
   int blocks = ceil_div(n, kThreads);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_widen, dim3(blocks), dim3(kThreads), 0, s, in, out, n);
+  launch_k(k_widen, dim3(blocks), dim3(kThreads), 0, s, in, out, n);
   return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@
 namespace hom {
 
 constexpr int kThreads = 256;
+// the FP32 recursion of the mixed solver aims at this fraction of the outer
+// tolerance, so the FP64 residual that replaces it usually passes the test
+constexpr double kTolSafety = 0.5;
 
 // per-item solver scalars, device resident
 struct ItemScal {
@@ -181,6 +184,73 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
 template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s);
 
+// Eigenvalue range [lo, hi] of the coefficient at one point (v holds its
+// nA values: kind 0 a I, kind 1 diagonal, kind 2 symmetric in Voigt order);
+// false if a value is not finite or the matrix is not positive definite.
+__host__ __device__ inline bool point_range(int d, int kind, const double* v, double* lo, double* hi) {
+  for (int t = 0; t < (kind == 0 ? 1 : kind == 1 ? d : d * (d + 1) / 2); ++t)
+    if (!isfinite(v[t])) return false;
+  if (kind == 0) {
+    *lo = *hi = v[0];
+    return v[0] > 0;
+  }
+  if (kind == 1) {
+    *lo = *hi = v[0];
+    for (int a = 0; a < d; ++a) {
+      *lo = fmin(*lo, v[a]);
+      *hi = fmax(*hi, v[a]);
+    }
+    return *lo > 0;
+  }
+  if (d == 1) {
+    *lo = *hi = v[0];
+    return v[0] > 0;
+  }
+  if (d == 2) {
+    const double a = v[0], b = v[1], c = v[2];
+    const double m = 0.5 * (a + b), r = sqrt(0.25 * (a - b) * (a - b) + c * c);
+    *lo = m - r;
+    *hi = m + r;
+    return *lo > 0;
+  }
+  // 3x3 symmetric: closed-form eigenvalues (trigonometric method)
+  const double a00 = v[0], a11 = v[1], a22 = v[2], a12 = v[3], a02 = v[4], a01 = v[5];
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  if (p1 == 0.0) {
+    *lo = fmin(a00, fmin(a11, a22));
+    *hi = fmax(a00, fmax(a11, a22));
+    return *lo > 0;
+  }
+  const double p2 = (a00 - q) * (a00 - q) + (a11 - q) * (a11 - q) + (a22 - q) * (a22 - q) + 2 * p1;
+  const double p = sqrt(p2 / 6.0);
+  const double b00 = (a00 - q) / p, b11 = (a11 - q) / p, b22 = (a22 - q) / p;
+  const double b01 = a01 / p, b02 = a02 / p, b12 = a12 / p;
+  const double detB = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
+                      b02 * (b01 * b12 - b11 * b02);
+  double rr = detB / 2.0;
+  rr = fmax(-1.0, fmin(1.0, rr));
+  const double phi = acos(rr) / 3.0;
+  const double e1 = q + 2 * p * cos(phi);
+  const double e3 = q + 2 * p * cos(phi + 2.0 * M_PI / 3.0);
+  *lo = e3;
+  *hi = e1;
+  // Sylvester criterion as the definiteness test (robust against rounding of e3)
+  const double m1 = a00, m2 = a00 * a11 - a01 * a01;
+  const double m3 = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
+                    a02 * (a01 * a12 - a11 * a02);
+  return m1 > 0 && m2 > 0 && m3 > 0 && e3 > 0;
+}
+
+// Range of the whole field A [nA][npts] (device pointer): lo, hi and flags
+// (bit 0: a value not finite, bit 1: a point not positive definite).
+hipError_t a_field_range(const double* A, int d, int kind, long npts, hipStream_t s, double* lo,
+                         double* hi, int* flags);
+
+// Arm HIP events for the next kernel launched by this thread through the
+// launchers below: hipExtLaunchKernel records them from the dispatch itself.
+void arm_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // mask (nullable): only items active in the mask are touched
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
                           hipStream_t s, const ItemScal* mask = nullptr);
@@ -193,13 +263,24 @@ hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int npart
 // (init != 0) sets rho0.
 hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int nparts, int items,
                               int init, hipStream_t s, const ItemScal* mask = nullptr);
-// inner FP32 start: r32 = p32 = r64 / sqrt(rho_out), x32 = 0, inner scalars
-// reset, outer step counter incremented
+// FP32 recursion (re)started from the FP64 residual: r32 = r64 / ||b|| (one
+// scale per solve, ||b||^2 = rho0 of the outer scalars), x32 = 0 and partials
+// of (r32, r32).  keep_dir = 0 is a fresh start (p32 = r32, iteration count
+// reset); keep_dir = 1 replaces the recursive residual and keeps p32.  The
+// outer counter of residual evaluations is incremented.
 hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float>* p32,
                               cpx<float>* x32, long stride, long count, int H, ItemScal* outer,
-                              ItemScal* inner, double eta, int max_iter, double* partials, int P,
+                              ItemScal* inner, int max_iter, int keep_dir, double* partials, int P,
                               int blocks, int items, hipStream_t s, const ItemScal* mask = nullptr);
-// x64 += sqrt(rho_out) * x32
+// inner scalars after launch_inner_start: rho = (r32, r32); a kept direction
+// continues with beta scaled to the new residual (a fresh start, or a true
+// residual more than twice the recursive one, restarts with p = r); the
+// recursion stops once its residual fell by max(eta, theta tol_out / rel_out).
+// An item whose iteration budget is spent also stops its outer loop.
+hipError_t launch_inner_init(ItemScal* inner, const double* partials, int P, int nparts, int items,
+                             ItemScal* outer, double eta, double theta, hipStream_t s,
+                             const ItemScal* mask = nullptr);
+// x64 += ||b|| * x32
 hipError_t launch_inner_accumulate(cpx<double>* x64, const cpx<float>* x32, long stride, long count,
                                    const ItemScal* outer, int blocks, int items, hipStream_t s,
                                    const ItemScal* mask = nullptr);

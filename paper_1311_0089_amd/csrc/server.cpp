@@ -11,8 +11,9 @@
 //           outer check, start the inner FP32 solve       (mask: new items)
 //   tick    replay the class graph (K iterations, all live items), read the
 //           flags back
-//   refine  items whose inner solve finished: x64 += x32, FP64 residual with
-//           the FP64 operator, outer check, restart inner  (mask: those items)
+//   refine  items whose FP32 recursion stopped: x64 += x32, FP64 residual
+//           with the FP64 operator, outer check, the FP64 residual replaces
+//           the recursive one (search direction kept)  (mask: those items)
 //   retire  slots whose items all stopped: FP64 strain synthesis and energy
 //           quadrature, results, free the slot
 // Classes run on their own streams, so their work overlaps on the device.
@@ -243,10 +244,10 @@ hipError_t hom_server::admit(SizeClass* k, std::vector<std::pair<int, Req*>>& ad
                              k->mask);
   if (err == hipSuccess)
     err = launch_inner_start(w.r, w32.r, w32.p, w32.x, e->S, e->S, e->H, w.sc, w32.sc,
-                             opt.inner_tol, opt.max_iter, w32.part, P, ub, k->items, e->stream,
-                             k->mask);
+                             opt.max_iter, 0, w32.part, P, ub, k->items, e->stream, k->mask);
   if (err == hipSuccess)
-    err = launch_cg_init(w32.sc, w32.part, P, ub, k->items, e->stream, k->mask);
+    err = launch_inner_init(w32.sc, w32.part, P, ub, k->items, w.sc, opt.inner_tol, kTolSafety,
+                            e->stream, k->mask);
   if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
   return err;
 }
@@ -397,7 +398,7 @@ hipError_t hom_server::refine_and_retire(SizeClass* k) {
     if (k->h_outer[i].active && !k->h_inner[i].active) {
       m.active = 1;
       any = true;
-      k->slot_req[i / dd]->inner_sum[i % dd] += k->h_inner[i].iters;
+      k->slot_req[i / dd]->inner_sum[i % dd] = k->h_inner[i].iters;
       if (k->h_inner[i].status == -5) k->h_outer[i].status = -5;
     }
   }
@@ -418,10 +419,10 @@ hipError_t hom_server::refine_and_retire(SizeClass* k) {
                              k->mask);
   if (err == hipSuccess)
     err = launch_inner_start(w.r, w32.r, w32.p, w32.x, e->S, e->S, e->H, w.sc, w32.sc,
-                             opt.inner_tol, opt.max_iter, w32.part, P, ub, k->items, e->stream,
-                             k->mask);
+                             opt.max_iter, 1, w32.part, P, ub, k->items, e->stream, k->mask);
   if (err == hipSuccess)
-    err = launch_cg_init(w32.sc, w32.part, P, ub, k->items, e->stream, k->mask);
+    err = launch_inner_init(w32.sc, w32.part, P, ub, k->items, w.sc, opt.inner_tol, kTolSafety,
+                            e->stream, k->mask);
   if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
   return err;
 }

@@ -74,6 +74,7 @@ hipError_t Work<T>::alloc(int n, long S, long Xe, int d, int P) {
   if (e == hipSuccess) e = get((void**)&part, sizeof(double) * (size_t)P * n);
   if (e == hipSuccess) e = get((void**)&part2, sizeof(double) * (size_t)P * n);
   if (e == hipSuccess) e = get((void**)&sc, sizeof(ItemScal) * (size_t)n);
+  if (e == hipSuccess) e = get((void**)&mask, sizeof(ItemScal) * (size_t)n);
   if (e == hipSuccess) items = n;
   return e;
 }
@@ -766,8 +767,8 @@ hom_status hom_options_default(hom_options* o) {
   o->prec = HOM_FP64;
   o->Y[0] = o->Y[1] = o->Y[2] = 0.5;
   o->max_iter = 10000;
-  o->max_outer = 30;
-  o->inner_tol = 1e-4;
+  o->max_outer = 100;
+  o->inner_tol = 1e-2;
   o->check_every = 16;
   o->stream = nullptr;
   return HOM_OK;
@@ -780,59 +781,15 @@ static hom_status dev_status(hipError_t e) {
 }
 
 // eigenvalue range of the coefficient at one point; false if not SPD or not finite
-static bool point_range(int d, int kind, const double* v, double* lo, double* hi) {
-  for (int t = 0; t < (kind == 0 ? 1 : kind == 1 ? d : d * (d + 1) / 2); ++t)
-    if (!std::isfinite(v[t])) return false;
-  if (kind == 0) {
-    *lo = *hi = v[0];
-    return v[0] > 0;
-  }
-  if (kind == 1) {
-    *lo = *hi = v[0];
-    for (int a = 0; a < d; ++a) {
-      *lo = std::min(*lo, v[a]);
-      *hi = std::max(*hi, v[a]);
-    }
-    return *lo > 0;
-  }
-  if (d == 1) {
-    *lo = *hi = v[0];
-    return v[0] > 0;
-  }
-  if (d == 2) {
-    const double a = v[0], b = v[1], c = v[2];
-    const double m = 0.5 * (a + b), r = std::sqrt(0.25 * (a - b) * (a - b) + c * c);
-    *lo = m - r;
-    *hi = m + r;
-    return *lo > 0;
-  }
-  // 3x3 symmetric: closed-form eigenvalues (trigonometric method)
-  const double a00 = v[0], a11 = v[1], a22 = v[2], a12 = v[3], a02 = v[4], a01 = v[5];
-  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
-  const double q = (a00 + a11 + a22) / 3.0;
-  if (p1 == 0.0) {
-    *lo = std::min(a00, std::min(a11, a22));
-    *hi = std::max(a00, std::max(a11, a22));
-    return *lo > 0;
-  }
-  const double p2 = (a00 - q) * (a00 - q) + (a11 - q) * (a11 - q) + (a22 - q) * (a22 - q) + 2 * p1;
-  const double p = std::sqrt(p2 / 6.0);
-  const double b00 = (a00 - q) / p, b11 = (a11 - q) / p, b22 = (a22 - q) / p;
-  const double b01 = a01 / p, b02 = a02 / p, b12 = a12 / p;
-  const double detB = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
-                      b02 * (b01 * b12 - b11 * b02);
-  double rr = detB / 2.0;
-  rr = std::max(-1.0, std::min(1.0, rr));
-  const double phi = std::acos(rr) / 3.0;
-  const double e1 = q + 2 * p * std::cos(phi);
-  const double e3 = q + 2 * p * std::cos(phi + 2.0 * M_PI / 3.0);
-  *lo = e3;
-  *hi = e1;
-  // Sylvester criterion as the definiteness test (robust against rounding of e3)
-  const double m1 = a00, m2 = a00 * a11 - a01 * a01;
-  const double m3 = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
-                    a02 * (a01 * a12 - a11 * a02);
-  return m1 > 0 && m2 > 0 && m3 > 0 && e3 > 0;
+
+// order the cell stream after work already queued on the caller's stream
+static void wait_user_stream(CellImpl* c) {
+  if (!c->opt.stream) return;
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+  (void)hipEventRecord(ev, (hipStream_t)c->opt.stream);
+  (void)hipStreamWaitEvent(c->stream, ev, 0);
+  (void)hipEventDestroy(ev);
 }
 
 hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const double* A,
@@ -873,40 +830,6 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   int device = 0;
   hipError_t e = hipGetDevice(&device);
   if (e != hipSuccess) return dev_status(e);
-  // host copy of A for validation (A2: finite, symmetric positive definite)
-  std::vector<double> hA((size_t)nA_user * nQ);
-  if (A_on_device) {
-    e = hipMemcpy(hA.data(), A, sizeof(double) * hA.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return dev_status(e);
-  } else {
-    std::memcpy(hA.data(), A, sizeof(double) * hA.size());
-  }
-  double lo = INFINITY, hi = 0.0;
-  if (kind != HOM_A_FULLSYM || d == 1) {
-    // every plane holds eigenvalues directly
-    bool finite = true;
-    for (size_t i = 0; i < hA.size(); ++i) {
-      const double x = hA[i];
-      finite = finite && std::isfinite(x);
-      lo = std::min(lo, x);
-      hi = std::max(hi, x);
-    }
-    if (!finite) return HOM_EINVAL;
-    if (!(lo > 0)) return HOM_ENOTSPD;
-  } else {
-    std::vector<double> v(6);
-    for (long p = 0; p < nQ; ++p) {
-      for (int t = 0; t < nA_user; ++t) v[t] = hA[(size_t)t * nQ + p];
-      double l, h;
-      if (!point_range(d, kind, v.data(), &l, &h)) {
-        bool finite = true;
-        for (int t = 0; t < nA_user; ++t) finite = finite && std::isfinite(v[t]);
-        return finite ? HOM_ENOTSPD : HOM_EINVAL;
-      }
-      lo = std::min(lo, l);
-      hi = std::max(hi, h);
-    }
-  }
   CellImpl* c = pool_take(device, key);
   if (!c) {
     c = new (std::nothrow) CellImpl();
@@ -934,18 +857,29 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   }
   c->d = d;
   c->opt = o;
-  c->rhoA = hi / lo;
+  // A goes to the device as given (FP64), is validated there (A2: finite,
+  // symmetric positive definite at every point; contrast from the eigenvalue
+  // range) and converted to the FP32 copy of the mixed path
   const size_t nAd = (size_t)c->nA * nQ;
-  std::vector<float> hA32(nAd);
-  for (size_t i = 0; i < nAd; ++i) hA32[i] = (float)hA[i];
-  e = hipMemcpyAsync(c->A64, hA.data(), sizeof(double) * nAd, hipMemcpyHostToDevice, c->stream);
+  wait_user_stream(c);
+  e = hipMemcpyAsync(c->A64, A, sizeof(double) * nAd,
+                     A_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+  double lo = 0.0, hi = 0.0;
+  int flags = 0;
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->A32, hA32.data(), sizeof(float) * nAd, hipMemcpyHostToDevice, c->stream);
+    e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, c->stream, &lo, &hi,
+                      &flags);
+  if (e == hipSuccess && flags == 0) e = launch_convert(c->A64, c->A32, (long)nAd, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
     return dev_status(e);
   }
+  if (flags != 0) {
+    pool_put(c);
+    return (flags & 1) ? HOM_EINVAL : HOM_ENOTSPD;
+  }
+  c->rhoA = hi / lo;
   hom_cell* hc = new (std::nothrow) hom_cell();
   if (!hc) {
     pool_put(c);
@@ -975,14 +909,6 @@ hom_status hom_cell_dims(const hom_cell* c, int32_t* d, int32_t* N, int32_t* Q) 
   return HOM_OK;
 }
 
-static void wait_user_stream(CellImpl* c) {
-  if (!c->opt.stream) return;
-  hipEvent_t ev;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
-  (void)hipEventRecord(ev, (hipStream_t)c->opt.stream);
-  (void)hipStreamWaitEvent(c->stream, ev, 0);
-  (void)hipEventDestroy(ev);
-}
 
 hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* strain, double* W,
                      double* J, const double* strain0, hom_info* info) {
@@ -1003,7 +929,6 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
   int it_inner = 0, it_outer = 0;
   double relres = 0.0;
   std::vector<ItemScal> hs;
-  std::vector<int> inner_sum(L, 0);
   Work<double>& w = c->w64;
   const int P = partial_slots(c);
   do {
@@ -1026,7 +951,12 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
         else if (!s.conv && st == HOM_OK) st = HOM_ENOTCONV;
       }
     } else {
-      // outer FP64 refinement around inner FP32 CG; rho0 = (b, b)
+      // FP32 CG recursion with FP64 residual replacement.  The outer scalars
+      // hold (b, b) as rho0 and the true residual (r, r) as rho.  Whenever an
+      // item's recursion stops (its residual fell by inner_tol, or it
+      // predicts tol), x64 += ||b|| x32 and the recursive residual is replaced
+      // by the FP64 one, b - Op x64; the search direction is kept, so the
+      // Krylov recursion goes on instead of restarting.
       Work<float>& w32 = c->w32;
       ItemScal* outer = w.sc;
       if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 1, c->stream)) != hipSuccess) break;
@@ -1036,41 +966,68 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           break;
       }
       const int ub = update_blocks(c->S);
-      std::vector<ItemScal> ho(L);
+      if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, outer, w32.sc,
+                                  c->opt.max_iter, 0, w32.part, P, ub, L, c->stream)) != hipSuccess)
+        break;
+      if ((e = launch_inner_init(w32.sc, w32.part, P, ub, L, outer, c->opt.inner_tol, kTolSafety,
+                                 c->stream)) != hipSuccess)
+        break;
+      hipGraphExec_t g = nullptr;
+      if ((e = cg_graph<float>(c, L, std::max(1, c->opt.check_every), &g)) != hipSuccess) break;
+      std::vector<ItemScal> ho(L), hi(L), hm(L);
       for (;;) {
         if ((e = hipMemcpyAsync(ho.data(), outer, sizeof(ItemScal) * L, hipMemcpyDeviceToHost,
                                 c->stream)) != hipSuccess)
           break;
+        if ((e = hipMemcpyAsync(hi.data(), w32.sc, sizeof(ItemScal) * L, hipMemcpyDeviceToHost,
+                                c->stream)) != hipSuccess)
+          break;
         if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) break;
-        bool any = false;
-        for (auto& s : ho) any = any || s.active;
-        if (!any) break;
-        if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, outer, w32.sc,
-                                    c->opt.inner_tol, c->opt.max_iter, w32.part, P, ub, L,
-                                    c->stream)) != hipSuccess)
-          break;
-        if ((e = launch_cg_init(w32.sc, w32.part, P, ub, L, c->stream)) != hipSuccess) break;
-        if ((e = cg_run<float>(c, L, c->opt.max_iter, hs)) != hipSuccess) break;
+        bool any_outer = false, any_inner = false, any_replace = false;
         for (int i = 0; i < L; ++i) {
+          hm[i] = ItemScal{};
           if (!ho[i].active) continue;
-          inner_sum[i] += hs[i].iters;
-          if (hs[i].status == -5) st = HOM_EBREAKDOWN;
+          any_outer = true;
+          if (hi[i].status == -5) st = HOM_EBREAKDOWN;
+          if (hi[i].active) {
+            any_inner = true;
+          } else {
+            hm[i].active = 1;
+            any_replace = true;
+          }
         }
-        if ((e = launch_inner_accumulate(w.x, w32.x, c->S, c->S, outer, ub, L, c->stream)) !=
-            hipSuccess)
-          break;
-        if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, outer,
-                                    w.part)) != hipSuccess)
-          break;
-        if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream)) != hipSuccess)
-          break;
+        if (!any_outer) break;
+        if (any_replace) {
+          if ((e = hipMemcpyAsync(w.mask, hm.data(), sizeof(ItemScal) * L, hipMemcpyHostToDevice,
+                                  c->stream)) != hipSuccess)
+            break;
+          if ((e = launch_inner_accumulate(w.x, w32.x, c->S, c->S, outer, ub, L, c->stream,
+                                           w.mask)) != hipSuccess)
+            break;
+          if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, w.mask,
+                                      w.part)) != hipSuccess)
+            break;
+          if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream, w.mask)) !=
+              hipSuccess)
+            break;
+          if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, outer, w32.sc,
+                                      c->opt.max_iter, 1, w32.part, P, ub, L, c->stream,
+                                      w.mask)) != hipSuccess)
+            break;
+          if ((e = launch_inner_init(w32.sc, w32.part, P, ub, L, outer, c->opt.inner_tol,
+                                     kTolSafety, c->stream, w.mask)) != hipSuccess)
+            break;
+          // the host needs the outer verdicts before it decides what runs next
+          if (!any_inner) continue;
+        }
+        if ((e = hipGraphLaunch(g, c->stream)) != hipSuccess) break;
       }
       if (e != hipSuccess) break;
-      for (int i = 0; i < L; ++i) it_inner = std::max(it_inner, inner_sum[i]);
-      for (auto& s : ho) {
-        it_outer = std::max(it_outer, s.iters);
-        if (s.status == -5) st = HOM_EBREAKDOWN;
-        else if (!s.conv && st == HOM_OK) st = HOM_ENOTCONV;
+      for (int i = 0; i < L; ++i) {
+        it_inner = std::max(it_inner, hi[i].iters);
+        it_outer = std::max(it_outer, ho[i].iters);
+        if (ho[i].status == -5) st = HOM_EBREAKDOWN;
+        else if (!ho[i].conv && st == HOM_OK) st = HOM_ENOTCONV;
       }
     }
     // true residual with the FP64 operator
@@ -1191,31 +1148,48 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   const long rows = (c->dd == 3) ? (long)Q0 * Q1 : Q0;
   const double S = (double)c->S;
   cpx<T>* Xrow = (c->dd == 3) ? w.X2 : w.X1;
-  // events around every kernel of `reps` consecutive CG iterations, so each
-  // kernel is timed in the context it runs in (caches as left by its predecessor)
-  const int NEV = 9;
-  std::vector<hipEvent_t> ev((size_t)reps * NEV);
+  // every kernel of `reps` consecutive CG iterations carries its own event
+  // pair, recorded by the dispatch itself (no marker packets in between), so
+  // each kernel is timed in the context it runs in during a solve: caches
+  // as left by its predecessor, no gaps added
+  // slots: 0 expand, 1 axis-1 inverse, 2 row, 3 axis-1 forward, 4 project,
+  // 5 update, 6 alpha + beta, 7 whole iteration (sum of the kernels)
+  const int NK = 8;   // launches per iteration: slots 0..5, alpha, beta
+  std::vector<hipEvent_t> ev((size_t)reps * NK * 2, nullptr);
   for (auto& x : ev) (void)hipEventCreate(&x);
+  std::vector<int> launched((size_t)reps * NK, 0);
   e = reset();
   for (int it = 0; it < reps && e == hipSuccess; ++it) {
-    hipEvent_t* E = ev.data() + (size_t)it * NEV;
-    (void)hipEventRecord(E[0], c->stream);
+    hipEvent_t* E = ev.data() + (size_t)it * NK * 2;
+    int* Ln = launched.data() + (size_t)it * NK;
+    auto arm = [&](int k) {
+      arm_launch_events(E[2 * k], E[2 * k + 1]);
+      Ln[k] = 1;
+    };
+    arm(0);
     e = stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc);
-    (void)hipEventRecord(E[1], c->stream);
-    if (e == hipSuccess && c->dd == 3) e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc);
-    (void)hipEventRecord(E[2], c->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && c->dd == 3) {
+      arm(1);
+      e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc);
+    }
+    if (e == hipSuccess) {
+      arm(2);
       e = stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, c->dd == 3 ? Q1 : 1, c->dd == 3 ? Q2 : Q1,
                        nullptr, nullptr, nullptr, w.sc);
-    (void)hipEventRecord(E[3], c->stream);
-    if (e == hipSuccess && c->dd == 3) e = stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc);
-    (void)hipEventRecord(E[4], c->stream);
-    if (e == hipSuccess)
+    }
+    if (e == hipSuccess && c->dd == 3) {
+      arm(3);
+      e = stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc);
+    }
+    if (e == hipSuccess) {
+      arm(4);
       e = stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr, nullptr, nullptr,
                            nullptr, w.part, w.sc, nullptr);
-    (void)hipEventRecord(E[5], c->stream);
-    if (e == hipSuccess) e = launch_cg_alpha(w.sc, w.part, P, tiles, L, c->stream);
-    (void)hipEventRecord(E[6], c->stream);
+    }
+    if (e == hipSuccess) {
+      arm(6);
+      e = launch_cg_alpha(w.sc, w.part, P, tiles, L, c->stream);
+    }
     if (e == hipSuccess) {
       CgUpdateArgs<T> u{};
       u.x = w.x;
@@ -1228,28 +1202,27 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
       u.partials = w.part2;
       u.P = P;
       u.sc = w.sc;
+      arm(5);
       e = launch_cg_update<T>(u, L, ub, c->stream);
     }
-    (void)hipEventRecord(E[7], c->stream);
-    if (e == hipSuccess) e = launch_cg_beta(w.sc, w.part2, P, ub, L, c->stream);
-    (void)hipEventRecord(E[8], c->stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  // slots: 0 expand, 1 axis-1 inverse, 2 row, 3 axis-1 forward, 4 project,
-  // 5 update, 6 alpha + beta, 7 whole iteration
-  const int map_from[8] = {0, 1, 2, 3, 4, 6, -1, 0};
-  for (int it = 0; it < reps && e == hipSuccess; ++it) {
-    hipEvent_t* E = ev.data() + (size_t)it * NEV;
-    float t = 0.f;
-    for (int k = 0; k < 6; ++k) {
-      const int a = map_from[k];
-      if (hipEventElapsedTime(&t, E[a], E[a + 1]) == hipSuccess) ms[k] += t;
+    if (e == hipSuccess) {
+      arm(7);
+      e = launch_cg_beta(w.sc, w.part2, P, ub, L, c->stream);
     }
-    if (hipEventElapsedTime(&t, E[5], E[6]) == hipSuccess) ms[6] += t;
-    if (hipEventElapsedTime(&t, E[7], E[8]) == hipSuccess) ms[6] += t;
-    if (hipEventElapsedTime(&t, E[0], E[8]) == hipSuccess) ms[7] += t;
   }
-  for (int k = 0; k < 8; ++k) ms[k] /= reps;
+  arm_launch_events(nullptr, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  for (int it = 0; it < reps && e == hipSuccess; ++it) {
+    hipEvent_t* E = ev.data() + (size_t)it * NK * 2;
+    const int* Ln = launched.data() + (size_t)it * NK;
+    for (int k = 0; k < NK; ++k) {
+      float t = 0.f;
+      if (!Ln[k] || hipEventElapsedTime(&t, E[2 * k], E[2 * k + 1]) != hipSuccess) continue;
+      ms[k < 7 ? k : 6] += t;   // beta joins alpha in slot 6
+    }
+  }
+  for (int k = 0; k < 7; ++k) ms[k] /= reps;
+  for (int k = 0; k < 7; ++k) ms[7] += ms[k];
   if (c->dd != 3) ms[1] = ms[3] = 0.0;
   bytes[0] = L * (3.0 * S * esz + (double)c->dd * Q0 * inner * esz);
   if (c->dd == 3) {
