@@ -141,12 +141,22 @@ hom_status hom_profile_iteration(hom_cell* c, hom_prec prec, int L, int reps, do
 hom_status hom_set_specialized(int enable);
 
 /* Autotuner: for each pass of c's CG iteration (L load cases, precision
- * prec), time every compile-time variant and the generic kernel (reps
- * launches each, HIP events) and keep the fastest, process-wide, keyed by
- * (pass, FFT length, trial length, precision, components).  best_us
- * (nullable, 5 entries) receives the winning times in pass order.  Not to be
- * run while other threads solve. */
+ * prec), time every compile-time variant and the generic kernel inside reps
+ * whole CG iterations (HIP events; the other passes at their current
+ * choice) and keep the fastest, process-wide, keyed by (pass, precision, FFT
+ * length, trial length, components).  best_us (nullable, 5 entries: expand,
+ * axis-1 inverse, row, axis-1 forward, project) receives the time of one CG
+ * iteration with each pass's winner; passes a cell does not have are left
+ * untouched.  Not to be run while other threads solve. */
 hom_status hom_autotune(hom_cell* c, hom_prec prec, int L, int reps, double* best_us);
+/* Number of compile-time variants of each pass of c's iteration in
+ * precision prec (counts[5], same pass order; 0 where only the generic
+ * kernel exists or the pass is absent). */
+hom_status hom_pass_variants(hom_cell* c, hom_prec prec, int32_t* counts);
+/* Use variant v (-1: the generic kernel) of pass `pass` for every cell of
+ * c's shape and precision, process-wide, until changed (testing and A/B
+ * timing).  HOM_EINVAL for a variant or pass that does not exist. */
+hom_status hom_force_variant(hom_cell* c, hom_prec prec, int pass, int variant);
 /* Write / read the tuned choices as JSON ({"arch": ..., "choices": [[pass,
  * element bytes, FFT length, trial length, components, variant], ...]});
  * loading a file tuned on another GPU architecture returns HOM_EINVAL. */

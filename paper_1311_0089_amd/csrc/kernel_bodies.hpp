@@ -24,6 +24,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 
 struct ColGen {
   static constexpr int NT = kThreads;
+  static constexpr int CP = 1;   // components per transform call
   __device__ static int W(int w) { return w; }
   __device__ static int nfft(int n) { return n; }
   __device__ static int ntrial(int n) { return n; }
@@ -36,12 +37,29 @@ struct ColGen {
 template <class SP, int NTRIAL, int W_, int NT_>
 struct ColStat {
   static constexpr int NT = NT_;
+  static constexpr int CP = 1;
   __device__ static constexpr int W(int) { return W_; }
   __device__ static constexpr int nfft(int) { return SP::n; }
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
   template <class T, int S>
   __device__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
     sfft<T, S, SP, W_, true, 1, W_, NT_>(lds, tw);
+  }
+};
+
+// all D_ components of a W_-column tile side by side in one LDS tile
+// ([row][component][column]) and transformed by one call, so the block's
+// threads share the stages of every component and its loads are issued together
+template <class SP, int NTRIAL, int W_, int D_, int NT_>
+struct ColStatCP {
+  static constexpr int NT = NT_;
+  static constexpr int CP = D_;
+  __device__ static constexpr int W(int) { return W_; }
+  __device__ static constexpr int nfft(int) { return SP::n; }
+  __device__ static constexpr int ntrial(int) { return NTRIAL; }
+  template <class T, int S>
+  __device__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
+    sfft<T, S, SP, D_ * W_, true, 1, D_ * W_, NT_>(lds, tw);
   }
 };
 
@@ -158,9 +176,13 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
       }
     }
   }
-  for (int al = 0; al < a.g.d; ++al) {
+  // components in groups of P::CP per transform; LDS tile [row][comp][column]
+  constexpr int CPN = P::CP;
+  const int LW = CPN * W;
+  for (int al0 = 0; al0 < a.g.d; al0 += CPN) {
+    const int nc = min(CPN, a.g.d - al0);
     if (n_fft != n_in) {
-      for (int f = threadIdx.x; f < n_fft * W; f += NT) lds[f] = cpx<T>{T(0), T(0)};
+      for (int f = threadIdx.x; f < n_fft * LW; f += NT) lds[f] = cpx<T>{T(0), T(0)};
       __syncthreads();
     }
 #pragma unroll
@@ -170,15 +192,15 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
         const int w = f % W;
         T nv[3];
         unit_normal<T>(a.g, kof(f / W, n_in), min(col0 + w, a.inner - 1), nv);
-        lds[row[it] * W + w] = cscale(s[it], nv[al]);
+        for (int c = 0; c < nc; ++c) lds[row[it] * LW + c * W + w] = cscale(s[it], nv[al0 + c]);
       }
     }
     __syncthreads();
     P::template fft<T, +1>(lds, a.plan, W, a.tw);
-    cpx<T>* X = a.X + (long)item * a.X_stride + (long)al * a.X_cstride;
-    for (int f = threadIdx.x; f < n_fft * W; f += NT) {
-      const int i = f / W, w = f % W;
-      if (w < ncols) X[(long)i * a.inner + col0 + w] = lds[i * W + w];
+    cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride;
+    for (int f = threadIdx.x; f < n_fft * W * nc; f += NT) {
+      const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+      if (w < ncols) X[(long)c * a.X_cstride + (long)i * a.inner + col0 + w] = lds[i * LW + c * W + w];
     }
     __syncthreads();
   }
@@ -250,11 +272,16 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
       row[it] = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
     }
   }
-  for (int al = 0; al < a.d; ++al) {
-    const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al * a.X_cstride + col0;
-    for (int f = threadIdx.x; f < n_fft * W; f += NT) {
-      const int i = f / W, w = f % W;
-      lds[f] = (w < ncols) ? X[(long)i * a.inner + w] : cpx<T>{T(0), T(0)};
+  // components in groups of P::CP per transform; LDS tile [row][comp][column]
+  constexpr int CPN = P::CP;
+  const int LW = CPN * W;
+  for (int al0 = 0; al0 < a.d; al0 += CPN) {
+    const int nc = min(CPN, a.d - al0);
+    const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
+    for (int f = threadIdx.x; f < n_fft * W * nc; f += NT) {
+      const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+      lds[i * LW + c * W + w] = (w < ncols) ? X[(long)c * a.X_cstride + (long)i * a.inner + w]
+                                            : cpx<T>{T(0), T(0)};
     }
     __syncthreads();
     P::template fft<T, -1>(lds, a.plan, W, a.tw);
@@ -265,9 +292,11 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
         const int i = f / W, w = f % W;
         T nv[3];
         unit_normal<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1), nv);
-        const cpx<T> v = lds[row[it] * W + w];
-        acc[it].x += nv[al] * v.x;
-        acc[it].y += nv[al] * v.y;
+        for (int c = 0; c < nc; ++c) {
+          const cpx<T> v = lds[row[it] * LW + c * W + w];
+          acc[it].x += nv[al0 + c] * v.x;
+          acc[it].y += nv[al0 + c] * v.y;
+        }
       }
     }
     __syncthreads();

@@ -35,7 +35,9 @@ std::vector<const StaticKernel*> static_variants(int kind, int esz, int n, int n
                                                  const FftPlan& p) {
   std::vector<const StaticKernel*> out;
   for (const StaticKernel& k : static_registry()) {
-    if (k.kind != kind || k.esz != esz || k.n != n || k.ntrial != ntrial || k.d != d) continue;
+    // d: components the kernel is built for (0: any)
+    if (k.kind != kind || k.esz != esz || k.n != n || k.ntrial != ntrial) continue;
+    if (k.d != 0 && k.d != d) continue;
     // static LDS of the block reductions sits on top of the dynamic size
     if (k.lds + 1024 > g_static_max_lds) continue;
     // the compile-time plan must describe the same tables the host uploaded

@@ -22,6 +22,19 @@ RegCol<T, P125, 63, 16, 256> c125;
 RegCol<T, P61, 31, 16, 256> c61;
 RegCol<T, P29, 15, 16, 256> c29;
 RegCol<T, P509, 255, 8, 512> c509;
+// columns, all components per transform: plan, trial length, W, components,
+// workgroup size
+RegColCP<T, P1023, 1023, 4, 2, 512> x1023_4;
+RegColCP<T, P1023, 1023, 2, 2, 256> x1023_2;
+RegColCP<T, P1023, 1023, 1, 2, 128> x1023_1;
+RegColCP<T, P255, 255, 8, 3, 384> x255_8;
+RegColCP<T, P255, 255, 4, 3, 192> x255_4;
+RegColCP<T, P255, 255, 16, 3, 768> x255_16;
+RegColCP<T, P255, 255, 8, 2, 256> x255_8d2;
+RegColCP<T, P253, 127, 8, 3, 320> x253_8;
+RegColCP<T, P253, 127, 4, 3, 192> x253_4;
+RegColCP<T, P127, 127, 8, 3, 256> x127_8;
+RegColCP<T, P63, 63, 16, 3, 256> x63_16;
 // rows: plan, trial length, components, row pairs, workgroup size
 RegRow<T, P1023, 1023, 2, 2, 256> r1023_2;
 RegRow<T, P1023, 1023, 2, 4, 512> r1023_2w;

@@ -19,6 +19,11 @@ RegCol<T, P125, 63, 16, 256> c125;
 RegCol<T, P61, 31, 16, 256> c61;
 RegCol<T, P29, 15, 16, 256> c29;
 RegCol<T, P509, 255, 4, 512> c509;
+RegColCP<T, P1023, 1023, 1, 2, 256> x1023_1;
+RegColCP<T, P255, 255, 4, 3, 192> x255_4;
+RegColCP<T, P255, 255, 8, 3, 384> x255_8;
+RegColCP<T, P253, 127, 4, 3, 192> x253_4;
+RegColCP<T, P127, 127, 4, 3, 256> x127_4;
 RegRow<T, P1023, 1023, 2, 1, 256> r1023_2;
 RegRow<T, P1023, 1023, 2, 2, 512> r1023_2w;
 RegRow<T, P1023, 1023, 2, 1, 128> r1023_2n;

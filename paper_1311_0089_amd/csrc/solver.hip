@@ -217,7 +217,7 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
-  const StaticKernel* sk = find_static(KK_EXPAND, sizeof(cpx<T>), G0, c->N[0], 0, p0->p);
+  const StaticKernel* sk = find_static(KK_EXPAND, sizeof(cpx<T>), G0, c->N[0], c->dd, p0->p);
   if (sk) {
     a.W = sk->W;
     return launch_col_expand<T>(a, items, sk->lds, c->stream, sk);
@@ -341,7 +341,7 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
-  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), G0, c->N[0], 0, p0->p);
+  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), G0, c->N[0], c->dd, p0->p);
   if (sk) {
     a.W = sk->W;
     if (tiles) *tiles = (a.inner + sk->W - 1) / sk->W;
@@ -359,7 +359,7 @@ int project_tiles(CellImpl* c) {
   const DevPlan* p0;
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
   const int inner = (int)inner0(c);
-  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), c->Q[0], c->N[0], 0, p0->p);
+  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), c->Q[0], c->N[0], c->dd, p0->p);
   if (sk) return (inner + sk->W - 1) / sk->W;
   ColShape sh;
   if (col_shape(p0->p, c->N[0], inner, sizeof(cpx<T>), &sh) != hipSuccess) return 0;
@@ -1265,6 +1265,38 @@ extern "C" hom_status hom_set_specialized(int enable) {
 // ---------------------------------------------------------------------------
 namespace hom {
 
+// the passes of one CG iteration of c with their tuning keys and FFT lengths,
+// in the order expand, axis-1 inverse, row, axis-1 forward, project (the
+// axis-1 passes only in 3-D)
+struct PassKey {
+  int slot;
+  TuneKey key;
+  int fft_len;
+};
+template <class T>
+static std::vector<PassKey> pass_keys(const CellImpl* c) {
+  const int dd = c->dd, esz = (int)sizeof(cpx<T>);
+  const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
+  const int Glast = (dd == 3) ? Q2 : Q1;
+  std::vector<PassKey> v;
+  v.push_back({0, TuneKey{KK_EXPAND, esz, Q0, c->N[0], dd}, Q0});
+  if (dd == 3) v.push_back({1, TuneKey{KK_PLAIN_INV, esz, Q1, c->N[1], 0}, Q1});
+  v.push_back({2, TuneKey{KK_ROW, esz, Glast, c->N[dd - 1], dd}, Glast});
+  if (dd == 3) v.push_back({3, TuneKey{KK_PLAIN_FWD, esz, Q1, c->N[1], 0}, Q1});
+  v.push_back({4, TuneKey{KK_PROJECT, esz, Q0, c->N[0], dd}, Q0});
+  return v;
+}
+
+static int pass_variant_count(const PassKey& pk) {
+  const DevPlan* pl = nullptr;
+  if (get_dev_plan(pk.fft_len, &pl) != hipSuccess) return 0;
+  return (int)static_variants(pk.key.kind, pk.key.esz, pk.key.n, pk.key.ntrial, pk.key.d, pl->p)
+      .size();
+}
+
+// Each variant of each pass is timed inside whole CG iterations (the other
+// passes at their current choice), so it sees the caches its predecessor
+// leaves, as in a solve; passes are tuned one after the other.
 template <class T>
 static hipError_t autotune_impl(CellImpl* c, int L, int reps, double* best_us) {
   Work<T>& w = work_of<T>(c);
@@ -1275,57 +1307,34 @@ static hipError_t autotune_impl(CellImpl* c, int L, int reps, double* best_us) {
   if ((e = hipMalloc(&dE, sizeof(double) * hE.size())) != hipSuccess) return e;
   e = hipMemcpy(dE, hE.data(), sizeof(double) * hE.size(), hipMemcpyHostToDevice);
   const int P = partial_slots(c);
-  const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
-  const int dd = c->dd, esz = (int)sizeof(cpx<T>);
-  const int Glast = (dd == 3) ? Q2 : Q1;
-  cpx<T>* Xrow = (dd == 3) ? w.X2 : w.X1;
-  if (e == hipSuccess) e = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
-  if (e == hipSuccess) e = pipe_rhs<T>(c, w, L, dE, nullptr);
-  if (e == hipSuccess) e = launch_cg_init(w.sc, w.part, P, project_tiles<T>(c), L, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  // a fresh right-hand side before every measurement; tol 0 keeps every item
+  // iterating through the few iterations timed
+  auto reset = [&]() -> hipError_t {
+    hipError_t e2 = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
+    if (e2 == hipSuccess) e2 = pipe_rhs<T>(c, w, L, dE, nullptr);
+    if (e2 == hipSuccess) e2 = launch_cg_init(w.sc, w.part, P, project_tiles<T>(c), L, c->stream);
+    return e2;
+  };
   hipEvent_t ev0, ev1;
   (void)hipEventCreate(&ev0);
   (void)hipEventCreate(&ev1);
-  struct Stage {
-    TuneKey key;
-    int fft_len;
-    std::function<hipError_t()> run;
-  };
-  std::vector<Stage> stages;
-  stages.push_back({TuneKey{KK_EXPAND, esz, Q0, c->N[0], 0}, Q0,
-                    [&]() { return stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc); }});
-  if (dd == 3) {
-    stages.push_back({TuneKey{KK_PLAIN_INV, esz, Q1, c->N[1], 0}, Q1,
-                      [&]() { return stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc); }});
-    stages.push_back({TuneKey{KK_PLAIN_FWD, esz, Q1, c->N[1], 0}, Q1,
-                      [&]() { return stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc); }});
-  }
-  stages.push_back({TuneKey{KK_ROW, esz, Glast, c->N[dd - 1], dd}, Glast, [&]() {
-                      return stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, dd == 3 ? Q1 : 1, Glast,
-                                          nullptr, nullptr, nullptr, w.sc);
-                    }});
-  stages.push_back({TuneKey{KK_PROJECT, esz, Q0, c->N[0], 0}, Q0, [&]() {
-                      return stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr,
-                                              nullptr, nullptr, nullptr, w.part, w.sc, nullptr);
-                    }});
-  int si = 0;
-  for (Stage& st : stages) {
+  const int R = std::max(1, reps);
+  for (const PassKey& pk : pass_keys<T>(c)) {
     if (e != hipSuccess) break;
-    const DevPlan* pl = nullptr;
-    if ((e = get_dev_plan(st.fft_len, &pl)) != hipSuccess) break;
-    const int nvar = (int)static_variants(st.key.kind, st.key.esz, st.key.n, st.key.ntrial,
-                                          st.key.d, pl->p).size();
+    const int nvar = pass_variant_count(pk);
     double best = 1e30;
     int best_v = nvar > 0 ? 0 : -1;
     for (int v = -1; v < nvar; ++v) {
-      set_choice(st.key, v);
-      hipError_t e2 = st.run();  // warm-up; fails when no generic shape fits
+      set_choice(pk.key, v);
+      hipError_t e2 = reset();
+      if (e2 == hipSuccess) e2 = cg_body<T>(c, w, L, 2);  // warm-up; fails when no generic shape fits
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
       if (e2 != hipSuccess) {
         (void)hipGetLastError();
         continue;
       }
       (void)hipEventRecord(ev0, c->stream);
-      for (int i = 0; i < reps && e2 == hipSuccess; ++i) e2 = st.run();
+      e2 = cg_body<T>(c, w, L, R);
       (void)hipEventRecord(ev1, c->stream);
       if (e2 == hipSuccess) e2 = hipEventSynchronize(ev1);
       float ms = 0.f;
@@ -1334,15 +1343,14 @@ static hipError_t autotune_impl(CellImpl* c, int L, int reps, double* best_us) {
         e = e2;
         break;
       }
-      const double us = 1e3 * ms / reps;
+      const double us = 1e3 * ms / R;
       if (us < best) {
         best = us;
         best_v = v;
       }
     }
-    set_choice(st.key, best_v);
-    if (best_us && si < 5) best_us[si] = best;
-    ++si;
+    set_choice(pk.key, best_v);
+    if (best_us) best_us[pk.slot] = best;
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
@@ -1376,6 +1384,34 @@ extern "C" hom_status hom_autotune(hom_cell* hc, hom_prec prec, int L, int reps,
   e = (prec == HOM_FP64) ? autotune_impl<double>(c, L, reps, best_us)
                          : autotune_impl<float>(c, L, reps, best_us);
   return dev_status(e);
+}
+
+extern "C" hom_status hom_pass_variants(hom_cell* hc, hom_prec prec, int32_t* counts) {
+  if (!hc || !counts || (prec != HOM_FP64 && prec != HOM_MIXED)) return HOM_EINVAL;
+  hom::CellImpl* c = hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return HOM_EDEVICE;
+  for (int i = 0; i < 5; ++i) counts[i] = 0;
+  const auto keys = (prec == HOM_FP64) ? hom::pass_keys<double>(c) : hom::pass_keys<float>(c);
+  for (const auto& pk : keys) counts[pk.slot] = hom::pass_variant_count(pk);
+  return HOM_OK;
+}
+
+extern "C" hom_status hom_force_variant(hom_cell* hc, hom_prec prec, int pass, int variant) {
+  if (!hc || (prec != HOM_FP64 && prec != HOM_MIXED) || pass < 0 || pass > 4) return HOM_EINVAL;
+  hom::CellImpl* c = hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return HOM_EDEVICE;
+  const auto keys = (prec == HOM_FP64) ? hom::pass_keys<double>(c) : hom::pass_keys<float>(c);
+  for (const auto& pk : keys) {
+    if (pk.slot != pass) continue;
+    if (variant < -1 || variant >= hom::pass_variant_count(pk)) return HOM_EINVAL;
+    hom::set_choice(pk.key, variant);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    return HOM_OK;
+  }
+  return HOM_EINVAL;   // the pass does not exist for this cell (axis 1 of a 2-D cell)
 }
 
 extern "C" hom_status hom_tune_save(const char* path) {

@@ -6,8 +6,9 @@
 // radices largest first, then 8, 4, 2; Bluestein grids for primes above 31),
 // column tile width W and workgroup size for FP32 and for FP64, and row pairs
 // per workgroup for 2 and 3 components.  Shapes keep dynamic LDS <= 66 KiB
-// (two or more workgroups per CU) and each Stockham stage within the per-
-// thread register budget (checked at compile time below).
+// (two or more workgroups per CU; the all-components column tiles may take
+// up to a CU's LDS) and each Stockham stage within the per-thread register
+// budget (checked at compile time below).
 #pragma once
 #include "kernel_bodies.hpp"
 
@@ -46,6 +47,37 @@ struct RegCol {
     k.len = SP::len;
     k.blue = SP::blue;
     fill(k, typename SP::radices{});
+    register_static(k);
+  }
+};
+
+// axis-0 expand and project with all D components of a W-column tile in one
+// LDS tile and one transform call (matches cells with D device components)
+template <class T, class SP, int NTRIAL, int W, int D, int NT>
+struct RegColCP {
+  static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
+  static constexpr size_t lds = (size_t)SP::len * W * D * sizeof(cpx<T>);
+  static_assert(lds <= 150 * 1024, "column tile exceeds the LDS of a CU");
+  static_assert(PMAX <= 32, "too many positions per thread");
+  RegColCP() {
+    using P = ColStatCP<SP, NTRIAL, W, D, NT>;
+    add(KK_EXPAND, (const void*)&k_col_expand<T, P, PMAX>);
+    add(KK_PROJECT, (const void*)&k_col_project<T, P, PMAX>);
+  }
+  static void add(int kind, const void* fn) {
+    StaticKernel k{};
+    k.kind = kind;
+    k.esz = (int)sizeof(cpx<T>);
+    k.n = SP::n;
+    k.ntrial = NTRIAL;
+    k.d = D;
+    k.fn = fn;
+    k.W = W;
+    k.NT = NT;
+    k.lds = lds;
+    k.len = SP::len;
+    k.blue = SP::blue;
+    RegCol<T, SP, NTRIAL, 1, 256>::fill(k, typename SP::radices{});
     register_static(k);
   }
 };

@@ -20,7 +20,8 @@ ISO, DIAG, FULLSYM = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "hom_options_default", "hom_create_cell", "hom_solve", "hom_apply", "hom_project",
-    "hom_profile_iteration", "hom_set_specialized", "hom_autotune", "hom_tune_save",
+    "hom_profile_iteration", "hom_set_specialized", "hom_autotune", "hom_pass_variants",
+    "hom_force_variant", "hom_tune_save",
     "hom_tune_load", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
     "hom_server_create", "hom_server_submit", "hom_server_poll", "hom_server_times",
     "hom_server_destroy",
@@ -73,6 +74,8 @@ def lib():
         L.hom_profile_iteration.argtypes = [vp, ip, ip, ip, dp, dp]
         L.hom_set_specialized.argtypes = [ip]
         L.hom_autotune.argtypes = [vp, ip, ip, ip, dp]
+        L.hom_pass_variants.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32)]
+        L.hom_force_variant.argtypes = [vp, ip, ip, ip]
         L.hom_tune_save.argtypes = [ctypes.c_char_p]
         L.hom_tune_load.argtypes = [ctypes.c_char_p]
         L.hom_destroy_cell.argtypes = [vp]
@@ -225,6 +228,18 @@ class Cell:
         best = np.zeros(5)
         _check(lib().hom_autotune(self._h, prec, L, reps, _dptr(best)), "hom_autotune")
         return best
+
+    def pass_variants(self, prec=FP64):
+        """Compile-time variants per pass: [expand, axis-1 inverse, row,
+        axis-1 forward, project]."""
+        n = (ctypes.c_int32 * 5)()
+        _check(lib().hom_pass_variants(self._h, prec, n), "hom_pass_variants")
+        return list(n)
+
+    def force_variant(self, pass_index, variant, prec=FP64):
+        """Run variant `variant` (-1: generic kernel) of pass `pass_index` for
+        every cell of this shape and precision (process-wide)."""
+        _check(lib().hom_force_variant(self._h, prec, pass_index, variant), "hom_force_variant")
 
     def profile(self, prec=FP64, L=1, reps=20):
         ms = np.zeros(8)

@@ -121,6 +121,46 @@ def test_specialised_operator_matches_oracle(hom, oracle, torch_cuda, N, kind, s
     assert rel(a, b) < 1e-13
 
 
+# shapes whose passes have several compile-time variants: column tiles of
+# different widths, all components per transform, different row-pair counts
+VARIANT_CASES = [((1023, 15), 0, 0), ((15, 1023), 1, 0), ((255, 15), 0, 0),
+                 ((255, 15, 15), 0, 0), ((127, 15, 15), 2, 1), ((127, 15, 15), 0, 0),
+                 ((63, 15, 15), 1, 0), ((15, 15, 255), 0, 0), ((15, 15, 127), 0, 1)]
+
+
+@gpu
+@pytest.mark.parametrize("N,kind,scheme", VARIANT_CASES)
+def test_every_kernel_variant_matches_oracle(hom, oracle, torch_cuda, N, kind, scheme):
+    """Every registered variant of every pass (forced one at a time, the
+    others at their default) gives the oracle's operator, and the FP64
+    variants agree with each other to round-off."""
+    torch = torch_cuda
+    d = len(N)
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    A = hi.random_spd_field(Q, kind, seed=11 + kind, contrast=30.0)
+    ocell = oracle.Cell(A, N, kind=kind, scheme=scheme)
+    u = np.stack([ocell.apply_G(rand_field((d,) + N, 300 + l)) for l in range(2)])
+    ref = np.stack([ocell.apply_GA(u[l]) for l in range(2)])
+    ut = torch.from_numpy(u).cuda()
+    g = hom.Cell(A, N, kind=kind, scheme=scheme)
+    tried = 0
+    for prec, tol in ((hom.FP64, 1e-12), (hom.MIXED, 2e-5)):
+        counts = g.pass_variants(prec)
+        base = g.apply(ut, prec=prec).cpu().numpy()
+        for pas, cnt in enumerate(counts):
+            for v in range(cnt):
+                g.force_variant(pas, v, prec=prec)
+                try:
+                    out = g.apply(ut, prec=prec).cpu().numpy()
+                finally:
+                    g.force_variant(pas, 0, prec=prec)
+                tried += 1
+                assert rel(out, ref) < tol, (prec, pas, v)
+                if prec == hom.FP64:
+                    assert rel(out, base) < 1e-13, (pas, v)
+    assert tried >= 4
+
+
 @gpu
 @pytest.mark.parametrize("N,kind,scheme", SPECIALISED_ROW_BLUESTEIN)
 def test_specialised_row_bluestein_matches_oracle(hom, oracle, torch_cuda, N, kind, scheme):
