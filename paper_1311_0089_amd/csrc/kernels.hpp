@@ -274,9 +274,10 @@ hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float
                               int blocks, int items, hipStream_t s, const ItemScal* mask = nullptr);
 // inner scalars after launch_inner_start: rho = (r32, r32); a kept direction
 // continues with beta scaled to the new residual (a fresh start, or a true
-// residual more than twice the recursive one, restarts with p = r); the
-// recursion stops once its residual fell by max(eta, theta tol_out / rel_out).
-// An item whose iteration budget is spent also stops its outer loop.
+// residual more than twice the recursive one, restarts with p = r).  The
+// recursion stops once its residual fell by max(eta, theta tol_out /
+// rel_out), where the host replaces it again.  An item whose iteration budget
+// is spent also stops its outer loop.
 hipError_t launch_inner_init(ItemScal* inner, const double* partials, int P, int nparts, int items,
                              ItemScal* outer, double eta, double theta, hipStream_t s,
                              const ItemScal* mask = nullptr);

@@ -388,7 +388,8 @@ hipError_t hom_server::refine_and_retire(SizeClass* k) {
     for (int l = 0; l < r->L; ++l) all_done = all_done && !k->h_outer[(size_t)s * dd + l].active;
     if (all_done && (err = retire(k, s)) != hipSuccess) return err;
   }
-  // refinement step for items whose inner solve finished
+  // residual replacement for items whose recursion stopped (its residual
+  // fell by the inner tolerance, or budget or breakdown)
   bool any = false;
   for (int i = 0; i < k->items; ++i) {
     ItemScal& m = k->h_mask[i];

@@ -541,31 +541,84 @@ hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
 template hipError_t cg_graph<float>(CellImpl*, int, int, hipGraphExec_t*);
 template hipError_t cg_graph<double>(CellImpl*, int, int, hipGraphExec_t*);
 
-// run CG until every item is inactive; returns max iterations
+// Launch planner.  A captured graph runs K iterations; an item that stops
+// inside it leaves the rest as launches that do nothing but still cost their
+// dispatch, and every host check costs a round trip.  After each launch the
+// host reads every item's residual ratio, estimates its convergence rate per
+// iteration from the previous reading and launches the number of iterations
+// (at most Kmax) predicted to bring the nearest item to its stopping test.
+struct IterPlanner {
+  int Kmax = 16;
+  std::vector<double> prev_rho, rate;
+  std::vector<int> prev_it;
+  explicit IterPlanner(int items, int kmax) : Kmax(std::max(1, kmax)) {
+    prev_rho.assign(items, -1.0);
+    rate.assign(items, -1.0);
+    prev_it.assign(items, 0);
+  }
+  // forget the reading of item i (its residual was replaced); its rate stays
+  void reset(int i) { prev_rho[i] = -1.0; }
+  int next(const std::vector<ItemScal>& hs, const std::vector<char>& live) {
+    double need = 1e300;
+    for (size_t i = 0; i < hs.size(); ++i) {
+      if (!live[i] || !hs[i].active) continue;
+      const ItemScal& q = hs[i];
+      if (prev_rho[i] > 0.0 && q.iters > prev_it[i] && q.rho > 0.0 && q.rho < prev_rho[i])
+        rate[i] = std::pow(q.rho / prev_rho[i], 1.0 / (q.iters - prev_it[i]));
+      prev_rho[i] = q.rho;
+      prev_it[i] = q.iters;
+      if (!(rate[i] > 0.0 && rate[i] < 1.0) || !(q.rho > 0.0) || !(q.rho0 > 0.0)) {
+        need = std::min(need, (double)Kmax);
+        continue;
+      }
+      const double target = q.tol * q.tol * q.rho0;   // rho at which the item is done
+      const double it = (q.rho <= target) ? 1.0 : std::log(target / q.rho) / std::log(rate[i]);
+      need = std::min(need, std::max(1.0, std::ceil(it)));
+    }
+    return (need >= (double)Kmax) ? Kmax : (int)need;
+  }
+};
+
+// K iterations as back-to-back launches of graphs of power-of-two lengths
+template <class T>
+static hipError_t cg_launch(CellImpl* c, int items, int K) {
+  hipError_t e = hipSuccess;
+  for (int b = 1 << 30; b > 0 && e == hipSuccess; b >>= 1) {
+    if (!(K & b)) continue;
+    hipGraphExec_t g = nullptr;
+    e = cg_graph<T>(c, items, b, &g);
+    if (e == hipSuccess) e = hipGraphLaunch(g, c->stream);
+  }
+  return e;
+}
+
+static hipError_t read_scal(CellImpl* c, const ItemScal* d, int items, std::vector<ItemScal>& h) {
+  h.resize(items);
+  hipError_t e = hipMemcpyAsync(h.data(), d, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
+// run CG until every item is inactive
 template <class T>
 static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemScal>& hs) {
   Work<T>& w = work_of<T>(c);
-  const int K = std::max(1, c->opt.check_every);
-  hipGraphExec_t g = nullptr;
-  hipError_t e = cg_graph<T>(c, items, K, &g);
+  IterPlanner plan(items, c->opt.check_every);
+  std::vector<char> live(items, 1);
+  hipError_t e = read_scal(c, w.sc, items, hs);
   if (e != hipSuccess) return e;
-  hs.resize(items);
-  if ((e = hipMemcpyAsync(hs.data(), w.sc, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
-                          c->stream)) != hipSuccess)
-    return e;
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  int K = plan.Kmax;
   long launched = 0;
   for (;;) {
     bool any = false;
     for (auto& s : hs) any = any || s.active;
     if (!any) break;
-    if (launched > (long)max_iter + K) break;  // the device also stops at max_iter
-    if ((e = hipGraphLaunch(g, c->stream)) != hipSuccess) return e;
+    if (launched > (long)max_iter + plan.Kmax) break;  // the device also stops at max_iter
+    if ((e = cg_launch<T>(c, items, K)) != hipSuccess) return e;
     launched += K;
-    if ((e = hipMemcpyAsync(hs.data(), w.sc, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
-                            c->stream)) != hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+    if ((e = read_scal(c, w.sc, items, hs)) != hipSuccess) return e;
+    K = plan.next(hs, live);
   }
   return hipSuccess;
 }
@@ -952,11 +1005,11 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
       }
     } else {
       // FP32 CG recursion with FP64 residual replacement.  The outer scalars
-      // hold (b, b) as rho0 and the true residual (r, r) as rho.  Whenever an
-      // item's recursion stops (its residual fell by inner_tol, or it
-      // predicts tol), x64 += ||b|| x32 and the recursive residual is replaced
-      // by the FP64 one, b - Op x64; the search direction is kept, so the
-      // Krylov recursion goes on instead of restarting.
+      // hold (b, b) as rho0 and the true residual (r, r) as rho.  When an
+      // item's recursive residual has fallen by its inner tolerance (inner_tol,
+      // or less once it predicts tol), x64 += ||b|| x32 and the recursive
+      // residual is replaced by the FP64 one, b - Op x64; the search direction
+      // is kept, so the Krylov recursion goes on instead of restarting.
       Work<float>& w32 = c->w32;
       ItemScal* outer = w.sc;
       if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 1, c->stream)) != hipSuccess) break;
@@ -972,31 +1025,30 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
       if ((e = launch_inner_init(w32.sc, w32.part, P, ub, L, outer, c->opt.inner_tol, kTolSafety,
                                  c->stream)) != hipSuccess)
         break;
-      hipGraphExec_t g = nullptr;
-      if ((e = cg_graph<float>(c, L, std::max(1, c->opt.check_every), &g)) != hipSuccess) break;
+      IterPlanner plan(L, c->opt.check_every);
       std::vector<ItemScal> ho(L), hi(L), hm(L);
+      std::vector<char> live(L, 1);
+      if ((e = read_scal(c, outer, L, ho)) != hipSuccess) break;
+      int K = plan.Kmax;
       for (;;) {
-        if ((e = hipMemcpyAsync(ho.data(), outer, sizeof(ItemScal) * L, hipMemcpyDeviceToHost,
-                                c->stream)) != hipSuccess)
-          break;
-        if ((e = hipMemcpyAsync(hi.data(), w32.sc, sizeof(ItemScal) * L, hipMemcpyDeviceToHost,
-                                c->stream)) != hipSuccess)
-          break;
-        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) break;
-        bool any_outer = false, any_inner = false, any_replace = false;
+        bool any_outer = false;
+        for (int i = 0; i < L; ++i) any_outer = any_outer || ho[i].active;
+        if (!any_outer) break;
+        if ((e = cg_launch<float>(c, L, K)) != hipSuccess) break;
+        if ((e = read_scal(c, w32.sc, L, hi)) != hipSuccess) break;
+        // an item whose recursion stopped (its residual fell by its inner
+        // tolerance, or budget or breakdown) gets the FP64 residual
+        bool any_replace = false;
         for (int i = 0; i < L; ++i) {
           hm[i] = ItemScal{};
+          live[i] = ho[i].active;
           if (!ho[i].active) continue;
-          any_outer = true;
           if (hi[i].status == -5) st = HOM_EBREAKDOWN;
-          if (hi[i].active) {
-            any_inner = true;
-          } else {
+          if (!hi[i].active) {
             hm[i].active = 1;
             any_replace = true;
           }
         }
-        if (!any_outer) break;
         if (any_replace) {
           if ((e = hipMemcpyAsync(w.mask, hm.data(), sizeof(ItemScal) * L, hipMemcpyHostToDevice,
                                   c->stream)) != hipSuccess)
@@ -1017,10 +1069,14 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           if ((e = launch_inner_init(w32.sc, w32.part, P, ub, L, outer, c->opt.inner_tol,
                                      kTolSafety, c->stream, w.mask)) != hipSuccess)
             break;
-          // the host needs the outer verdicts before it decides what runs next
-          if (!any_inner) continue;
+          if ((e = read_scal(c, outer, L, ho)) != hipSuccess) break;
+          if ((e = read_scal(c, w32.sc, L, hi)) != hipSuccess) break;
+          for (int i = 0; i < L; ++i) {
+            if (hm[i].active) plan.reset(i);
+            live[i] = ho[i].active;
+          }
         }
-        if ((e = hipGraphLaunch(g, c->stream)) != hipSuccess) break;
+        K = plan.next(hi, live);
       }
       if (e != hipSuccess) break;
       for (int i = 0; i < L; ++i) {
@@ -1030,12 +1086,19 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
         else if (!ho[i].conv && st == HOM_OK) st = HOM_ENOTCONV;
       }
     }
-    // true residual with the FP64 operator
-    if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.q, nullptr, w.b, nullptr,
-                                w.part2)) != hipSuccess)
-      break;
+    // true residual with the FP64 operator (the mixed path's last outer check
+    // evaluated it for the final iterate already)
     std::vector<double> rr;
-    if ((e = sum_partials_host(c, w.part2, L, tiles64, rr)) != hipSuccess) break;
+    if (mixed) {
+      std::vector<ItemScal> ho;
+      if ((e = read_scal(c, w.sc, L, ho)) != hipSuccess) break;
+      for (int i = 0; i < L; ++i) rr.push_back(ho[i].rho);
+    } else {
+      if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.q, nullptr, w.b, nullptr,
+                                  w.part2)) != hipSuccess)
+        break;
+      if ((e = sum_partials_host(c, w.part2, L, tiles64, rr)) != hipSuccess) break;
+    }
     for (int i = 0; i < L; ++i) {
       const double v = (bb[i] > 0) ? std::sqrt(rr[i] / bb[i]) : std::sqrt(rr[i]);
       relres = std::max(relres, v);
