@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("operator applies/s & voxel-iters/s; cell solves/s with p50/p99 at A_H rel err 1e-6")
 HBM_PEAK_GBS = 8000.0
+PREC_NAME = {0: "fp64", 1: "mixed"}
 
 
 def parse():
@@ -52,6 +53,9 @@ def parse():
     ap.add_argument("--extra", action="store_true", help="also measure the 3-D workloads")
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving stream")
     ap.add_argument("--serving-rate", type=float, default=500.0)
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="mixed path: fall of the FP32 recursive residual between FP64 "
+                         "residual replacements (library default if omitted)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run an elementwise copy (b = -a) of MIB MiB of float32, "
                          "three times: a kernel of known HBM traffic that calibrates "
@@ -104,9 +108,10 @@ def tune(hom, w, prec, L, mode, out_path):
     return "run"
 
 
-def measure(hom, w, prec, steps, warmup, ref=True):
+def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
     """Time create+solve steps of workload w; profile one CG iteration."""
     L = w.E.shape[0]
+    kw = {} if inner_tol is None else {"inner_tol": inner_tol}
     import torch
     # the coefficient field is resident in HBM before the timed region; a step
     # validates it there, makes the FP32 copy and solves
@@ -114,7 +119,7 @@ def measure(hom, w, prec, steps, warmup, ref=True):
     torch.cuda.synchronize()
 
     def step():
-        cell = hom.Cell(A_dev, w.N, kind=w.kind, scheme=w.scheme, prec=prec)
+        cell = hom.Cell(A_dev, w.N, kind=w.kind, scheme=w.scheme, prec=prec, **kw)
         res = cell.solve(w.E, tol=w.tol)
         cell.close()
         return res
@@ -165,8 +170,14 @@ def measure(hom, w, prec, steps, warmup, ref=True):
     achieved = kernels[dom]["bytes"] / (kernels[dom]["ms"] * 1e-3) / 1e9
     out["iteration_profile_us"] = {k: round(v["ms"] * 1e3, 2) for k, v in prof.items()}
     out["iteration_GBps"] = prof["iteration"]["bytes"] / (prof["iteration"]["ms"] * 1e-3) / 1e9
+    # measured HBM bytes per launch of the dominant kernel, from the committed
+    # counter summary of this workload while the kernel sources are unchanged
+    from paper_1311_0089_amd import traffic
+    rec = traffic.load(os.path.join(ROOT, "profiles", f"traffic_{w.name}_{PREC_NAME[prec]}.md"))
+    tr = rec["slots"].get(dom, {}).get("bytes") if rec else None
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
+                       "algorithmic_bytes": kernels[dom]["bytes"]}
     log(f"{w.name}: {dt * 1e3:.2f} ms/step, iters {it_in}/{it_out}, profile " +
         ", ".join(f"{k} {v['ms'] * 1e3:.1f}us" for k, v in prof.items()))
     return out
@@ -256,7 +267,8 @@ def main():
     prec = hom.MIXED if args.prec == "mixed" else hom.FP64
     log(f"workload {w.name} vf={w.info['vf']:.3f} prec={args.prec} tol={w.tol}")
     tuned = tune(hom, w, prec, w.E.shape[0], args.tune, args.tune_out)
-    m = measure(hom, w, prec, args.steps, args.warmup, ref=not args.no_ref)
+    m = measure(hom, w, prec, args.steps, args.warmup, ref=not args.no_ref,
+                inner_tol=args.inner_tol)
     out = {
         "metric": METRIC,
         "value": m["voxel_iters_per_s"],
@@ -290,7 +302,8 @@ def main():
         for make in (hi.cfg3_spheres, hi.cfg4_lognormal):
             wx = make()
             t = tune(hom, wx, hom.MIXED, wx.E.shape[0], args.tune, args.tune_out)
-            mx = measure(hom, wx, hom.MIXED, max(2, args.steps // 3), 1, ref=not args.no_ref)
+            mx = measure(hom, wx, hom.MIXED, max(2, args.steps // 3), 1, ref=not args.no_ref,
+                         inner_tol=args.inner_tol)
             mx["kernel_tuning"] = t
             mx["contrast"] = wx.info.get("contrast")
             extra[wx.name] = mx

@@ -72,7 +72,7 @@ typedef struct {
   int max_iter;        /* CG iterations per (inner) solve, default 10000 */
   int max_outer;       /* FP64 residual replacements (HOM_MIXED), default 100 */
   double inner_tol;    /* HOM_MIXED: fall of the FP32 recursive residual between
-                          replacements, default 1e-2 */
+                          replacements, default 1e-3 */
   int check_every;     /* iterations per captured graph between host checks, default 16 */
   void* stream;        /* hipStream_t the caller orders work against, or NULL */
 } hom_options;

@@ -111,6 +111,7 @@ hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>
                       const double* dE, bool onQ, double* out);
 // launch helpers shared with the serving runtime
 int update_blocks(long S);
+int scalar_n0(const CellImpl* c);
 int partial_slots(const CellImpl* c);
 template <class T>
 int project_tiles(CellImpl* c);

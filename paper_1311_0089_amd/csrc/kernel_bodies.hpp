@@ -22,28 +22,52 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return (b % 8) * (n / 8) + b / 8;
 }
 
+// SL: layout of the scalar spectra (0: given at run time by the strides,
+// 1: column-major, 2: row-major); fixed at compile time in the specialised
+// kernels, so only one thread mapping is built
 struct ColGen {
   static constexpr int NT = kThreads;
   static constexpr int CP = 1;   // components per transform call
+  static constexpr int SL = 0;
   __device__ static int W(int w) { return w; }
   __device__ static int nfft(int n) { return n; }
   __device__ static int ntrial(int n) { return n; }
+  // LDS row length of the expand / project tiles ([row][component][column])
+  __device__ static int rowlen(int lw) { return lw; }
   template <class T, int S>
   __device__ static void fft(cpx<T>* lds, const FftPlan& P, int W, const cpx<T>* tw) {
     line_fft<T, S>(lds, P, LdsLines{W, 1, W, true}, tw);
   }
+  template <class T, int S>
+  __device__ static void fft_rows(cpx<T>* lds, const FftPlan& P, int W, const cpx<T>* tw) {
+    line_fft<T, S>(lds, P, LdsLines{W, 1, W, true}, tw);
+  }
 };
 
-template <class SP, int NTRIAL, int W_, int NT_>
+// an even row length of 8-byte or 16-byte elements is padded to the next odd
+// one where the expand / project tiles are written and read with axis 0
+// across the threads of a wave (column-major scalars): an even stride folds
+// those accesses onto few LDS banks
+__host__ __device__ constexpr int odd_rowlen(int lw) { return (lw > 1 && lw % 2 == 0) ? lw + 1 : lw; }
+
+template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0>
 struct ColStat {
   static constexpr int NT = NT_;
   static constexpr int CP = 1;
+  static constexpr int SL = SL_;
+  // only the column-major mapping (axis 0 across the threads) needs the pad
+  static constexpr int RL = (SL_ == 1) ? odd_rowlen(W_) : W_;
   __device__ static constexpr int W(int) { return W_; }
   __device__ static constexpr int nfft(int) { return SP::n; }
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
+  __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
   __device__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
     sfft<T, S, SP, W_, true, 1, W_, NT_>(lds, tw);
+  }
+  template <class T, int S>
+  __device__ static void fft_rows(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
+    sfft<T, S, SP, W_, true, 1, RL, NT_>(lds, tw);
   }
 };
 
@@ -54,12 +78,15 @@ template <class SP, int NTRIAL, int W_, int D_, int NT_>
 struct ColStatCP {
   static constexpr int NT = NT_;
   static constexpr int CP = D_;
+  static constexpr int SL = (D_ == 2) ? 1 : 2;   // the layout cells with D_ components use
+  static constexpr int RL = (SL == 1) ? odd_rowlen(D_ * W_) : D_ * W_;
   __device__ static constexpr int W(int) { return W_; }
   __device__ static constexpr int nfft(int) { return SP::n; }
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
+  __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
-  __device__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
-    sfft<T, S, SP, D_ * W_, true, 1, D_ * W_, NT_>(lds, tw);
+  __device__ static void fft_rows(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
+    sfft<T, S, SP, D_ * W_, true, 1, RL, NT_>(lds, tw);
   }
 };
 
@@ -151,6 +178,7 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
   const long ibase = (long)item * a.c_stride;
   const T beta = a.fuse ? T(a.sc[item].beta) : T(0);
   const int npos = n_in * W;
+  const bool colm = (P::SL == 0) ? (a.si == 1) : (P::SL == 1);
   cpx<T> s[PMAX];
   int row[PMAX];
 #pragma unroll
@@ -159,10 +187,12 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
     s[it] = cpx<T>{T(0), T(0)};
     row[it] = -1;
     if (f < npos) {
-      const int i = f / W, w = f % W;
+      // with column-major scalars axis 0 runs across the threads (contiguous
+      // loads), else the tile columns do
+      const int i = colm ? f % n_in : f / W, w = colm ? f / n_in : f % W;
       row[it] = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
       if (w < ncols) {
-        const long idx = ibase + (long)i * a.inner + col0 + w;
+        const long idx = ibase + (long)i * a.si + (long)(col0 + w) * a.sc_;
         if (a.fuse) {
           const cpx<T> rv = a.r[idx];
           cpx<T> pv = a.p[idx];
@@ -178,9 +208,9 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
   }
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
-  const int LW = CPN * W;
+  const int LW = P::rowlen(CPN * W);
   for (int al0 = 0; al0 < a.g.d; al0 += CPN) {
-    const int nc = min(CPN, a.g.d - al0);
+    constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     if (n_fft != n_in) {
       for (int f = threadIdx.x; f < n_fft * LW; f += NT) lds[f] = cpx<T>{T(0), T(0)};
       __syncthreads();
@@ -189,14 +219,14 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
     for (int it = 0; it < PMAX; ++it) {
       if (row[it] >= 0) {
         const int f = threadIdx.x + it * NT;
-        const int w = f % W;
+        const int i = colm ? f % n_in : f / W, w = colm ? f / n_in : f % W;
         T nv[3];
-        unit_normal<T>(a.g, kof(f / W, n_in), min(col0 + w, a.inner - 1), nv);
+        unit_normal<T>(a.g, kof(i, n_in), min(col0 + w, a.inner - 1), nv);
         for (int c = 0; c < nc; ++c) lds[row[it] * LW + c * W + w] = cscale(s[it], nv[al0 + c]);
       }
     }
     __syncthreads();
-    P::template fft<T, +1>(lds, a.plan, W, a.tw);
+    P::template fft_rows<T, +1>(lds, a.plan, W, a.tw);
     cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride;
     for (int f = threadIdx.x; f < n_fft * W * nc; f += NT) {
       const int w = f % W, t = f / W, c = t % nc, i = t / nc;
@@ -260,6 +290,7 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   const int col0 = tile * W;
   const int ncols = min(W, a.inner - col0);
   const int npos = n_out * W;
+  const bool colm = (P::SL == 0) ? (a.si == 1) : (P::SL == 1);
   cpx<T> acc[PMAX];
   int row[PMAX];
 #pragma unroll
@@ -268,15 +299,15 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
     const int f = threadIdx.x + it * NT;
     row[it] = -1;
     if (f < npos) {
-      const int i = f / W;
+      const int i = colm ? f % n_out : f / W;
       row[it] = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
     }
   }
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
-  const int LW = CPN * W;
+  const int LW = P::rowlen(CPN * W);
   for (int al0 = 0; al0 < a.d; al0 += CPN) {
-    const int nc = min(CPN, a.d - al0);
+    constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
     for (int f = threadIdx.x; f < n_fft * W * nc; f += NT) {
       const int w = f % W, t = f / W, c = t % nc, i = t / nc;
@@ -284,12 +315,12 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
                                             : cpx<T>{T(0), T(0)};
     }
     __syncthreads();
-    P::template fft<T, -1>(lds, a.plan, W, a.tw);
+    P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
 #pragma unroll
     for (int it = 0; it < PMAX; ++it) {
       if (row[it] >= 0) {
         const int f = threadIdx.x + it * NT;
-        const int i = f / W, w = f % W;
+        const int i = colm ? f % n_out : f / W, w = colm ? f / n_out : f % W;
         T nv[3];
         unit_normal<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1), nv);
         for (int c = 0; c < nc; ++c) {
@@ -306,10 +337,10 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
     const int f = threadIdx.x + it * NT;
-    if (row[it] >= 0 && (f % W) < ncols) {
-      const int i = f / W, w = f % W;
+    const int i = colm ? f % n_out : f / W, w = colm ? f / n_out : f % W;
+    if (row[it] >= 0 && w < ncols) {
       const int col = col0 + w;
-      const long idx = sb + (long)i * a.inner + col;
+      const long idx = sb + (long)i * a.si + (long)col * a.sc_;
       const double wt = ((col % a.g.H) == 0) ? 1.0 : 2.0;
       cpx<T> qv = cscale(acc[it], a.scale);
       if (a.epi == EPI_STORE) {

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
     rv.y -= alpha * qv.y;
     a.x[base + e] = xv;
     a.r[base + e] = rv;
-    const double wt = ((e % a.H) == 0) ? 1.0 : 2.0;
+    const double wt = (((e / a.n0) % a.H) == 0) ? 1.0 : 2.0;
     part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
   }
   part = block_sum<kThreads>(part);
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_outer_check(ItemScal* sc, const do
 __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64, cpx<float>* r32,
                                                           cpx<float>* p32, cpx<float>* x32,
                                                           long stride, long count, int H,
-                                                          ItemScal* outer, ItemScal* inner,
+                                                          int n0, ItemScal* outer, ItemScal* inner,
                                                           int max_iter, int keep_dir,
                                                           double* partials, int P,
                                                           const ItemScal* mask) {
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
     r32[base + e] = w;
     if (!keep_dir) p32[base + e] = w;
     x32[base + e] = cpx<float>{0.f, 0.f};
-    const double wt = ((e % H) == 0) ? 1.0 : 2.0;
+    const double wt = (((e / n0) % H) == 0) ? 1.0 : 2.0;
     part += wt * ((double)w.x * (double)w.x + (double)w.y * (double)w.y);
   }
   part = block_sum<kThreads>(part);
@@ -338,19 +338,16 @@ __global__ __launch_bounds__(kThreads) void k_a_range(const double* A, int d, in
   }
 }
 
-hipError_t a_field_range(const double* A, int d, int kind, long npts, hipStream_t s, double* lo,
-                         double* hi, int* flags) {
+hipError_t a_field_range(const double* A, int d, int kind, long npts, double* scratch,
+                         hipStream_t s, double* lo, double* hi, int* flags) {
   const int blocks = (int)std::max(1L, std::min((long)kRangeBlocks, (npts + kThreads - 1) / kThreads));
-  double* dout = nullptr;
-  hipError_t e = hipMalloc(&dout, sizeof(double) * 3 * blocks);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_a_range, dim3(blocks), dim3(kThreads), 0, s, A, d, kind, npts, dout);
-  e = hipGetLastError();
+  static_assert(3 * kRangeBlocks <= kQuadScratch, "range partials exceed the scratch buffer");
+  hipLaunchKernelGGL(k_a_range, dim3(blocks), dim3(kThreads), 0, s, A, d, kind, npts, scratch);
+  hipError_t e = hipGetLastError();
   std::vector<double> h((size_t)3 * blocks);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h.data(), dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(h.data(), scratch, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(dout);
   if (e != hipSuccess) return e;
   *lo = INFINITY;
   *hi = 0.0;
@@ -552,11 +549,12 @@ hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int n
   return hipGetLastError();
 }
 hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float>* p32,
-                              cpx<float>* x32, long stride, long count, int H, ItemScal* outer,
-                              ItemScal* inner, int max_iter, int keep_dir, double* partials, int P,
-                              int blocks, int items, hipStream_t s, const ItemScal* mask) {
+                              cpx<float>* x32, long stride, long count, int H, int n0,
+                              ItemScal* outer, ItemScal* inner, int max_iter, int keep_dir,
+                              double* partials, int P, int blocks, int items, hipStream_t s,
+                              const ItemScal* mask) {
   launch_k(k_inner_start, dim3(blocks, items), dim3(kThreads), 0, s, r64, r32, p32, x32,
-                     stride, count, H, outer, inner, max_iter, keep_dir, partials, P, mask);
+                     stride, count, H, n0, outer, inner, max_iter, keep_dir, partials, P, mask);
   return hipGetLastError();
 }
 hipError_t launch_inner_init(ItemScal* inner, const double* partials, int P, int nparts, int items,

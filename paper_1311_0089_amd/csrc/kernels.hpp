@@ -52,12 +52,15 @@ struct NormalGeo {
 // pass along axis 0 from the scalar potential: X_a = F_0^-1 Pad(n_a c)
 template <class T>
 struct ColExpandArgs {
-  const cpx<T>* c;  // scalar spectrum [item][n_in][inner]
+  // scalar spectra: element (axis-0 index i, column) at i * si + column * sc
+  // (row-major: si = inner, sc = 1; column-major: si = 1, sc = n_in)
+  const cpx<T>* c;  // scalar spectrum
   const cpx<T>* r;  // fuse: p <- r + beta p, then expand p (c must equal p)
   cpx<T>* p;
   cpx<T>* X;        // [item][d][n_fft][inner]
   long c_stride, X_stride, X_cstride;
   int n_in, n_fft, inner, W, fuse;
+  int si, sc_;      // scalar strides (see above); si == 1 maps axis 0 across threads
   NormalGeo g;
   FftPlan plan;
   const cpx<T>* tw;
@@ -83,7 +86,7 @@ template <class T>
 struct ColProjectArgs {
   const cpx<T>* X;   // [item][d][n_fft][inner]
   long X_stride, X_cstride;
-  cpx<T>* q;         // [item][n_out][inner]
+  cpx<T>* q;         // scalar spectrum, layout as in ColExpandArgs (si, sc_)
   long s_stride;     // item stride of all scalar spectra below
   const cpx<T>* p;   // EPI_STORE: partial (p, q) when non-null
   cpx<T>* r;         // EPI_RHS: r = p = q = -n.F[..]; x = 0   EPI_RESID: r = b - q
@@ -93,6 +96,7 @@ struct ColProjectArgs {
   double* partials;  // [item][P]
   int P;
   int n_fft, n_out, inner, W, epi, d;
+  int si, sc_;
   T scale;
   NormalGeo g;
   FftPlan plan;
@@ -128,6 +132,7 @@ struct CgUpdateArgs {
   const cpx<T>* q;
   long stride, count;   // item stride and elements per item
   int H;                // weight 1 for h = 0, 2 otherwise
+  int n0;               // column = e / n0 (column-major scalars; 1 for row-major)
   double* partials;
   int P;
   ItemScal* sc;
@@ -244,8 +249,10 @@ __host__ __device__ inline bool point_range(int d, int kind, const double* v, do
 
 // Range of the whole field A [nA][npts] (device pointer): lo, hi and flags
 // (bit 0: a value not finite, bit 1: a point not positive definite).
-hipError_t a_field_range(const double* A, int d, int kind, long npts, hipStream_t s, double* lo,
-                         double* hi, int* flags);
+// scratch: device buffer of kQuadScratch doubles.
+constexpr long kQuadScratch = 1024 * 18 + 64;
+hipError_t a_field_range(const double* A, int d, int kind, long npts, double* scratch,
+                         hipStream_t s, double* lo, double* hi, int* flags);
 
 // Arm HIP events for the next kernel launched by this thread through the
 // launchers below: hipExtLaunchKernel records them from the dispatch itself.
@@ -269,7 +276,8 @@ hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int n
 // reset); keep_dir = 1 replaces the recursive residual and keeps p32.  The
 // outer counter of residual evaluations is incremented.
 hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float>* p32,
-                              cpx<float>* x32, long stride, long count, int H, ItemScal* outer,
+                              cpx<float>* x32, long stride, long count, int H, int n0,
+                              ItemScal* outer,
                               ItemScal* inner, int max_iter, int keep_dir, double* partials, int P,
                               int blocks, int items, hipStream_t s, const ItemScal* mask = nullptr);
 // inner scalars after launch_inner_start: rho = (r32, r32); a kept direction

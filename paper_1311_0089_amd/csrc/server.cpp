@@ -161,7 +161,7 @@ SizeClass* hom_server::make_class(const CellImpl* like, size_t free_bytes) {
   if (err == hipSuccess) err = hipMalloc(&k->dE, sizeof(double) * k->items * k->dd);
   if (err == hipSuccess) err = hipMalloc(&k->mask, sizeof(ItemScal) * k->items);
   if (err == hipSuccess) err = hipMalloc(&k->ebuf, sizeof(double) * (size_t)k->dd * k->dd * e->nQ);
-  if (err == hipSuccess && !e->quad) err = hipMalloc(&e->quad, sizeof(double) * (18 * 1024 + 64));
+  if (err == hipSuccess && !e->quad) err = hipMalloc(&e->quad, sizeof(double) * kQuadScratch);
   // every item starts inactive
   if (err == hipSuccess) err = launch_set_scal(e->w64.sc, k->items, 1.0, 0, 0, e->stream);
   if (err == hipSuccess) err = launch_set_scal(e->w32.sc, k->items, 1.0, 0, 0, e->stream);
@@ -243,7 +243,7 @@ hipError_t hom_server::admit(SizeClass* k, std::vector<std::pair<int, Req*>>& ad
     err = launch_outer_check(w.sc, w.part, P, project_tiles<double>(e), k->items, 1, e->stream,
                              k->mask);
   if (err == hipSuccess)
-    err = launch_inner_start(w.r, w32.r, w32.p, w32.x, e->S, e->S, e->H, w.sc, w32.sc,
+    err = launch_inner_start(w.r, w32.r, w32.p, w32.x, e->S, e->S, e->H, scalar_n0(e), w.sc, w32.sc,
                              opt.max_iter, 0, w32.part, P, ub, k->items, e->stream, k->mask);
   if (err == hipSuccess)
     err = launch_inner_init(w32.sc, w32.part, P, ub, k->items, w.sc, opt.inner_tol, kTolSafety,
@@ -419,7 +419,7 @@ hipError_t hom_server::refine_and_retire(SizeClass* k) {
     err = launch_outer_check(w.sc, w.part, P, project_tiles<double>(e), k->items, 0, e->stream,
                              k->mask);
   if (err == hipSuccess)
-    err = launch_inner_start(w.r, w32.r, w32.p, w32.x, e->S, e->S, e->H, w.sc, w32.sc,
+    err = launch_inner_start(w.r, w32.r, w32.p, w32.x, e->S, e->S, e->H, scalar_n0(e), w.sc, w32.sc,
                              opt.max_iter, 1, w32.part, P, ub, k->items, e->stream, k->mask);
   if (err == hipSuccess)
     err = launch_inner_init(w32.sc, w32.part, P, ub, k->items, w.sc, opt.inner_tol, kTolSafety,

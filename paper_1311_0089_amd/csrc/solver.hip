@@ -195,6 +195,16 @@ static NormalGeo normal_geo(const CellImpl* c) {
 
 static long inner0(const CellImpl* c) { return (c->dd == 3) ? (long)c->N[1] * c->H : c->H; }
 
+// Layout of the scalar spectra (c, r, p, q, b, x) of an item: 2-D cells keep
+// them column-major (axis 0 contiguous), so the first-axis passes, whose
+// tiles are few columns wide there, load and store whole cache lines; 3-D
+// cells keep them row-major, where the tiles are wide enough already.
+static bool scalar_colmajor(const CellImpl* c) { return c->dd == 2; }
+static int scalar_si(const CellImpl* c) { return scalar_colmajor(c) ? 1 : (int)inner0(c); }
+static int scalar_sc(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 1; }
+// elements per column as the CG vector kernels see them (1: row-major)
+int scalar_n0(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 1; }
+
 template <class T>
 static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse,
                                int G0, ItemScal* sc) {
@@ -207,6 +217,8 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.p = w.p;
   a.X = w.X1;
   a.c_stride = c->S;
+  a.si = scalar_si(c);
+  a.sc_ = scalar_sc(c);
   a.X_stride = (long)c->dd * c->Xe;
   a.X_cstride = c->Xe;
   a.n_in = c->N[0];
@@ -324,6 +336,8 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.X_cstride = c->Xe;
   a.q = out;
   a.s_stride = c->S;
+  a.si = scalar_si(c);
+  a.sc_ = scalar_sc(c);
   a.p = pdot;
   a.r = r;
   a.pp = pp;
@@ -501,6 +515,7 @@ static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K) {
       u.stride = c->S;
       u.count = c->S;
       u.H = c->H;
+      u.n0 = scalar_n0(c);
       u.partials = w.part2;
       u.P = P;
       u.sc = w.sc;
@@ -600,6 +615,18 @@ static hipError_t read_scal(CellImpl* c, const ItemScal* d, int items, std::vect
   return e;
 }
 
+static hipError_t read_scal2(CellImpl* c, const ItemScal* d1, std::vector<ItemScal>& h1,
+                             const ItemScal* d2, std::vector<ItemScal>& h2, int items) {
+  h1.resize(items);
+  h2.resize(items);
+  hipError_t e = hipMemcpyAsync(h1.data(), d1, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h2.data(), d2, sizeof(ItemScal) * items, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
 // run CG until every item is inactive
 template <class T>
 static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemScal>& hs) {
@@ -677,7 +704,7 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
   }
   if ((e = pipe_synth(c, c->w64, L, x, dE, true, eQ)) != hipSuccess) return e;
   if (!c->quad) {
-    if ((e = hipMalloc(&c->quad, sizeof(double) * (1024 * 18 + 64))) != hipSuccess) return e;
+    if ((e = hipMalloc(&c->quad, sizeof(double) * kQuadScratch)) != hipSuccess) return e;
   }
   const int blocks = (int)std::min<long>(1024, (c->nQ + kThreads - 1) / kThreads);
   std::vector<double> hW((size_t)L * L, 0.0), hJ((size_t)L * c->dd, 0.0);
@@ -821,7 +848,7 @@ hom_status hom_options_default(hom_options* o) {
   o->Y[0] = o->Y[1] = o->Y[2] = 0.5;
   o->max_iter = 10000;
   o->max_outer = 100;
-  o->inner_tol = 1e-2;
+  o->inner_tol = 1e-3;
   o->check_every = 16;
   o->stream = nullptr;
   return HOM_OK;
@@ -910,6 +937,10 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   }
   c->d = d;
   c->opt = o;
+  if (!c->quad && (e = hipMalloc(&c->quad, sizeof(double) * kQuadScratch)) != hipSuccess) {
+    pool_put(c);
+    return dev_status(e);
+  }
   // A goes to the device as given (FP64), is validated there (A2: finite,
   // symmetric positive definite at every point; contrast from the eigenvalue
   // range) and converted to the FP32 copy of the mixed path
@@ -920,8 +951,8 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   double lo = 0.0, hi = 0.0;
   int flags = 0;
   if (e == hipSuccess)
-    e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, c->stream, &lo, &hi,
-                      &flags);
+    e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, c->quad, c->stream,
+                      &lo, &hi, &flags);
   if (e == hipSuccess && flags == 0) e = launch_convert(c->A64, c->A32, (long)nAd, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -991,8 +1022,10 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
       break;
     if ((e = pipe_rhs<double>(c, w, L, dE, nullptr)) != hipSuccess) break;
     const int tiles64 = project_tiles<double>(c);
-    std::vector<double> bb;   // (b, b) per load case, for the true relative residual
-    if ((e = sum_partials_host(c, w.part, L, tiles64, bb)) != hipSuccess) break;
+    // (b, b) per load case, for the true relative residual (the mixed path's
+    // outer scalars keep it as rho0)
+    std::vector<double> bb;
+    if (!mixed && (e = sum_partials_host(c, w.part, L, tiles64, bb)) != hipSuccess) break;
     if (!mixed) {
       if (strain0 && (e = warm_start(c, L, strain0)) != hipSuccess) break;
       // rho0 = (r0, r0): of b, or of the warm residual written by warm_start
@@ -1019,7 +1052,8 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           break;
       }
       const int ub = update_blocks(c->S);
-      if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, outer, w32.sc,
+      if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, scalar_n0(c), outer,
+                                  w32.sc,
                                   c->opt.max_iter, 0, w32.part, P, ub, L, c->stream)) != hipSuccess)
         break;
       if ((e = launch_inner_init(w32.sc, w32.part, P, ub, L, outer, c->opt.inner_tol, kTolSafety,
@@ -1062,15 +1096,15 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream, w.mask)) !=
               hipSuccess)
             break;
-          if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, outer, w32.sc,
+          if ((e = launch_inner_start(w.r, w32.r, w32.p, w32.x, c->S, c->S, c->H, scalar_n0(c), outer,
+                                  w32.sc,
                                       c->opt.max_iter, 1, w32.part, P, ub, L, c->stream,
                                       w.mask)) != hipSuccess)
             break;
           if ((e = launch_inner_init(w32.sc, w32.part, P, ub, L, outer, c->opt.inner_tol,
                                      kTolSafety, c->stream, w.mask)) != hipSuccess)
             break;
-          if ((e = read_scal(c, outer, L, ho)) != hipSuccess) break;
-          if ((e = read_scal(c, w32.sc, L, hi)) != hipSuccess) break;
+          if ((e = read_scal2(c, outer, ho, w32.sc, hi, L)) != hipSuccess) break;
           for (int i = 0; i < L; ++i) {
             if (hm[i].active) plan.reset(i);
             live[i] = ho[i].active;
@@ -1092,7 +1126,10 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
     if (mixed) {
       std::vector<ItemScal> ho;
       if ((e = read_scal(c, w.sc, L, ho)) != hipSuccess) break;
-      for (int i = 0; i < L; ++i) rr.push_back(ho[i].rho);
+      for (int i = 0; i < L; ++i) {
+        rr.push_back(ho[i].rho);
+        bb.push_back(ho[i].rho0);
+      }
     } else {
       if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.q, nullptr, w.b, nullptr,
                                   w.part2)) != hipSuccess)
@@ -1262,6 +1299,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
       u.stride = c->S;
       u.count = c->S;
       u.H = c->H;
+      u.n0 = scalar_n0(c);
       u.partials = w.part2;
       u.P = P;
       u.sc = w.sc;

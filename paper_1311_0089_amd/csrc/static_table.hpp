@@ -17,15 +17,23 @@ namespace hom {
 template <class T, class SP, int NTRIAL, int W, int NT>
 struct RegCol {
   static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
-  static constexpr size_t lds = (size_t)SP::len * W * sizeof(cpx<T>);
-  static_assert(lds <= 66 * 1024 + 512, "column tile exceeds the LDS budget");
+  // the column-major expand / project tiles use the padded row length
+  static constexpr size_t lds = (size_t)SP::len * odd_rowlen(W) * sizeof(cpx<T>);
+  static constexpr size_t lds_rm = (size_t)SP::len * W * sizeof(cpx<T>);
+  static_assert(lds <= 150 * 1024, "column tile exceeds the LDS of a CU");
   static_assert(PMAX <= 32, "too many positions per thread");
   RegCol() {
+    // expand / project per scalar layout: column-major for 2-D cells,
+    // row-major for 3-D cells; the plain passes do not touch scalars
+    using P2 = ColStat<SP, NTRIAL, W, NT, 1>;
+    using P3 = ColStat<SP, NTRIAL, W, NT, 2>;
+    add(KK_EXPAND, (const void*)&k_col_expand<T, P2, PMAX>, 2, lds);
+    add(KK_PROJECT, (const void*)&k_col_project<T, P2, PMAX>, 2, lds);
+    add(KK_EXPAND, (const void*)&k_col_expand<T, P3, PMAX>, 3, lds_rm);
+    add(KK_PROJECT, (const void*)&k_col_project<T, P3, PMAX>, 3, lds_rm);
     using P = ColStat<SP, NTRIAL, W, NT>;
-    add(KK_EXPAND, (const void*)&k_col_expand<T, P, PMAX>);
-    add(KK_PROJECT, (const void*)&k_col_project<T, P, PMAX>);
-    add(KK_PLAIN_INV, (const void*)&k_col_plain<T, P, +1>);
-    add(KK_PLAIN_FWD, (const void*)&k_col_plain<T, P, -1>);
+    add(KK_PLAIN_INV, (const void*)&k_col_plain<T, P, +1>, 0, lds_rm);
+    add(KK_PLAIN_FWD, (const void*)&k_col_plain<T, P, -1>, 0, lds_rm);
   }
   template <int... Rs>
   static void fill(StaticKernel& k, Rad<Rs...>) {
@@ -33,17 +41,17 @@ struct RegCol {
     k.nst = (int)sizeof...(Rs);
     for (int i = 0; i < k.nst; ++i) k.rad[i] = r[i];
   }
-  static void add(int kind, const void* fn) {
+  static void add(int kind, const void* fn, int d, size_t lds_bytes) {
     StaticKernel k{};
     k.kind = kind;
     k.esz = (int)sizeof(cpx<T>);
     k.n = SP::n;
     k.ntrial = NTRIAL;
-    k.d = 0;
+    k.d = d;
     k.fn = fn;
     k.W = W;
     k.NT = NT;
-    k.lds = lds;
+    k.lds = lds_bytes;
     k.len = SP::len;
     k.blue = SP::blue;
     fill(k, typename SP::radices{});
@@ -56,7 +64,8 @@ struct RegCol {
 template <class T, class SP, int NTRIAL, int W, int D, int NT>
 struct RegColCP {
   static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
-  static constexpr size_t lds = (size_t)SP::len * W * D * sizeof(cpx<T>);
+  static constexpr size_t lds =
+      (size_t)SP::len * (D == 2 ? odd_rowlen(W * D) : W * D) * sizeof(cpx<T>);
   static_assert(lds <= 150 * 1024, "column tile exceeds the LDS of a CU");
   static_assert(PMAX <= 32, "too many positions per thread");
   RegColCP() {

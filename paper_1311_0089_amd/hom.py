@@ -121,7 +121,7 @@ def tune_load(path: str) -> bool:
     return lib().hom_tune_load(path.encode()) == 0
 
 
-def make_options(scheme=GANI, prec=FP64, Y=None, max_iter=10000, max_outer=100, inner_tol=1e-2,
+def make_options(scheme=GANI, prec=FP64, Y=None, max_iter=10000, max_outer=100, inner_tol=1e-3,
                  check_every=16, stream=None) -> Options:
     o = Options()
     lib().hom_options_default(ctypes.byref(o))
@@ -142,7 +142,7 @@ class Cell:
     scheme: GANI (A on N) or GA (A on 2N-1); prec: FP64 or MIXED."""
 
     def __init__(self, A, N, kind=ISO, scheme=GANI, prec=FP64, Y=None, max_iter=10000,
-                 max_outer=100, inner_tol=1e-2, check_every=16):
+                 max_outer=100, inner_tol=1e-3, check_every=16):
         import torch
         self.N = tuple(int(n) for n in N)
         self.d = len(self.N)
@@ -253,7 +253,7 @@ class Cell:
 class Server:
     """Continuous-batching request loop (see hom.h)."""
 
-    def __init__(self, hbm_budget_bytes: int, prec=MIXED, max_iter=10000, inner_tol=1e-2,
+    def __init__(self, hbm_budget_bytes: int, prec=MIXED, max_iter=10000, inner_tol=1e-3,
                  check_every=16):
         self._h = ctypes.c_void_p(None)
         o = make_options(GANI, prec, None, max_iter, 100, inner_tol, check_every, None)
