@@ -105,7 +105,7 @@ hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemSc
 template <class T>
 hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse, int epi,
                       cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
-                      double* partials);
+                      double* partials, const CgFuse* cg = nullptr);
 // real strain on grid G (G = N or Q) from the potential: e = E + F_G^-1 Pad(n c)
 hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>* cin,
                       const double* dE, bool onQ, double* out);

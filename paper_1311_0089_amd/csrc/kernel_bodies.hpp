@@ -161,6 +161,50 @@ __device__ __forceinline__ double sum_partials(const double* p, int nparts) {
   return block_sum<kThreads>(v);
 }
 
+// the same fixed-order sum for a workgroup of NT threads, returned to every
+// thread (each workgroup that needs a CG scalar derives it identically)
+template <int NT>
+__device__ __forceinline__ double sum_partials_all(const double* p, int nparts) {
+  __shared__ double total;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) v += p[i];
+  v = block_sum<NT>(v);
+  if (threadIdx.x == 0) total = v;
+  __syncthreads();
+  v = total;
+  __syncthreads();
+  return v;
+}
+
+// CG bookkeeping of one completed update from the sum s = (r, r): iteration
+// count, stopping test (relative residual or budget), beta and rho.  One
+// thread of one workgroup per item runs it, in a kernel whose other
+// workgroups do not read these fields.
+__device__ __forceinline__ void cg_book(ItemScal& q, double s) {
+  q.iters += 1;
+  if (!isfinite(s)) {
+    q.status = -5;
+    q.active = 0;
+    return;
+  }
+  // beta is kept also when the item stops: a residual replacement of the
+  // mixed solver rescales it and carries the search direction on
+  q.beta = s / q.rho;
+  if (sqrt(s / q.rho0) <= q.tol) {
+    q.conv = 1;
+    q.active = 0;
+  } else if (q.iters >= q.max_iter) {
+    q.active = 0;
+  }
+  q.rho = s;
+}
+
+// the decision cg_book will take, derived by every workgroup of the next
+// expansion: 1 if the item stops after its last update
+__device__ __forceinline__ bool cg_stops(const ItemScal& q, double s) {
+  return !isfinite(s) || sqrt(s / q.rho0) <= q.tol || q.iters + 1 >= q.max_iter;
+}
+
 // ---------------------------------------------------------------------------
 // axis 0 from the scalar potential (optionally fusing p <- r + beta p):
 // X_a = F_0^-1 Pad(n_a c) for every component a
@@ -176,7 +220,14 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
   const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
   const int ncols = min(W, a.inner - col0);
   const long ibase = (long)item * a.c_stride;
-  const T beta = a.fuse ? T(a.sc[item].beta) : T(0);
+  T beta = a.fuse ? T(a.sc[item].beta) : T(0);
+  if (a.fuse && a.rr_part && !a.sc[item].fresh) {
+    // s = (r, r) of the last update; its bookkeeping runs in the projection
+    const double s = sum_partials_all<NT>(a.rr_part + (long)item * a.P, a.rr_n);
+    const ItemScal q = a.sc[item];
+    if (cg_stops(q, s)) return;
+    beta = T(s / q.rho);
+  }
   const int npos = n_in * W;
   const bool colm = (P::SL == 0) ? (a.si == 1) : (P::SL == 1);
   cpx<T> s[PMAX];
@@ -367,6 +418,16 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   if (a.partials) {
     part = block_sum<NT>(part);
     if (threadIdx.x == 0) a.partials[(long)item * a.P + tile] = part;
+  }
+  if (a.rr_part && blockIdx.x == 0) {
+    // bookkeeping of the update before this iteration's expansion (that
+    // expansion has finished reading rho; no other workgroup here reads it)
+    const bool fresh = a.sc[item].fresh != 0;
+    const double s = fresh ? 0.0 : sum_partials_all<NT>(a.rr_part + (long)item * a.P, a.rr_n);
+    if (threadIdx.x == 0) {
+      if (fresh) a.sc[item].fresh = 0;
+      else cg_book(a.sc[item], s);
+    }
   }
 }
 

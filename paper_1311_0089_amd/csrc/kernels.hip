@@ -85,7 +85,23 @@ template <class T>
 __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   const int item = blockIdx.y;
   if (!a.sc[item].active) return;
-  const T alpha = T(a.sc[item].alpha);
+  // alpha = rho / (p, q), derived by every workgroup from the projection's
+  // partials in the same order
+  const double g = sum_partials_all<kThreads>(a.pq_part + (long)item * a.P, a.pq_n);
+  if (!(g > 0.0) || !isfinite(g)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sc[item].gamma = g;
+      a.sc[item].status = -5;
+      a.sc[item].active = 0;
+    }
+    return;
+  }
+  const double alpha64 = a.sc[item].rho / g;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.sc[item].gamma = g;
+    a.sc[item].alpha = alpha64;
+  }
+  const T alpha = T(alpha64);
   const long base = (long)item * a.stride;
   double part = 0.0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < a.count;
@@ -116,6 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(ItemScal* sc, const double
     q.iters = 0;
     q.beta = 0.0;
     q.alpha = 0.0;
+    q.fresh = 1;
     q.status = 0;
     q.conv = (s == 0.0) ? 1 : 0;
     q.active = (s > 0.0 && isfinite(s) && q.max_iter > 0) ? 1 : 0;
@@ -123,47 +140,14 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(ItemScal* sc, const double
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_cg_alpha(ItemScal* sc, const double* partials, int P,
-                                                       int nparts) {
+__global__ __launch_bounds__(kThreads) void k_cg_finalize(ItemScal* sc, const double* partials,
+                                                          int P, int nparts) {
   const int item = blockIdx.x;
-  if (!sc[item].active) return;
-  const double g = sum_partials(partials + (long)item * P, nparts);
-  if (threadIdx.x == 0) {
-    ItemScal& q = sc[item];
-    q.gamma = g;
-    if (!(g > 0.0) || !isfinite(g)) {
-      q.status = -5;
-      q.active = 0;
-      q.alpha = 0.0;
-    } else {
-      q.alpha = q.rho / g;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_cg_beta(ItemScal* sc, const double* partials, int P,
-                                                      int nparts) {
-  const int item = blockIdx.x;
-  if (!sc[item].active) return;
+  if (!sc[item].active || sc[item].fresh) return;
   const double s = sum_partials(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
-    ItemScal& q = sc[item];
-    q.iters += 1;
-    if (!isfinite(s)) {
-      q.status = -5;
-      q.active = 0;
-      return;
-    }
-    // beta is kept also when the item stops: a residual replacement of the
-    // mixed solver rescales it and carries the search direction on
-    q.beta = s / q.rho;
-    if (sqrt(s / q.rho0) <= q.tol) {
-      q.conv = 1;
-      q.active = 0;
-    } else if (q.iters >= q.max_iter) {
-      q.active = 0;
-    }
-    q.rho = s;
+    cg_book(sc[item], s);
+    sc[item].fresh = 1;
   }
 }
 
@@ -254,6 +238,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_init(ItemScal* inner, const 
     const double rel = sqrt(s);
     q.tol = (rel > 0.0) ? fmax(eta, theta * outer[item].tol / rel) : eta;
     q.alpha = 0.0;
+    q.fresh = 1;
     q.status = isfinite(s) ? 0 : -5;
     q.conv = (s == 0.0) ? 1 : 0;
     q.active = (s > 0.0 && isfinite(s) && q.iters < q.max_iter) ? 1 : 0;
@@ -532,14 +517,9 @@ hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int npart
   launch_k(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask);
   return hipGetLastError();
 }
-hipError_t launch_cg_alpha(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                           hipStream_t s) {
-  launch_k(k_cg_alpha, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
-  return hipGetLastError();
-}
-hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                          hipStream_t s) {
-  launch_k(k_cg_beta, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
+hipError_t launch_cg_finalize(ItemScal* sc, const double* partials, int P, int nparts, int items,
+                              hipStream_t s) {
+  launch_k(k_cg_finalize, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
   return hipGetLastError();
 }
 hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int nparts, int items,

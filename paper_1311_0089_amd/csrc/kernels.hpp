@@ -27,6 +27,14 @@ constexpr int kThreads = 256;
 // tolerance, so the FP64 residual that replaces it usually passes the test
 constexpr double kTolSafety = 0.5;
 
+// a CG iteration's fused scalar work: the (r, r) partials of the last update
+// (rr, rr_n per item, stride P) from which the expansion derives beta and the
+// stopping test and the projection does the bookkeeping
+struct CgFuse {
+  const double* rr;
+  int rr_n;
+};
+
 // per-item solver scalars, device resident
 struct ItemScal {
   double rho, rho0, gamma, alpha, beta, tol;
@@ -35,7 +43,8 @@ struct ItemScal {
   int status;    // 0, or -5 on breakdown
   int conv;      // 1 once the stopping test passed
   int max_iter;
-  int pad;
+  int fresh;     // 1: beta and the stopping test are current (set at a (re)start and by
+                 // the end-of-launch bookkeeping); 0: the next expansion derives them
 };
 
 enum { EPI_STORE = 0, EPI_RHS = 1, EPI_RESID = 2 };
@@ -61,6 +70,10 @@ struct ColExpandArgs {
   long c_stride, X_stride, X_cstride;
   int n_in, n_fft, inner, W, fuse;
   int si, sc_;      // scalar strides (see above); si == 1 maps axis 0 across threads
+  // fused CG step (fuse != 0): partials of (r, r) left by the last update,
+  // from which every workgroup derives beta and the stopping test itself
+  const double* rr_part;
+  int rr_n, P;
   NormalGeo g;
   FftPlan plan;
   const cpx<T>* tw;
@@ -97,6 +110,10 @@ struct ColProjectArgs {
   int P;
   int n_fft, n_out, inner, W, epi, d;
   int si, sc_;
+  // CG bookkeeping in workgroup 0 (rr_part non-null): iteration count,
+  // stopping test and rho from the (r, r) partials of the last update
+  const double* rr_part;
+  int rr_n;
   T scale;
   NormalGeo g;
   FftPlan plan;
@@ -136,6 +153,10 @@ struct CgUpdateArgs {
   double* partials;
   int P;
   ItemScal* sc;
+  // partials of (p, q) left by the projection: every workgroup derives
+  // alpha = rho / (p, q) itself
+  const double* pq_part;
+  int pq_n;
 };
 
 // compile-time specialised pass kernels, registered by kernels_static*.hip
@@ -261,10 +282,10 @@ void arm_launch_events(hipEvent_t start, hipEvent_t stop);
 // mask (nullable): only items active in the mask are touched
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
                           hipStream_t s, const ItemScal* mask = nullptr);
-hipError_t launch_cg_alpha(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                           hipStream_t s);
-hipError_t launch_cg_beta(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                          hipStream_t s);
+// end-of-launch bookkeeping of the last update: iteration count, stopping
+// test, beta and rho from its (r, r) partials; marks the scalars fresh
+hipError_t launch_cg_finalize(ItemScal* sc, const double* partials, int P, int nparts, int items,
+                              hipStream_t s);
 // outer (FP64 refinement) residual check: rho = sum partials; stop when
 // sqrt(rho / rho0) <= tol or after max_iter refinement steps; the first call
 // (init != 0) sets rho0.

@@ -207,7 +207,7 @@ int scalar_n0(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 1; }
 
 template <class T>
 static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse,
-                               int G0, ItemScal* sc) {
+                               int G0, ItemScal* sc, const CgFuse* cg = nullptr) {
   const DevPlan* p0;
   hipError_t e = get_dev_plan(G0, &p0);
   if (e != hipSuccess) return e;
@@ -225,6 +225,11 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.n_fft = G0;
   a.inner = (int)inner0(c);
   a.fuse = fuse;
+  if (cg) {
+    a.rr_part = cg->rr;
+    a.rr_n = cg->rr_n;
+  }
+  a.P = partial_slots(c);
   a.g = normal_geo(c);
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
@@ -325,7 +330,7 @@ template <class T>
 static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>* X, int G0,
                                 int epi, cpx<T>* out, const cpx<T>* pdot, cpx<T>* r, cpx<T>* pp,
                                 cpx<T>* x, const cpx<T>* b, double* partials, ItemScal* sc,
-                                int* tiles) {
+                                int* tiles, const CgFuse* cg = nullptr) {
   const DevPlan* p0;
   hipError_t e = get_dev_plan(G0, &p0);
   if (e != hipSuccess) return e;
@@ -350,6 +355,10 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.inner = (int)inner0(c);
   a.epi = epi;
   a.d = c->dd;
+  if (cg) {
+    a.rr_part = cg->rr;
+    a.rr_n = cg->rr_n;
+  }
   a.scale = T(1.0 / (double)G0);
   a.g = normal_geo(c);
   a.plan = p0->p;
@@ -384,10 +393,10 @@ int project_tiles(CellImpl* c) {
 template <class T>
 hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse, int epi,
                       cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
-                      double* partials) {
+                      double* partials, const CgFuse* cg) {
   hipError_t e;
   const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
-  if ((e = stage_expand<T>(c, w, items, in, fuse, Q0, sc)) != hipSuccess) return e;
+  if ((e = stage_expand<T>(c, w, items, in, fuse, Q0, sc, cg)) != hipSuccess) return e;
   if (c->dd == 3) {
     if ((e = stage_axis1<T>(c, w, items, +1, Q0, Q1, w.X1, w.X2, sc)) != hipSuccess) return e;
     if ((e = stage_row<T>(c, items, ROW_APPLY, w.X2, w.X2, Q0, Q1, Q2, nullptr, nullptr, nullptr,
@@ -401,7 +410,7 @@ hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int 
   }
   cpx<T>* rr = (epi == EPI_RESID) ? out : nullptr;
   return stage_project<T>(c, w, items, w.X1, Q0, epi, out, pdot, rr, nullptr, nullptr, b,
-                          partials, sc, nullptr);
+                          partials, sc, nullptr, cg);
 }
 
 template <class T>
@@ -485,10 +494,10 @@ hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double
 
 template hipError_t pipe_apply<float>(CellImpl*, Work<float>&, int, const cpx<float>*, int, int,
                                       cpx<float>*, const cpx<float>*, const cpx<float>*, ItemScal*,
-                                      double*);
+                                      double*, const CgFuse*);
 template hipError_t pipe_apply<double>(CellImpl*, Work<double>&, int, const cpx<double>*, int, int,
                                        cpx<double>*, const cpx<double>*, const cpx<double>*,
-                                       ItemScal*, double*);
+                                       ItemScal*, double*, const CgFuse*);
 template hipError_t pipe_rhs<float>(CellImpl*, Work<float>&, int, const double*, ItemScal*);
 template int project_tiles<float>(CellImpl*);
 template int project_tiles<double>(CellImpl*);
@@ -498,31 +507,41 @@ template hipError_t pipe_rhs<double>(CellImpl*, Work<double>&, int, const double
 // CG iterations, captured K at a time into a HIP graph
 // ---------------------------------------------------------------------------
 template <class T>
-static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K) {
+static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles) {
+  CgUpdateArgs<T> u{};
+  u.x = w.x;
+  u.r = w.r;
+  u.p = w.p;
+  u.q = w.q;
+  u.stride = c->S;
+  u.count = c->S;
+  u.H = c->H;
+  u.n0 = scalar_n0(c);
+  u.partials = w.part2;
+  u.P = partial_slots(c);
+  u.sc = w.sc;
+  u.pq_part = w.part;
+  u.pq_n = tiles;
+  return u;
+}
+
+template <class T>
+static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K, bool finalize = true) {
+  // one iteration: expansion (beta and stopping test from the last update's
+  // (r, r) partials, p <- r + beta p), the operator's passes, projection
+  // (q, (p, q) partials, bookkeeping of the last update), update (alpha from
+  // the (p, q) partials, x and r, (r, r) partials); after K iterations the
+  // last update is booked so the host reads current scalars
   hipError_t e = hipSuccess;
   const int P = partial_slots(c);
   const int tiles = project_tiles<T>(c);
   const int ub = update_blocks(c->S);
+  const CgFuse cg{w.part2, ub};
   for (int k = 0; k < K && e == hipSuccess; ++k) {
-    e = pipe_apply<T>(c, w, items, w.p, 1, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part);
-    if (e == hipSuccess) e = launch_cg_alpha(w.sc, w.part, P, tiles, items, c->stream);
-    if (e == hipSuccess) {
-      CgUpdateArgs<T> u{};
-      u.x = w.x;
-      u.r = w.r;
-      u.p = w.p;
-      u.q = w.q;
-      u.stride = c->S;
-      u.count = c->S;
-      u.H = c->H;
-      u.n0 = scalar_n0(c);
-      u.partials = w.part2;
-      u.P = P;
-      u.sc = w.sc;
-      e = launch_cg_update<T>(u, items, ub, c->stream);
-    }
-    if (e == hipSuccess) e = launch_cg_beta(w.sc, w.part2, P, ub, items, c->stream);
+    e = pipe_apply<T>(c, w, items, w.p, 1, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part, &cg);
+    if (e == hipSuccess) e = launch_cg_update<T>(update_args<T>(c, w, tiles), items, ub, c->stream);
   }
+  if (e == hipSuccess && finalize) e = launch_cg_finalize(w.sc, w.part2, P, ub, items, c->stream);
   return e;
 }
 
@@ -1253,11 +1272,14 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   // each kernel is timed in the context it runs in during a solve: caches
   // as left by its predecessor, no gaps added
   // slots: 0 expand, 1 axis-1 inverse, 2 row, 3 axis-1 forward, 4 project,
-  // 5 update, 6 alpha + beta, 7 whole iteration (sum of the kernels)
-  const int NK = 8;   // launches per iteration: slots 0..5, alpha, beta
+  // 5 update (alpha and beta are derived inside these kernels), 6 the
+  // end-of-launch bookkeeping (once per launch of up to 16 iterations, shown
+  // per iteration as 1/16 of its duration), 7 whole iteration
+  const int NK = 7;
   std::vector<hipEvent_t> ev((size_t)reps * NK * 2, nullptr);
   for (auto& x : ev) (void)hipEventCreate(&x);
   std::vector<int> launched((size_t)reps * NK, 0);
+  const CgFuse cg{w.part2, ub};
   e = reset();
   for (int it = 0; it < reps && e == hipSuccess; ++it) {
     hipEvent_t* E = ev.data() + (size_t)it * NK * 2;
@@ -1267,7 +1289,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
       Ln[k] = 1;
     };
     arm(0);
-    e = stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc);
+    e = stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc, &cg);
     if (e == hipSuccess && c->dd == 3) {
       arm(1);
       e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc);
@@ -1284,31 +1306,15 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     if (e == hipSuccess) {
       arm(4);
       e = stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr, nullptr, nullptr,
-                           nullptr, w.part, w.sc, nullptr);
+                           nullptr, w.part, w.sc, nullptr, &cg);
     }
     if (e == hipSuccess) {
-      arm(6);
-      e = launch_cg_alpha(w.sc, w.part, P, tiles, L, c->stream);
-    }
-    if (e == hipSuccess) {
-      CgUpdateArgs<T> u{};
-      u.x = w.x;
-      u.r = w.r;
-      u.p = w.p;
-      u.q = w.q;
-      u.stride = c->S;
-      u.count = c->S;
-      u.H = c->H;
-      u.n0 = scalar_n0(c);
-      u.partials = w.part2;
-      u.P = P;
-      u.sc = w.sc;
       arm(5);
-      e = launch_cg_update<T>(u, L, ub, c->stream);
+      e = launch_cg_update<T>(update_args<T>(c, w, tiles), L, ub, c->stream);
     }
-    if (e == hipSuccess) {
-      arm(7);
-      e = launch_cg_beta(w.sc, w.part2, P, ub, L, c->stream);
+    if (e == hipSuccess && it == reps - 1) {
+      arm(6);
+      e = launch_cg_finalize(w.sc, w.part2, P, ub, L, c->stream);
     }
   }
   arm_launch_events(nullptr, nullptr);
@@ -1319,10 +1325,9 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     for (int k = 0; k < NK; ++k) {
       float t = 0.f;
       if (!Ln[k] || hipEventElapsedTime(&t, E[2 * k], E[2 * k + 1]) != hipSuccess) continue;
-      ms[k < 7 ? k : 6] += t;   // beta joins alpha in slot 6
+      ms[k] += (k == 6) ? t / 16.0 : t / reps;
     }
   }
-  for (int k = 0; k < 7; ++k) ms[k] /= reps;
   for (int k = 0; k < 7; ++k) ms[7] += ms[k];
   if (c->dd != 3) ms[1] = ms[3] = 0.0;
   bytes[0] = L * (3.0 * S * esz + (double)c->dd * Q0 * inner * esz);
