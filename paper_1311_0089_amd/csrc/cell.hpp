@@ -63,6 +63,10 @@ struct CellImpl {
   double* ebuf = nullptr;     // FP64 real strain scratch [items][d][Q]
   long ebuf_items = 0;
   double* quad = nullptr;     // quadrature partials / outputs
+  void* pin = nullptr;        // pinned host staging for scalar reads and small uploads
+  size_t pin_bytes = 0;
+  double* dE = nullptr;       // device copy of the load cases [items][dd]
+  int dE_items = 0;
   int A_group = 1 << 30;      // items sharing one coefficient block (batched cells: d)
   long A_block = 0;           // elements per coefficient block (0: one shared block)
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -111,6 +115,8 @@ hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>
                       const double* dE, bool onQ, double* out);
 // launch helpers shared with the serving runtime
 int update_blocks(long S);
+// pinned host staging of at least `bytes` bytes, owned by the cell
+hipError_t pinned(CellImpl* c, size_t bytes, void** out);
 int scalar_n0(const CellImpl* c);
 int partial_slots(const CellImpl* c);
 template <class T>

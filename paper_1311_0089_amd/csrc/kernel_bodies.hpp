@@ -62,11 +62,12 @@ struct ColStat {
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
   __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
-  __device__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
+  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
     sfft<T, S, SP, W_, true, 1, W_, NT_>(lds, tw);
   }
   template <class T, int S>
-  __device__ static void fft_rows(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
+  __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan&, int,
+                                                  const cpx<T>* tw) {
     sfft<T, S, SP, W_, true, 1, RL, NT_>(lds, tw);
   }
 };
@@ -85,7 +86,8 @@ struct ColStatCP {
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
   __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
-  __device__ static void fft_rows(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
+  __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan&, int,
+                                                  const cpx<T>* tw) {
     sfft<T, S, SP, D_ * W_, true, 1, RL, NT_>(lds, tw);
   }
 };
@@ -112,7 +114,8 @@ struct RowStat {
   __device__ static constexpr int H(int) { return (NTRIAL + 1) / 2; }
   __device__ static constexpr int ls(int) { return SP::len; }
   template <class T, int S>
-  __device__ static void fft(cpx<T>* lds, const FftPlan&, int, int, const cpx<T>* tw) {
+  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan&, int, int,
+                                             const cpx<T>* tw) {
     sfft<T, S, SP, D_ * RP_, false, SP::len, 1, NT_>(lds, tw);
   }
 };

@@ -324,14 +324,14 @@ __global__ __launch_bounds__(kThreads) void k_a_range(const double* A, int d, in
 }
 
 hipError_t a_field_range(const double* A, int d, int kind, long npts, double* scratch,
-                         hipStream_t s, double* lo, double* hi, int* flags) {
+                         double* host, hipStream_t s, double* lo, double* hi, int* flags) {
   const int blocks = (int)std::max(1L, std::min((long)kRangeBlocks, (npts + kThreads - 1) / kThreads));
   static_assert(3 * kRangeBlocks <= kQuadScratch, "range partials exceed the scratch buffer");
   hipLaunchKernelGGL(k_a_range, dim3(blocks), dim3(kThreads), 0, s, A, d, kind, npts, scratch);
   hipError_t e = hipGetLastError();
-  std::vector<double> h((size_t)3 * blocks);
+  double* h = host;
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h.data(), scratch, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(h, scratch, sizeof(double) * 3 * blocks, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   *lo = INFINITY;
@@ -384,13 +384,12 @@ __global__ __launch_bounds__(kThreads) void k_quad(const double* e, long es, lon
 
 __global__ __launch_bounds__(kThreads) void k_quad_final(const double* partials, int blocks,
                                                          long npts, double* out) {
-  // out[0..8] = W (3x3 slots), out[9..17] = J sums, each divided by npts
-  for (int t = 0; t < 18; ++t) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < blocks; b += blockDim.x) v += partials[(long)b * 18 + t];
-    v = block_sum<kThreads>(v);
-    if (threadIdx.x == 0) out[t] = v / (double)npts;
-  }
+  // workgroup t: out[t], t < 9 a W slot (3x3), t >= 9 a J sum, divided by npts
+  const int t = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += blockDim.x) v += partials[(long)b * 18 + t];
+  v = block_sum<kThreads>(v);
+  if (threadIdx.x == 0) out[t] = v / (double)npts;
 }
 
 __global__ void k_convert(const double* in, float* out, long n) {
@@ -491,7 +490,9 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
   const long pairs = (a.rows + 1) / 2;
   dim3 grid(ceil_div(pairs, a.RP), items);
   if (sk) {
-    if (mode != ROW_APPLY) return hipErrorInvalidValue;
+    const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
+                   : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
+    if (sk->kind != kind) return hipErrorInvalidValue;
     auto fn = reinterpret_cast<void (*)(RowArgs<T>)>(const_cast<void*>(sk->fn));
     launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();
@@ -569,7 +570,7 @@ hipError_t launch_quad_final(const double* partials, int blocks, int nl, int nm,
   (void)nl;
   (void)nm;
   (void)d;
-  launch_k(k_quad_final, dim3(1), dim3(kThreads), 0, s, partials, blocks, npts, out);
+  launch_k(k_quad_final, dim3(18), dim3(kThreads), 0, s, partials, blocks, npts, out);
   return hipGetLastError();
 }
 hipError_t launch_convert(const double* in, float* out, long n, hipStream_t s) {

@@ -160,7 +160,8 @@ struct CgUpdateArgs {
 };
 
 // compile-time specialised pass kernels, registered by kernels_static*.hip
-enum { KK_EXPAND = 0, KK_PROJECT = 1, KK_PLAIN_INV = 2, KK_PLAIN_FWD = 3, KK_ROW = 4 };
+enum { KK_EXPAND = 0, KK_PROJECT = 1, KK_PLAIN_INV = 2, KK_PLAIN_FWD = 3, KK_ROW = 4,
+       KK_ROW_CONST = 5, KK_ROW_SYNTH = 6 };
 struct StaticKernel {
   int kind, esz, n, ntrial, d;  // d: component count (row kernels), else 0
   const void* fn;
@@ -270,10 +271,12 @@ __host__ __device__ inline bool point_range(int d, int kind, const double* v, do
 
 // Range of the whole field A [nA][npts] (device pointer): lo, hi and flags
 // (bit 0: a value not finite, bit 1: a point not positive definite).
-// scratch: device buffer of kQuadScratch doubles.
-constexpr long kQuadScratch = 1024 * 18 + 64;
+// scratch: device buffer of kQuadScratch doubles; host: pinned host buffer
+// of at least 3 * 1024 doubles.
+constexpr int kQuadBlocks = 2048;   // workgroups of the energy quadrature
+constexpr long kQuadScratch = (long)kQuadBlocks * 18 + 64;
 hipError_t a_field_range(const double* A, int d, int kind, long npts, double* scratch,
-                         hipStream_t s, double* lo, double* hi, int* flags);
+                         double* host, hipStream_t s, double* lo, double* hi, int* flags);
 
 // Arm HIP events for the next kernel launched by this thread through the
 // launchers below: hipExtLaunchKernel records them from the dispatch itself.

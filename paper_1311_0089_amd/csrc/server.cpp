@@ -92,7 +92,7 @@ static void footprint(const CellImpl* c, size_t* per_slot, size_t* fixed) {
                      2 * sizeof(double) * P + sizeof(ItemScal);
   *per_slot = (size_t)c->nA * c->nQ * (sizeof(double) + sizeof(float)) +
               (size_t)c->dd * (w64 + w32 + sizeof(ItemScal) + 3 * sizeof(double));
-  *fixed = sizeof(double) * (size_t)c->dd * c->dd * c->nQ + sizeof(double) * (18 * 1024 + 64);
+  *fixed = sizeof(double) * (size_t)c->dd * c->dd * c->nQ + sizeof(double) * kQuadScratch;
 }
 
 }  // namespace hom
@@ -322,7 +322,7 @@ hipError_t hom_server::retire(SizeClass* k, int s) {
   // FP64 strain of the slot's load cases on the quadrature grid, then W and J
   err = pipe_synth(e, v, L, v.x, k->dE + (size_t)s * dd * dd, true, k->ebuf);
   const double* A = e->A64 + (size_t)e->A_block * s;
-  const int blocks = (int)std::min<long>(1024, (e->nQ + kThreads - 1) / kThreads);
+  const int blocks = (int)std::min<long>(kQuadBlocks, (e->nQ + kThreads - 1) / kThreads);
   std::vector<double> hW((size_t)L * L, 0.0), hJ((size_t)L * dd, 0.0);
   for (int l0 = 0; l0 < L && err == hipSuccess; l0 += 3) {
     const int nl = std::min(3, L - l0);
@@ -330,7 +330,7 @@ hipError_t hom_server::retire(SizeClass* k, int s) {
       const int nm = std::min(3, L - m0);
       err = launch_quad(k->ebuf, (long)dd * e->nQ, e->nQ, A, e->nQ, e->kind, dd, e->nQ, l0, nl,
                         m0, nm, e->quad, blocks, e->stream);
-      double* outp = e->quad + 18 * 1024;
+      double* outp = e->quad + (size_t)kQuadBlocks * 18;
       if (err == hipSuccess)
         err = launch_quad_final(e->quad, blocks, nl, nm, dd, e->nQ, outp, e->stream);
       double h[18];
@@ -372,13 +372,17 @@ hipError_t hom_server::retire(SizeClass* k, int s) {
 
 hipError_t hom_server::refine_and_retire(SizeClass* k) {
   CellImpl* e = k->eng;
-  hipError_t err = hipMemcpyAsync(k->h_outer.data(), e->w64.sc, sizeof(ItemScal) * k->items,
-                                  hipMemcpyDeviceToHost, e->stream);
+  // the flags come back through the engine's pinned staging: [outer][inner][mask]
+  const size_t b = sizeof(ItemScal) * k->items;
+  void* hp = nullptr;
+  hipError_t err = pinned(e, 3 * b, &hp);
+  if (err == hipSuccess) err = hipMemcpyAsync(hp, e->w64.sc, b, hipMemcpyDeviceToHost, e->stream);
   if (err == hipSuccess)
-    err = hipMemcpyAsync(k->h_inner.data(), e->w32.sc, sizeof(ItemScal) * k->items,
-                         hipMemcpyDeviceToHost, e->stream);
+    err = hipMemcpyAsync((char*)hp + b, e->w32.sc, b, hipMemcpyDeviceToHost, e->stream);
   if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
   if (err != hipSuccess) return err;
+  std::memcpy(k->h_outer.data(), hp, b);
+  std::memcpy(k->h_inner.data(), (char*)hp + b, b);
   const int dd = k->dd;
   // retire slots whose load cases all stopped
   for (int s = 0; s < k->slots; ++s) {
@@ -408,8 +412,11 @@ hipError_t hom_server::refine_and_retire(SizeClass* k) {
   const int ub = update_blocks(e->S);
   Work<double>& w = e->w64;
   Work<float>& w32 = e->w32;
-  err = hipMemcpyAsync(k->mask, k->h_mask.data(), sizeof(ItemScal) * k->items,
-                       hipMemcpyHostToDevice, e->stream);
+  // the mask region of the staging is not written again before this copy has
+  // run: the next write follows the next read-back, which synchronises
+  if ((err = pinned(e, 3 * b, &hp)) != hipSuccess) return err;   // retiring may not move it; cheap
+  std::memcpy((char*)hp + 2 * b, k->h_mask.data(), b);
+  err = hipMemcpyAsync(k->mask, (char*)hp + 2 * b, b, hipMemcpyHostToDevice, e->stream);
   if (err == hipSuccess)
     err = launch_inner_accumulate(w.x, w32.x, e->S, e->S, w.sc, ub, k->items, e->stream, k->mask);
   if (err == hipSuccess)

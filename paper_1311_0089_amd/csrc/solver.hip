@@ -92,7 +92,23 @@ CellImpl::~CellImpl() {
   if (A32) (void)hipFree(A32);
   if (ebuf) (void)hipFree(ebuf);
   if (quad) (void)hipFree(quad);
+  if (dE) (void)hipFree(dE);
+  if (pin) (void)hipHostFree(pin);
   if (stream) (void)hipStreamDestroy(stream);
+}
+
+hipError_t pinned(CellImpl* c, size_t bytes, void** out) {
+  if (c->pin_bytes < bytes) {
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 64 * 1024);
+    hipError_t e = hipHostMalloc(&c->pin, want, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    c->pin_bytes = want;
+  }
+  *out = c->pin;
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -313,8 +329,10 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   a.tw = tw_of<T>(pl);
   a.sc = sc;
   const int Nlast = c->N[c->dd - 1];
+  const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
+                 : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
   const StaticKernel* sk =
-      (mode == ROW_APPLY) ? find_static(KK_ROW, sizeof(cpx<T>), Glast, Nlast, c->dd, pl->p) : nullptr;
+      (kind >= 0) ? find_static(kind, sizeof(cpx<T>), Glast, Nlast, c->dd, pl->p) : nullptr;
   if (sk) {
     a.RP = sk->W;
     return launch_row<T>(a, items, mode, sk->lds, c->stream, sk);
@@ -626,11 +644,15 @@ static hipError_t cg_launch(CellImpl* c, int items, int K) {
   return e;
 }
 
+// scalar read-back through the cell's pinned staging (a DMA, no bounce)
 static hipError_t read_scal(CellImpl* c, const ItemScal* d, int items, std::vector<ItemScal>& h) {
   h.resize(items);
-  hipError_t e = hipMemcpyAsync(h.data(), d, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
-                                c->stream);
+  void* hp = nullptr;
+  hipError_t e = pinned(c, sizeof(ItemScal) * items, &hp);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp, d, sizeof(ItemScal) * items, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) std::memcpy(h.data(), hp, sizeof(ItemScal) * items);
   return e;
 }
 
@@ -638,10 +660,28 @@ static hipError_t read_scal2(CellImpl* c, const ItemScal* d1, std::vector<ItemSc
                              const ItemScal* d2, std::vector<ItemScal>& h2, int items) {
   h1.resize(items);
   h2.resize(items);
-  hipError_t e = hipMemcpyAsync(h1.data(), d1, sizeof(ItemScal) * items, hipMemcpyDeviceToHost,
-                                c->stream);
+  const size_t b = sizeof(ItemScal) * items;
+  void* hp = nullptr;
+  hipError_t e = pinned(c, 2 * b, &hp);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp, d1, b, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h2.data(), d2, sizeof(ItemScal) * items, hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync((char*)hp + b, d2, b, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) {
+    std::memcpy(h1.data(), hp, b);
+    std::memcpy(h2.data(), (char*)hp + b, b);
+  }
+  return e;
+}
+
+// host -> device through the pinned staging; waits for the copy, so the
+// staging can be reused at once
+static hipError_t upload(CellImpl* c, void* dst, const void* src, size_t bytes) {
+  void* hp = nullptr;
+  hipError_t e = pinned(c, bytes, &hp);
+  if (e != hipSuccess) return e;
+  std::memcpy(hp, src, bytes);
+  e = hipMemcpyAsync(dst, hp, bytes, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return e;
 }
@@ -672,26 +712,35 @@ static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemS
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// the load cases on the device, in the cell's persistent buffer
 static hipError_t upload_E(CellImpl* c, int L, const double* E, double** dE) {
   // [L][dd] with zero padding for d = 1
   std::vector<double> h((size_t)L * c->dd, 0.0);
   for (int l = 0; l < L; ++l)
     for (int a = 0; a < c->d; ++a) h[(size_t)l * c->dd + a] = E[(size_t)l * c->d + a];
-  hipError_t e = hipMalloc(dE, sizeof(double) * h.size());
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(*dE, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  return e;
+  if (c->dE_items < L) {
+    if (c->dE) (void)hipFree(c->dE);
+    c->dE = nullptr;
+    c->dE_items = 0;
+    hipError_t e = hipMalloc(&c->dE, sizeof(double) * 3 * std::max(L, 8));
+    if (e != hipSuccess) return e;
+    c->dE_items = std::max(L, 8);
+  }
+  *dE = c->dE;
+  return upload(c, c->dE, h.data(), sizeof(double) * h.size());
 }
 
 static hipError_t sum_partials_host(CellImpl* c, const double* dpart, int items, int nparts,
                                     std::vector<double>& out) {
   const int P = partial_slots(c);
   std::vector<double> h((size_t)items * P);
-  hipError_t e = hipMemcpyAsync(h.data(), dpart, sizeof(double) * h.size(),
-                                hipMemcpyDeviceToHost, c->stream);
+  void* hp = nullptr;
+  hipError_t e = pinned(c, sizeof(double) * h.size(), &hp);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp, dpart, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return e;
+  std::memcpy(h.data(), hp, sizeof(double) * h.size());
   out.assign(items, 0.0);
   for (int i = 0; i < items; ++i)
     for (int t = 0; t < nparts; ++t) out[i] += h[(size_t)i * P + t];
@@ -725,7 +774,7 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
   if (!c->quad) {
     if ((e = hipMalloc(&c->quad, sizeof(double) * kQuadScratch)) != hipSuccess) return e;
   }
-  const int blocks = (int)std::min<long>(1024, (c->nQ + kThreads - 1) / kThreads);
+  const int blocks = (int)std::min<long>(kQuadBlocks, (c->nQ + kThreads - 1) / kThreads);
   std::vector<double> hW((size_t)L * L, 0.0), hJ((size_t)L * c->dd, 0.0);
   for (int l0 = 0; l0 < L; l0 += 3) {
     const int nl = std::min(3, L - l0);
@@ -734,15 +783,18 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
       if ((e = launch_quad(eQ, (long)c->dd * c->nQ, c->nQ, c->A64, c->nQ, c->kind, c->dd, c->nQ,
                            l0, nl, m0, nm, c->quad, blocks, c->stream)) != hipSuccess)
         return e;
-      double* outp = c->quad + (size_t)1024 * 18;
+      double* outp = c->quad + (size_t)kQuadBlocks * 18;
       if ((e = launch_quad_final(c->quad, blocks, nl, nm, c->dd, c->nQ, outp, c->stream)) !=
           hipSuccess)
         return e;
       double h[18];
-      if ((e = hipMemcpyAsync(h, outp, sizeof(h), hipMemcpyDeviceToHost, c->stream)) !=
+      void* hp = nullptr;
+      if ((e = pinned(c, sizeof(h), &hp)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(hp, outp, sizeof(h), hipMemcpyDeviceToHost, c->stream)) !=
           hipSuccess)
         return e;
       if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+      std::memcpy(h, hp, sizeof(h));
       for (int l = 0; l < nl; ++l)
         for (int m = 0; m < nm; ++m) hW[(size_t)(l0 + l) * L + m0 + m] = h[l * 3 + m];
       if (l0 == 0)
@@ -969,9 +1021,11 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
                      A_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
   double lo = 0.0, hi = 0.0;
   int flags = 0;
+  void* hp = nullptr;
+  if (e == hipSuccess) e = pinned(c, sizeof(double) * 3 * 1024, &hp);
   if (e == hipSuccess)
-    e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, c->quad, c->stream,
-                      &lo, &hi, &flags);
+    e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, c->quad,
+                      (double*)hp, c->stream, &lo, &hi, &flags);
   if (e == hipSuccess && flags == 0) e = launch_convert(c->A64, c->A32, (long)nAd, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -1103,9 +1157,7 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           }
         }
         if (any_replace) {
-          if ((e = hipMemcpyAsync(w.mask, hm.data(), sizeof(ItemScal) * L, hipMemcpyHostToDevice,
-                                  c->stream)) != hipSuccess)
-            break;
+          if ((e = upload(c, w.mask, hm.data(), sizeof(ItemScal) * L)) != hipSuccess) break;
           if ((e = launch_inner_accumulate(w.x, w32.x, c->S, c->S, outer, ub, L, c->stream,
                                            w.mask)) != hipSuccess)
             break;
@@ -1162,7 +1214,6 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
     if ((e = homogenize(c, L, dE, strain, W, J)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (false);
-  (void)hipFree(dE);
   if (e != hipSuccess) return dev_status(e);
   if (info) {
     info->iters_inner = it_inner;
@@ -1206,7 +1257,6 @@ hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double
     if ((e = pipe_synth(c, c->w64, L, w.q, dE, false, out)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (false);
-  if (dE) (void)hipFree(dE);
   return dev_status(e);
 }
 
@@ -1227,7 +1277,6 @@ hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
     if ((e = pipe_synth(c, c->w64, L, c->w64.x, dE, false, out)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (false);
-  if (dE) (void)hipFree(dE);
   return dev_status(e);
 }
 

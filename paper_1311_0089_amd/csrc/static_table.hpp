@@ -97,13 +97,21 @@ struct RegRow {
   static_assert(lds <= 66 * 1024 + 512, "row tile exceeds the LDS budget");
   RegRow() {
     using P = RowStat<SP, NTRIAL, D, RP, NT>;
+    add(KK_ROW, (const void*)&k_row<T, P, ROW_APPLY>);
+    // the FP64 right-hand side and strain synthesis passes of the same shape
+    if constexpr (sizeof(T) == 8) {
+      add(KK_ROW_CONST, (const void*)&k_row<T, P, ROW_CONST>);
+      add(KK_ROW_SYNTH, (const void*)&k_row<T, P, ROW_SYNTH>);
+    }
+  }
+  static void add(int kind, const void* fn) {
     StaticKernel k{};
-    k.kind = KK_ROW;
+    k.kind = kind;
     k.esz = (int)sizeof(cpx<T>);
     k.n = SP::n;
     k.ntrial = NTRIAL;
     k.d = D;
-    k.fn = (const void*)&k_row<T, P, ROW_APPLY>;
+    k.fn = fn;
     k.W = RP;
     k.NT = NT;
     k.lds = lds;
