@@ -63,8 +63,6 @@ struct CellImpl {
   double* ebuf = nullptr;     // FP64 real strain scratch [items][d][Q]
   long ebuf_items = 0;
   double* quad = nullptr;     // quadrature partials / outputs
-  void* pin = nullptr;        // pinned host staging for scalar reads and small uploads
-  size_t pin_bytes = 0;
   double* dE = nullptr;       // device copy of the load cases [items][dd]
   int dE_items = 0;
   int A_group = 1 << 30;      // items sharing one coefficient block (batched cells: d)
@@ -115,7 +113,7 @@ hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>
                       const double* dE, bool onQ, double* out);
 // launch helpers shared with the serving runtime
 int update_blocks(long S);
-// pinned host staging of at least `bytes` bytes, owned by the cell
+// pinned host staging of at least `bytes` bytes (the calling thread's)
 hipError_t pinned(CellImpl* c, size_t bytes, void** out);
 int scalar_n0(const CellImpl* c);
 int partial_slots(const CellImpl* c);

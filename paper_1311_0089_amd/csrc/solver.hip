@@ -93,21 +93,43 @@ CellImpl::~CellImpl() {
   if (ebuf) (void)hipFree(ebuf);
   if (quad) (void)hipFree(quad);
   if (dE) (void)hipFree(dE);
-  if (pin) (void)hipHostFree(pin);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
+// Pinned host staging, one buffer per host thread (grown on demand, kept for
+// the thread's life): cells are not re-entrant, so a thread's cells never
+// use it concurrently, and thousands of cells cost no pinned memory each.
 hipError_t pinned(CellImpl* c, size_t bytes, void** out) {
-  if (c->pin_bytes < bytes) {
-    if (c->pin) (void)hipHostFree(c->pin);
-    c->pin = nullptr;
-    c->pin_bytes = 0;
+  (void)c;
+  static thread_local void* buf = nullptr;
+  static thread_local size_t cap = 0;
+  if (cap < bytes) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
     const size_t want = std::max<size_t>(bytes, 64 * 1024);
-    hipError_t e = hipHostMalloc(&c->pin, want, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&buf, want, hipHostMallocDefault);
     if (e != hipSuccess) return e;
-    c->pin_bytes = want;
+    cap = want;
   }
-  *out = c->pin;
+  *out = buf;
+  return hipSuccess;
+}
+
+// device scratch of the coefficient check, one per device (creation only)
+static std::mutex g_range_mu;
+static hipError_t range_scratch(int device, double** out) {
+  static std::map<int, double*> bufs;
+  auto it = bufs.find(device);
+  if (it != bufs.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  double* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(double) * kQuadScratch);
+  if (e != hipSuccess) return e;
+  bufs[device] = p;
+  *out = p;
   return hipSuccess;
 }
 
@@ -674,15 +696,16 @@ static hipError_t read_scal2(CellImpl* c, const ItemScal* d1, std::vector<ItemSc
   return e;
 }
 
-// host -> device through the pinned staging; waits for the copy, so the
-// staging can be reused at once
-static hipError_t upload(CellImpl* c, void* dst, const void* src, size_t bytes) {
+// host -> device through the pinned staging.  With wait == false the copy
+// is only queued: the caller's next host access to the staging must follow a
+// stream synchronisation (the read-backs synchronise before they touch it).
+static hipError_t upload(CellImpl* c, void* dst, const void* src, size_t bytes, bool wait = true) {
   void* hp = nullptr;
   hipError_t e = pinned(c, bytes, &hp);
   if (e != hipSuccess) return e;
   std::memcpy(hp, src, bytes);
   e = hipMemcpyAsync(dst, hp, bytes, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && wait) e = hipStreamSynchronize(c->stream);
   return e;
 }
 
@@ -694,7 +717,7 @@ static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemS
   std::vector<char> live(items, 1);
   hipError_t e = read_scal(c, w.sc, items, hs);
   if (e != hipSuccess) return e;
-  int K = plan.Kmax;
+  int K = plan.next(hs, live);   // the first reading: no rate yet, Kmax
   long launched = 0;
   for (;;) {
     bool any = false;
@@ -1008,10 +1031,6 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   }
   c->d = d;
   c->opt = o;
-  if (!c->quad && (e = hipMalloc(&c->quad, sizeof(double) * kQuadScratch)) != hipSuccess) {
-    pool_put(c);
-    return dev_status(e);
-  }
   // A goes to the device as given (FP64), is validated there (A2: finite,
   // symmetric positive definite at every point; contrast from the eigenvalue
   // range) and converted to the FP32 copy of the mixed path
@@ -1023,9 +1042,14 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   int flags = 0;
   void* hp = nullptr;
   if (e == hipSuccess) e = pinned(c, sizeof(double) * 3 * 1024, &hp);
-  if (e == hipSuccess)
-    e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, c->quad,
-                      (double*)hp, c->stream, &lo, &hi, &flags);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_range_mu);
+    double* scratch = nullptr;
+    e = range_scratch(device, &scratch);
+    if (e == hipSuccess)
+      e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, scratch,
+                        (double*)hp, c->stream, &lo, &hi, &flags);
+  }
   if (e == hipSuccess && flags == 0) e = launch_convert(c->A64, c->A32, (long)nAd, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -1135,8 +1159,9 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
       IterPlanner plan(L, c->opt.check_every);
       std::vector<ItemScal> ho(L), hi(L), hm(L);
       std::vector<char> live(L, 1);
-      if ((e = read_scal(c, outer, L, ho)) != hipSuccess) break;
-      int K = plan.Kmax;
+      if ((e = read_scal2(c, outer, ho, w32.sc, hi, L)) != hipSuccess) break;
+      for (int i = 0; i < L; ++i) live[i] = ho[i].active;
+      int K = plan.next(hi, live);   // the first reading: no rate yet, Kmax
       for (;;) {
         bool any_outer = false;
         for (int i = 0; i < L; ++i) any_outer = any_outer || ho[i].active;
@@ -1157,7 +1182,7 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           }
         }
         if (any_replace) {
-          if ((e = upload(c, w.mask, hm.data(), sizeof(ItemScal) * L)) != hipSuccess) break;
+          if ((e = upload(c, w.mask, hm.data(), sizeof(ItemScal) * L, false)) != hipSuccess) break;
           if ((e = launch_inner_accumulate(w.x, w32.x, c->S, c->S, outer, ub, L, c->stream,
                                            w.mask)) != hipSuccess)
             break;
