@@ -27,6 +27,7 @@ RegCol<T, P509, 255, 8, 512> c509;
 RegColCP<T, P1023, 1023, 4, 2, 512> x1023_4;
 RegColCP<T, P1023, 1023, 2, 2, 256> x1023_2;
 RegColCP<T, P1023, 1023, 1, 2, 128> x1023_1;
+RegColCP<T, P1023, 1023, 3, 2, 384> x1023_3;
 RegColCP<T, P255, 255, 8, 3, 384> x255_8;
 RegColCP<T, P255, 255, 4, 3, 192> x255_4;
 RegColCP<T, P255, 255, 16, 3, 768> x255_16;
@@ -39,6 +40,7 @@ RegColCP<T, P63, 63, 16, 3, 256> x63_16;
 RegRow<T, P1023, 1023, 2, 2, 256> r1023_2;
 RegRow<T, P1023, 1023, 2, 4, 512> r1023_2w;
 RegRow<T, P1023, 1023, 2, 1, 128> r1023_2n;
+RegRow<T, P1023, 1023, 2, 3, 384> r1023_2m;
 RegRow<T, P1023, 1023, 3, 2, 512> r1023_3;
 RegRow<T, P255, 255, 2, 8, 256> r255_2;
 RegRow<T, P255, 255, 3, 8, 512> r255_3;

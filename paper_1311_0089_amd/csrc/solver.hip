@@ -32,7 +32,9 @@ static hipError_t ensure_configured() {
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) return e;
-  size_t mx = prop.sharedMemPerBlock;
+  // a workgroup may take the whole LDS of a CU where the device allows it
+  // (gfx950: 160 KiB); the tuner decides whether the large tiles pay
+  size_t mx = std::max(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
   if (mx < 64 * 1024) mx = 64 * 1024;
   if (mx > 160 * 1024) mx = 160 * 1024;
   e = configure_kernels(mx);
