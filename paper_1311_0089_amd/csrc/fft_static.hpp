@@ -56,35 +56,55 @@ __device__ __forceinline__ void sstage(cpx<T>* buf, const cpx<T>* __restrict__ t
   constexpr int nb = LEN / R;
   constexpr int total = nb * W;
   constexpr int MB = (total + NT - 1) / NT;
+  constexpr int NTW = (Ns > 1) ? R - 1 : 1;
+  // butterfly f of this thread's round it: line w, index j in the line.  Every
+  // read is unconditional (a thread past the last butterfly repeats its reads
+  // and writes nothing), so the twiddle loads of all rounds go out together
+  // instead of each being waited for under its own branch.
+  auto at = [](int it, int& w, int& j) __attribute__((always_inline)) {
+    const int f0 = threadIdx.x + it * NT;
+    const int f = ((total % NT) == 0) ? f0 : min(f0, total - 1);
+    if (WF) {
+      w = f % W;
+      j = f / W;
+    } else {
+      j = f % nb;
+      w = f / nb;
+    }
+    return ((total % NT) == 0) || f0 < total;
+  };
   cpx<T> v[MB][R];
+  cpx<T> t[MB][NTW];
   int ob[MB];
+  if (Ns > 1) {
+#pragma unroll
+    for (int it = 0; it < MB; ++it) {
+      int w, j;
+      at(it, w, j);
+      const cpx<T>* tk = tw + (j % Ns) * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) t[it][r - 1] = tk[r - 1];
+    }
+  }
 #pragma unroll
   for (int it = 0; it < MB; ++it) {
-    const int f = threadIdx.x + it * NT;
-    ob[it] = -1;
-    if ((total % NT) == 0 || f < total) {
-      int w, j;
-      if (WF) {
-        w = f % W;
-        j = f / W;
-      } else {
-        j = f % nb;
-        w = f / nb;
-      }
-      const cpx<T>* line = buf + w * LS;
-      const int k = j % Ns;
+    int w, j;
+    const bool live = at(it, w, j);
+    const cpx<T>* line = buf + w * LS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = line[(j + r * nb) * ES];
-      if (Ns > 1) {
-        const cpx<T>* t = tw + k * (R - 1);
+    for (int r = 0; r < R; ++r) v[it][r] = line[(j + r * nb) * ES];
+    const int k = j % Ns;
+    ob[it] = live ? w * LS + ((j / Ns) * Ns * R + k) * ES : -1;
+  }
+  if (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          cpx<T> w_ = t[r - 1];
-          if (S > 0) w_.y = -w_.y;
-          v[it][r] = cmul(v[it][r], w_);
-        }
+    for (int it = 0; it < MB; ++it) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cpx<T> w_ = t[it][r - 1];
+        if (S > 0) w_.y = -w_.y;
+        v[it][r] = cmul(v[it][r], w_);
       }
-      ob[it] = w * LS + ((j / Ns) * Ns * R + k) * ES;
     }
   }
   __syncthreads();

@@ -94,6 +94,10 @@ struct ColStatCP {
 
 struct RowGen {
   static constexpr int NT = kThreads;
+  // loads per thread in flight in the load / store phases (the generic FP64
+  // kernel, already short of registers, keeps one)
+  template <class T>
+  static constexpr int CH = (sizeof(T) == 8) ? 1 : 8;
   __device__ static int D(int d) { return d; }
   __device__ static int RP(int rp) { return rp; }
   __device__ static int n(int n_) { return n_; }
@@ -108,6 +112,8 @@ struct RowGen {
 template <class SP, int NTRIAL, int D_, int RP_, int NT_>
 struct RowStat {
   static constexpr int NT = NT_;
+  template <class T>
+  static constexpr int CH = 8;
   __device__ static constexpr int D(int) { return D_; }
   __device__ static constexpr int RP(int) { return RP_; }
   __device__ static constexpr int n(int) { return SP::n; }
@@ -157,27 +163,64 @@ __device__ __forceinline__ double block_sum(double v) {
   return v;
 }
 
-// fixed-order sum of nparts partials, result valid in thread 0
-__device__ __forceinline__ double sum_partials(const double* p, int nparts) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) v += p[i];
-  return block_sum<kThreads>(v);
+// Fixed-order sum of nparts partials, computed by every wave on its own: lane l
+// adds p[l], p[l + 64], p[l + 128], ... in turn (eight loads in flight at a
+// time), then the 64 lane sums meet in a butterfly, which leaves the same value
+// in every lane (each pairwise addition sees the same two operands on both
+// sides).  Every workgroup that needs a CG scalar derives it identically,
+// whatever its size, and without a barrier.  Split in two so that a kernel can
+// issue the first eight loads per lane (partials_head) ahead of its own loads
+// and add them up afterwards (partials_finish).
+__device__ __forceinline__ void partials_head(const double* p, int nparts, double* t) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) t[u] = p[max(min(lane + u * 64, nparts - 1), 0)];
 }
 
-// the same fixed-order sum for a workgroup of NT threads, returned to every
-// thread (each workgroup that needs a CG scalar derives it identically)
-template <int NT>
-__device__ __forceinline__ double sum_partials_all(const double* p, int nparts) {
-  __shared__ double total;
+__device__ __forceinline__ double partials_finish(const double* p, int nparts, const double* t) {
+  const int lane = threadIdx.x & 63;
   double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NT) v += p[i];
-  v = block_sum<NT>(v);
-  if (threadIdx.x == 0) total = v;
-  __syncthreads();
-  v = total;
-  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v += (lane + u * 64 < nparts) ? t[u] : 0.0;
+  for (int i0 = lane + 8 * 64; i0 < nparts; i0 += 8 * 64) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r[u] = (i0 + u * 64 < nparts) ? p[i0 + u * 64] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += r[u];
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
+__device__ __forceinline__ double sum_partials_wave(const double* p, int nparts) {
+  double t[8];
+  partials_head(p, nparts, t);
+  return partials_finish(p, nparts, t);
+}
+
+// f = threadIdx.x + k NT for every f < n, in rounds of CH per thread: a round
+// issues all of its loads (ld) before the first use (use), so a thread keeps CH
+// memory requests in flight instead of waiting for each in turn.  The loads are
+// unconditional (an index past the end reads element n - 1 again, unused):
+// a load under a branch is waited for inside that branch.
+template <int NT, int CH, class Ld, class Use>
+__device__ __forceinline__ void in_rounds(int n, const Ld& ld, const Use& use) {
+  using V = decltype(ld(0));
+  for (int f0 = threadIdx.x; f0 < n; f0 += CH * NT) {
+    V v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) v[u] = ld(min(f0 + u * NT, n - 1));
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (f0 + u * NT < n) use(f0 + u * NT, v[u]);
+  }
+}
+
+template <class T>
+struct cpx2 {
+  cpx<T> a, b;
+};
 
 // CG bookkeeping of one completed update from the sum s = (r, r): iteration
 // count, stopping test (relative residual or budget), beta and rho.  One
@@ -223,40 +266,60 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
   const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
   const int ncols = min(W, a.inner - col0);
   const long ibase = (long)item * a.c_stride;
+  const int npos = n_in * W;
+  const bool colm = (P::SL == 0) ? (a.si == 1) : (P::SL == 1);
+  // position it of this thread: (i, w) of the tile; with column-major scalars
+  // axis 0 runs across the threads (contiguous loads), else the tile columns do
+  auto pos = [=](int it, int& i, int& w) __attribute__((always_inline)) {
+    const int f = threadIdx.x + it * NT;
+    i = colm ? f % n_in : f / W;
+    w = colm ? f / n_in : f % W;
+    return f < npos;
+  };
+  // every load of the fill goes out before the stopping test and beta are
+  // derived from the partials, behind the first loads of those partials
+  // (unconditional: positions outside the tile read an element inside it again)
+  const bool derive = a.fuse && a.rr_part && !a.sc[item].fresh;
+  const double* rr = a.rr_part + (long)item * a.P;
+  double ph[8];
+  if (derive) partials_head(rr, a.rr_n, ph);
+  cpx<T> rv[PMAX], pv[PMAX];
+#pragma unroll
+  for (int it = 0; it < PMAX; ++it) {
+    int i, w;
+    pos(it, i, w);
+    const long idx = ibase + (long)min(i, n_in - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_;
+    if (a.fuse) {
+      rv[it] = a.r[idx];
+      pv[it] = a.p[idx];
+    } else {
+      rv[it] = a.c[idx];
+    }
+  }
   T beta = a.fuse ? T(a.sc[item].beta) : T(0);
-  if (a.fuse && a.rr_part && !a.sc[item].fresh) {
+  if (derive) {
     // s = (r, r) of the last update; its bookkeeping runs in the projection
-    const double s = sum_partials_all<NT>(a.rr_part + (long)item * a.P, a.rr_n);
+    const double s = partials_finish(rr, a.rr_n, ph);
     const ItemScal q = a.sc[item];
     if (cg_stops(q, s)) return;
     beta = T(s / q.rho);
   }
-  const int npos = n_in * W;
-  const bool colm = (P::SL == 0) ? (a.si == 1) : (P::SL == 1);
   cpx<T> s[PMAX];
   int row[PMAX];
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
-    const int f = threadIdx.x + it * NT;
-    s[it] = cpx<T>{T(0), T(0)};
     row[it] = -1;
-    if (f < npos) {
-      // with column-major scalars axis 0 runs across the threads (contiguous
-      // loads), else the tile columns do
-      const int i = colm ? f % n_in : f / W, w = colm ? f / n_in : f % W;
+    int i, w;
+    const bool in = pos(it, i, w);
+    s[it] = (in && w < ncols) ? rv[it] : cpx<T>{T(0), T(0)};
+    if (in) {
       row[it] = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
-      if (w < ncols) {
-        const long idx = ibase + (long)i * a.si + (long)(col0 + w) * a.sc_;
-        if (a.fuse) {
-          const cpx<T> rv = a.r[idx];
-          cpx<T> pv = a.p[idx];
-          // beta = 0 restarts the direction: p = r exactly, whatever p held
-          pv = (beta == T(0)) ? rv : cpx<T>{rv.x + beta * pv.x, rv.y + beta * pv.y};
-          a.p[idx] = pv;
-          s[it] = pv;
-        } else {
-          s[it] = a.c[idx];
-        }
+      if (a.fuse && w < ncols) {
+        // beta = 0 restarts the direction: p = r exactly, whatever p held
+        const cpx<T> p = (beta == T(0)) ? rv[it]
+                                        : cpx<T>{rv[it].x + beta * pv[it].x, rv[it].y + beta * pv[it].y};
+        a.p[ibase + (long)i * a.si + (long)(col0 + w) * a.sc_] = p;
+        s[it] = p;
       }
     }
   }
@@ -282,10 +345,16 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
     __syncthreads();
     P::template fft_rows<T, +1>(lds, a.plan, W, a.tw);
     cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride;
-    for (int f = threadIdx.x; f < n_fft * W * nc; f += NT) {
-      const int w = f % W, t = f / W, c = t % nc, i = t / nc;
-      if (w < ncols) X[(long)c * a.X_cstride + (long)i * a.inner + col0 + w] = lds[i * LW + c * W + w];
-    }
+    in_rounds<NT, 8>(
+        n_fft * W * nc,
+        [=](int f) __attribute__((always_inline)) {
+          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+          return lds[i * LW + c * W + w];
+        },
+        [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+          if (w < ncols) X[(long)c * a.X_cstride + (long)i * a.inner + col0 + w] = v;
+        });
     __syncthreads();
   }
 }
@@ -315,18 +384,30 @@ __global__ __launch_bounds__(P::NT) void k_col_plain(ColPlainArgs<T> a) {
     for (int f = threadIdx.x; f < n_fft * W; f += NT) lds[f] = cpx<T>{T(0), T(0)};
     __syncthreads();
   }
-  for (int f = threadIdx.x; f < n_in * W; f += NT) {
-    const int i = f / W, w = f % W;
-    const int rrow = (n_in == n_fft) ? i : posk(kof(i, n_in), n_fft);
-    lds[rrow * W + w] = (w < ncols) ? in[(long)i * a.inner + w] : cpx<T>{T(0), T(0)};
-  }
+  in_rounds<NT, 8>(
+      n_in * W,
+      [=](int f) __attribute__((always_inline)) {
+        const int i = f / W, w = f % W;
+        return in[(long)i * a.inner + min(w, ncols - 1)];
+      },
+      [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+        const int i = f / W, w = f % W;
+        const int rrow = (n_in == n_fft) ? i : posk(kof(i, n_in), n_fft);
+        lds[rrow * W + w] = (w < ncols) ? v : cpx<T>{T(0), T(0)};
+      });
   __syncthreads();
   P::template fft<T, S>(lds, a.plan, W, a.tw);
-  for (int f = threadIdx.x; f < n_out * W; f += NT) {
-    const int i = f / W, w = f % W;
-    const int rrow = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
-    if (w < ncols) out[(long)i * a.inner + w] = cscale(lds[rrow * W + w], a.scale);
-  }
+  in_rounds<NT, 8>(
+      n_out * W,
+      [=](int f) __attribute__((always_inline)) {
+        const int i = f / W, w = f % W;
+        const int rrow = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
+        return lds[rrow * W + w];
+      },
+      [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+        const int i = f / W, w = f % W;
+        if (w < ncols) out[(long)i * a.inner + w] = cscale(v, a.scale);
+      });
 }
 
 // ---------------------------------------------------------------------------
@@ -363,11 +444,16 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   for (int al0 = 0; al0 < a.d; al0 += CPN) {
     constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
-    for (int f = threadIdx.x; f < n_fft * W * nc; f += NT) {
-      const int w = f % W, t = f / W, c = t % nc, i = t / nc;
-      lds[i * LW + c * W + w] = (w < ncols) ? X[(long)c * a.X_cstride + (long)i * a.inner + w]
-                                            : cpx<T>{T(0), T(0)};
-    }
+    in_rounds<NT, 8>(
+        n_fft * W * nc,
+        [=](int f) __attribute__((always_inline)) {
+          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+          return X[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
+        },
+        [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+          lds[i * LW + c * W + w] = (w < ncols) ? v : cpx<T>{T(0), T(0)};
+        });
     __syncthreads();
     P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
 #pragma unroll
@@ -388,6 +474,16 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   }
   double part = 0.0;
   const long sb = (long)item * a.s_stride;
+  // the epilogue's loads (p for (p, q), b for the residual) all go out first
+  const cpx<T>* ld = (a.epi == EPI_STORE) ? a.p : (a.epi == EPI_RESID) ? a.b : nullptr;
+  cpx<T> lv[PMAX];
+#pragma unroll
+  for (int it = 0; it < PMAX; ++it) {
+    const int f = threadIdx.x + it * NT;
+    const int i = colm ? f % n_out : f / W, w = colm ? f / n_out : f % W;
+    lv[it] = cpx<T>{T(0), T(0)};
+    if (ld) lv[it] = ld[sb + (long)min(i, n_out - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_];
+  }
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
     const int f = threadIdx.x + it * NT;
@@ -400,7 +496,7 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
       if (a.epi == EPI_STORE) {
         a.q[idx] = qv;
         if (a.p) {
-          const cpx<T> pv = a.p[idx];
+          const cpx<T> pv = lv[it];
           part += wt * ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
         }
       } else if (a.epi == EPI_RHS) {
@@ -411,7 +507,7 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
         if (a.x) a.x[idx] = cpx<T>{T(0), T(0)};
         part += wt * ((double)qv.x * (double)qv.x + (double)qv.y * (double)qv.y);
       } else {  // EPI_RESID: r = b - q
-        const cpx<T> bv = a.b[idx];
+        const cpx<T> bv = lv[it];
         const cpx<T> rv = cpx<T>{bv.x - qv.x, bv.y - qv.y};
         a.r[idx] = rv;
         part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
@@ -426,7 +522,7 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
     // bookkeeping of the update before this iteration's expansion (that
     // expansion has finished reading rho; no other workgroup here reads it)
     const bool fresh = a.sc[item].fresh != 0;
-    const double s = fresh ? 0.0 : sum_partials_all<NT>(a.rr_part + (long)item * a.P, a.rr_n);
+    const double s = fresh ? 0.0 : sum_partials_wave(a.rr_part + (long)item * a.P, a.rr_n);
     if (threadIdx.x == 0) {
       if (fresh) a.sc[item].fresh = 0;
       else cg_book(a.sc[item], s);
@@ -437,36 +533,58 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
 // ---------------------------------------------------------------------------
 // last (contiguous) axis: pairs of rows packed as one complex line
 // ---------------------------------------------------------------------------
+// stored components of A per point: 1 (isotropic), d (diagonal) or d(d+1)/2
+// (symmetric, order 00 11 [22 12 02] 01)
+__device__ __forceinline__ int coef_count(int kind, int d) {
+  return kind == 0 ? 1 : kind == 1 ? d : d * (d + 1) / 2;
+}
+
+template <class T>
+__device__ __forceinline__ void load_coef(int kind, int d, const T* A, long Acs, long off, T* c) {
+  const int na = coef_count(kind, d), namax = (d == 3) ? 6 : (d == 2) ? 3 : 1;
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if (q < namax && q < na) c[q] = A[q * Acs + off];
+}
+
+// j = A e from the loaded components c of one point
+template <class T>
+__device__ __forceinline__ void flux_coef(int kind, int d, const T* c, const T* e, T* j) {
+  if (kind == 0) {
+    for (int q = 0; q < d; ++q) j[q] = c[0] * e[q];
+  } else if (kind == 1) {
+    for (int q = 0; q < d; ++q) j[q] = c[q] * e[q];
+  } else if (d == 1) {
+    j[0] = c[0] * e[0];
+  } else if (d == 2) {
+    j[0] = c[0] * e[0] + c[2] * e[1];
+    j[1] = c[2] * e[0] + c[1] * e[1];
+  } else {
+    j[0] = c[0] * e[0] + c[5] * e[1] + c[4] * e[2];
+    j[1] = c[5] * e[0] + c[1] * e[1] + c[3] * e[2];
+    j[2] = c[4] * e[0] + c[3] * e[1] + c[2] * e[2];
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void flux_point(int kind, int d, const T* A, long Acs, long off,
                                            const T* e, T* j) {
-  if (kind == 0) {
-    const T a = A[off];
-    for (int q = 0; q < d; ++q) j[q] = a * e[q];
-  } else if (kind == 1) {
-    for (int q = 0; q < d; ++q) j[q] = A[q * Acs + off] * e[q];
-  } else {
-    if (d == 1) {
-      j[0] = A[off] * e[0];
-    } else if (d == 2) {
-      const T a00 = A[off], a11 = A[Acs + off], a01 = A[2 * Acs + off];
-      j[0] = a00 * e[0] + a01 * e[1];
-      j[1] = a01 * e[0] + a11 * e[1];
-    } else {
-      const T a00 = A[off], a11 = A[Acs + off], a22 = A[2 * Acs + off];
-      const T a12 = A[3 * Acs + off], a02 = A[4 * Acs + off], a01 = A[5 * Acs + off];
-      j[0] = a00 * e[0] + a01 * e[1] + a02 * e[2];
-      j[1] = a01 * e[0] + a11 * e[1] + a12 * e[2];
-      j[2] = a02 * e[0] + a12 * e[1] + a22 * e[2];
-    }
-  }
+  T c[6];
+  load_coef<T>(kind, d, A, Acs, off, c);
+  flux_coef<T>(kind, d, c, e, j);
 }
+
+template <class T>
+struct Coef2 {
+  T c0[6], c1[6];
+};
 
 template <class T, class P, int MODE>
 __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
+  constexpr int CHL = P::template CH<T>;
   const int item = blockIdx.y;
   if (a.sc && !a.sc[item].active) return;
   const int n = P::n(a.n), H = P::H(a.H), RP = P::RP(a.RP), d = P::D(a.d);
@@ -482,45 +600,55 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
         lds[line * ls + x] = cpx<T>{T(0), T(0)};
       }
     }
-    for (int f = threadIdx.x; f < d * RP * H; f += NT) {
-      const int line = f / H, h = f % H;
-      const int comp = line / RP, lp = line % RP;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      cpx<T> xa = {T(0), T(0)}, xb = {T(0), T(0)};
-      if (r0 < a.rows) {
-        const cpx<T>* src = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride;
-        xa = src[(long)r0 * H + h];
-        if (r1 < a.rows) xb = src[(long)r1 * H + h];
-      }
-      if (h == 0) {
-        // the h = 0 bin of a real line is real: an imaginary part left there by
-        // rounding would otherwise leak into the other line of the pair
-        xa.y = T(0);
-        xb.y = T(0);
-      }
-      lds[line * ls + h] = cpx<T>{xa.x - xb.y, xa.y + xb.x};
-      if (h > 0) lds[line * ls + n - h] = cpx<T>{xa.x + xb.y, xb.x - xa.y};
-    }
+    in_rounds<NT, CHL>(
+        d * RP * H,
+        [=](int f) __attribute__((always_inline)) {
+          const int line = f / H, h = f % H;
+          const int comp = line / RP, lp = line % RP;
+          const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+          const cpx<T>* src = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride;
+          return cpx2<T>{src[(long)min(r0, a.rows - 1) * H + h],
+                         src[(long)min(r1, a.rows - 1) * H + h]};
+        },
+        [=](int f, cpx2<T> v) __attribute__((always_inline)) {
+          const int line = f / H, h = f % H;
+          const int lp = line % RP;
+          const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+          if (r0 >= a.rows) v.a = cpx<T>{T(0), T(0)};
+          if (r1 >= a.rows) v.b = cpx<T>{T(0), T(0)};
+          if (h == 0) {
+            // the h = 0 bin of a real line is real: an imaginary part left there
+            // by rounding would otherwise leak into the other line of the pair
+            v.a.y = T(0);
+            v.b.y = T(0);
+          }
+          lds[line * ls + h] = cpx<T>{v.a.x - v.b.y, v.a.y + v.b.x};
+          if (h > 0) lds[line * ls + n - h] = cpx<T>{v.a.x + v.b.y, v.b.x - v.a.y};
+        });
     __syncthreads();
     P::template fft<T, +1>(lds, a.plan, d * RP, ls, a.tw);
   } else if (MODE == ROW_FWD) {
-    for (int f = threadIdx.x; f < d * RP * n; f += NT) {
-      const int line = f / n, x = f % n;
-      const int comp = line / RP, lp = line % RP;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      T ua = T(0), ub = T(0);
-      if (r0 < a.rows) {
-        const double* src = a.ureal + (long)item * a.real_stride + (long)comp * a.real_cstride;
-        ua = T(src[(long)r0 * n + x]);
-        if (r1 < a.rows) ub = T(src[(long)r1 * n + x]);
-      }
-      lds[line * ls + x] = cpx<T>{ua, ub};
-    }
+    in_rounds<NT, CHL>(
+        d * RP * n,
+        [=](int f) __attribute__((always_inline)) {
+          const int line = f / n, x = f % n;
+          const int comp = line / RP, lp = line % RP;
+          const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+          cpx<T> u{T(0), T(0)};
+          if (r0 < a.rows) {
+            const double* src = a.ureal + (long)item * a.real_stride + (long)comp * a.real_cstride;
+            u.x = T(src[(long)r0 * n + x]);
+            if (r1 < a.rows) u.y = T(src[(long)r1 * n + x]);
+          }
+          return u;
+        },
+        [=](int f, const cpx<T>& u) __attribute__((always_inline)) { lds[(f / n) * ls + f % n] = u; });
     __syncthreads();
   }
 
   if (MODE == ROW_SYNTH) {
     const double* E = a.E + (long)item * d;
+    // once per solve: a plain loop
     for (int f = threadIdx.x; f < d * RP * n; f += NT) {
       const int line = f / n, x = f % n;
       const int comp = line / RP, lp = line % RP;
@@ -536,45 +664,60 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
 
   if (MODE == ROW_APPLY || MODE == ROW_CONST) {
     const T* A = a.A + (long)(item / a.A_group) * a.A_stride;
-    for (int f = threadIdx.x; f < RP * n; f += NT) {
-      const int lp = f / n, x = f % n;
-      const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-      if (r0 >= a.rows) continue;
-      T e0[3], e1[3], j0[3], j1[3];
-      if (MODE == ROW_CONST) {
-        const double* E = a.E + (long)item * d;
-        for (int q = 0; q < d; ++q) e0[q] = e1[q] = T(E[q]);
-      } else {
-        for (int q = 0; q < d; ++q) {
-          const cpx<T> z = lds[(q * RP + lp) * ls + x];
-          e0[q] = z.x;
-          e1[q] = z.y;
-        }
-      }
-      flux_point<T>(a.kind, d, A, a.A_cstride, (long)r0 * n + x, e0, j0);
-      flux_point<T>(a.kind, d, A, a.A_cstride, (long)((r1 < a.rows) ? r1 : r0) * n + x, e1, j1);
-      for (int q = 0; q < d; ++q) lds[(q * RP + lp) * ls + x] = cpx<T>{j0[q], j1[q]};
-    }
+    in_rounds<NT, (CHL + 1) / 2>(
+        RP * n,
+        [=](int f) __attribute__((always_inline)) {
+          const int lp = f / n, x = f % n;
+          const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+          Coef2<T> v;
+          load_coef<T>(a.kind, d, A, a.A_cstride, (long)min(r0, a.rows - 1) * n + x, v.c0);
+          load_coef<T>(a.kind, d, A, a.A_cstride, (long)min(r1, a.rows - 1) * n + x, v.c1);
+          return v;
+        },
+        [=](int f, const Coef2<T>& v) __attribute__((always_inline)) {
+          const int lp = f / n, x = f % n;
+          const int r0 = 2 * (pair0 + lp);
+          if (r0 >= a.rows) return;
+          T e0[3], e1[3], j0[3], j1[3];
+          if (MODE == ROW_CONST) {
+            const double* E = a.E + (long)item * d;
+            for (int q = 0; q < d; ++q) e0[q] = e1[q] = T(E[q]);
+          } else {
+            for (int q = 0; q < d; ++q) {
+              const cpx<T> z = lds[(q * RP + lp) * ls + x];
+              e0[q] = z.x;
+              e1[q] = z.y;
+            }
+          }
+          flux_coef<T>(a.kind, d, v.c0, e0, j0);
+          flux_coef<T>(a.kind, d, v.c1, e1, j1);
+          for (int q = 0; q < d; ++q) lds[(q * RP + lp) * ls + x] = cpx<T>{j0[q], j1[q]};
+        });
     __syncthreads();
   }
 
   // forward transform and split of the two packed real lines
   P::template fft<T, -1>(lds, a.plan, d * RP, ls, a.tw);
   const T half = T(0.5) / T(n);
-  for (int f = threadIdx.x; f < d * RP * H; f += NT) {
-    const int line = f / H, h = f % H;
-    const int comp = line / RP, lp = line % RP;
-    const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
-    if (r0 >= a.rows) continue;
-    const cpx<T> zh = lds[line * ls + h];
-    const cpx<T> zm = lds[line * ls + (h == 0 ? 0 : n - h)];
-    // A = (Z(h) + conj Z(n-h)) / 2,  B = (Z(h) - conj Z(n-h)) / (2 i)
-    const cpx<T> va = {(zh.x + zm.x) * half, (zh.y - zm.y) * half};
-    const cpx<T> vb = {(zh.y + zm.y) * half, (zm.x - zh.x) * half};
-    cpx<T>* dst = a.out + (long)item * a.out_stride + (long)comp * a.out_cstride;
-    dst[(long)r0 * H + h] = va;
-    if (r1 < a.rows) dst[(long)r1 * H + h] = vb;
-  }
+  in_rounds<NT, CHL>(
+      d * RP * H,
+      [=](int f) __attribute__((always_inline)) {
+        const int line = f / H, h = f % H;
+        return cpx2<T>{lds[line * ls + h], lds[line * ls + (h == 0 ? 0 : n - h)]};
+      },
+      [=](int f, const cpx2<T>& z) __attribute__((always_inline)) {
+        const int line = f / H, h = f % H;
+        const int comp = line / RP, lp = line % RP;
+        const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+        if (r0 >= a.rows) return;
+        const cpx<T> zh = z.a, zm = z.b;
+        // A = (Z(h) + conj Z(n-h)) / 2,  B = (Z(h) - conj Z(n-h)) / (2 i)
+        const cpx<T> va = {(zh.x + zm.x) * half, (zh.y - zm.y) * half};
+        const cpx<T> vb = {(zh.y + zm.y) * half, (zm.x - zh.x) * half};
+        cpx<T>* dst = a.out + (long)item * a.out_stride + (long)comp * a.out_cstride;
+        dst[(long)r0 * H + h] = va;
+        if (r1 < a.rows) dst[(long)r1 * H + h] = vb;
+      });
 }
 
 }  // namespace hom

@@ -85,9 +85,31 @@ template <class T>
 __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   const int item = blockIdx.y;
   if (!a.sc[item].active) return;
+  // rounds of CH elements per thread (grid-stride); the first round's loads go
+  // out before alpha is derived
+  constexpr int CH = 4;
+  const long base = (long)item * a.stride;
+  const long step = (long)gridDim.x * blockDim.x;
+  cpx<T> pv[CH], qv[CH], xv[CH], rv[CH];
+  auto load = [&](long e0) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      // unconditional (past the end: element count - 1 again, unused)
+      const long e = min(e0 + u * step, a.count - 1);
+      pv[u] = a.p[base + e];
+      qv[u] = a.q[base + e];
+      xv[u] = a.x[base + e];
+      rv[u] = a.r[base + e];
+    }
+  };
   // alpha = rho / (p, q), derived by every workgroup from the projection's
-  // partials in the same order
-  const double g = sum_partials_all<kThreads>(a.pq_part + (long)item * a.P, a.pq_n);
+  // partials in the same order (their first loads go out ahead of the data's)
+  const double* pq = a.pq_part + (long)item * a.P;
+  double ph[8];
+  partials_head(pq, a.pq_n, ph);
+  long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  load(e0);
+  const double g = partials_finish(pq, a.pq_n, ph);
   if (!(g > 0.0) || !isfinite(g)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.sc[item].gamma = g;
@@ -102,20 +124,24 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
     a.sc[item].alpha = alpha64;
   }
   const T alpha = T(alpha64);
-  const long base = (long)item * a.stride;
   double part = 0.0;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < a.count;
-       e += (long)gridDim.x * blockDim.x) {
-    const cpx<T> pv = a.p[base + e], qv = a.q[base + e];
-    cpx<T> xv = a.x[base + e], rv = a.r[base + e];
-    xv.x += alpha * pv.x;
-    xv.y += alpha * pv.y;
-    rv.x -= alpha * qv.x;
-    rv.y -= alpha * qv.y;
-    a.x[base + e] = xv;
-    a.r[base + e] = rv;
-    const double wt = (((e / a.n0) % a.H) == 0) ? 1.0 : 2.0;
-    part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
+  while (e0 < a.count) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const long e = e0 + u * step;
+      if (e < a.count) {
+        xv[u].x += alpha * pv[u].x;
+        xv[u].y += alpha * pv[u].y;
+        rv[u].x -= alpha * qv[u].x;
+        rv[u].y -= alpha * qv[u].y;
+        a.x[base + e] = xv[u];
+        a.r[base + e] = rv[u];
+        const double wt = (((e / a.n0) % a.H) == 0) ? 1.0 : 2.0;
+        part += wt * ((double)rv[u].x * (double)rv[u].x + (double)rv[u].y * (double)rv[u].y);
+      }
+    }
+    e0 += CH * step;
+    if (e0 < a.count) load(e0);
   }
   part = block_sum<kThreads>(part);
   if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
@@ -125,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(ItemScal* sc, const double
                                                       int nparts, const ItemScal* mask) {
   const int item = blockIdx.x;
   if (!sc[item].active || (mask && !mask[item].active)) return;
-  const double s = sum_partials(partials + (long)item * P, nparts);
+  const double s = sum_partials_wave(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
     ItemScal& q = sc[item];
     q.rho = q.rho0 = s;
@@ -144,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_finalize(ItemScal* sc, const do
                                                           int P, int nparts) {
   const int item = blockIdx.x;
   if (!sc[item].active || sc[item].fresh) return;
-  const double s = sum_partials(partials + (long)item * P, nparts);
+  const double s = sum_partials_wave(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
     cg_book(sc[item], s);
     sc[item].fresh = 1;
@@ -156,7 +182,7 @@ __global__ __launch_bounds__(kThreads) void k_outer_check(ItemScal* sc, const do
                                                           const ItemScal* mask) {
   const int item = blockIdx.x;
   if (!sc[item].active || (mask && !mask[item].active)) return;
-  const double s = sum_partials(partials + (long)item * P, nparts);
+  const double s = sum_partials_wave(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
     ItemScal& q = sc[item];
     if (init) {
@@ -224,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_init(ItemScal* inner, const 
                                                          const ItemScal* mask) {
   const int item = blockIdx.x;
   if ((mask && !mask[item].active) || !outer[item].active) return;
-  const double s = sum_partials(partials + (long)item * P, nparts);
+  const double s = sum_partials_wave(partials + (long)item * P, nparts);
   if (threadIdx.x == 0) {
     ItemScal& q = inner[item];
     // residual replacement: carry the direction on with beta rescaled to the
