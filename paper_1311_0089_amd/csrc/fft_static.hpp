@@ -120,37 +120,159 @@ __device__ __forceinline__ void sstage(cpx<T>* buf, const cpx<T>* __restrict__ t
   __syncthreads();
 }
 
-template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, int Ns, int OFF, int... Rs>
+// cos / sin (2 pi t / R) rounded once to FP32 (the values the register DFT of
+// the same radix uses), as a device table for per-lane lookups
+template <int R>
+struct MfmaRoots {
+  float c[R], s[R];
+  constexpr MfmaRoots() : c(), s() {
+    for (int t = 0; t < R; ++t) {
+      c[t] = float(cos2pi(t, R));
+      s[t] = float(sin2pi(t, R));
+    }
+  }
+};
+template <int R>
+__device__ constexpr MfmaRoots<R> kMfmaRoots{};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// First Stockham stage (Ns = 1, no twiddles) of an odd radix R <= 31 on the
+// matrix cores.  With s_0 = v_0, s_j = v_j + v_{R-j}, d_j = v_j - v_{R-j}
+// (j = 1..H, H = (R-1)/2, zero past H), the butterfly outputs are
+// y_0 = P_0, y_k = P_k + S i Q_k and y_{R-k} = P_k - S i Q_k (k = 1..H), where
+// P = C s and Q = Sn d with C_kj = cos(2 pi jk/R), Sn_kj = sin(2 pi jk/R),
+// k, j = 0..15 -- the symmetric-pair form of the register DFT, as products of
+// 16x16 constant matrices with 16 butterflies at a time (the columns).  Each
+// 16-butterfly column block takes KC steps of v_mfma_f32_16x16x4_f32 per real
+// part (P re, P im, Q re, Q im); lane l supplies row (l mod 16) of the
+// constant and column (l mod 16) of the data at K index l / 16, and holds
+// rows 4 (l / 16) .. 4 (l / 16) + 3 of column l mod 16 of the result.
+template <int R, int S, int LEN, int W, bool WF, int LS, int ES, int NT>
+__device__ __forceinline__ void mstage(cpx<float>* buf) {
+  constexpr int H = (R - 1) / 2;
+  constexpr int KC = (H + 1 + 3) / 4;
+  constexpr int nb = LEN / R, total = nb * W;
+  constexpr int NCB = (total + 15) / 16;
+  constexpr int NW = NT / 64;
+  constexpr int CPW = (NCB + NW - 1) / NW;
+  static_assert(NT % 64 == 0 && H + 1 <= 16, "matrix-core stage shape");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  float ca[KC], sa[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const int j = 4 * c + g, t = (n * j) % R;
+    ca[c] = (j <= H) ? kMfmaRoots<R>.c[t] : 0.f;
+    sa[c] = (j <= H) ? kMfmaRoots<R>.s[t] : 0.f;
+  }
+  auto at = [](int f, int& w, int& b) __attribute__((always_inline)) {
+    if (WF) {
+      w = f % W;
+      b = f / W;
+    } else {
+      b = f % nb;
+      w = f / nb;
+    }
+  };
+  f32x4 pr[CPW], pi[CPW], qr[CPW], qi[CPW];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    pr[q] = pi[q] = qr[q] = qi[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int cb = wave + q * NW;
+    if (cb < NCB) {   // the same for every lane of the wave
+      int w, b;
+      at(min(cb * 16 + n, total - 1), w, b);
+      const cpx<float>* line = buf + w * LS;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const int j = 4 * c + g;
+        float sr = 0.f, si = 0.f, dr = 0.f, di = 0.f;
+        if (j == 0) {
+          const cpx<float> v0 = line[b * ES];
+          sr = v0.x;
+          si = v0.y;
+        } else if (j <= H) {
+          const cpx<float> x = line[(b + j * nb) * ES], y = line[(b + (R - j) * nb) * ES];
+          sr = x.x + y.x;
+          si = x.y + y.y;
+          dr = x.x - y.x;
+          di = x.y - y.y;
+        }
+        pr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[c], sr, pr[q], 0, 0, 0);
+        pi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[c], si, pi[q], 0, 0, 0);
+        qr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[c], dr, qr[q], 0, 0, 0);
+        qi[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[c], di, qi[q], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int cb = wave + q * NW, f = cb * 16 + n;
+    if (cb < NCB && f < total) {
+      int w, b;
+      at(f, w, b);
+      cpx<float>* o = buf + w * LS + b * R * ES;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 4 * g + r;
+        const float Pr = pr[q][r], Pi = pi[q][r], Qr = qr[q][r], Qi = qi[q][r];
+        if (k == 0) {
+          o[0] = cpx<float>{Pr, Pi};
+        } else if (k <= H) {
+          o[k * ES] = cpx<float>{Pr - float(S) * Qi, Pi + float(S) * Qr};
+          o[(R - k) * ES] = cpx<float>{Pr + float(S) * Qi, Pi - float(S) * Qr};
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// the matrix-core form serves the first stage of FP32 transforms with an odd
+// radix of 17 or more (where the register DFT's quadratic cost dominates)
+template <class T, int R, int Ns, bool MF>
+constexpr bool use_mstage() {
+  return MF && Ns == 1 && R % 2 == 1 && R >= 17 && R <= 31 && sizeof(T) == 4;
+}
+
+template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, bool MF, int Ns, int OFF,
+          int... Rs>
 struct SStages;
-template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, int Ns, int OFF>
-struct SStages<T, S, LEN, W, WF, LS, ES, NT, Ns, OFF> {
+template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, bool MF, int Ns, int OFF>
+struct SStages<T, S, LEN, W, WF, LS, ES, NT, MF, Ns, OFF> {
   __device__ __forceinline__ static void run(cpx<T>*, const cpx<T>*) {}
 };
-template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, int Ns, int OFF, int R,
-          int... Rest>
-struct SStages<T, S, LEN, W, WF, LS, ES, NT, Ns, OFF, R, Rest...> {
+template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, bool MF, int Ns, int OFF,
+          int R, int... Rest>
+struct SStages<T, S, LEN, W, WF, LS, ES, NT, MF, Ns, OFF, R, Rest...> {
   __device__ __forceinline__ static void run(cpx<T>* buf, const cpx<T>* tw) {
-    sstage<T, R, S, LEN, W, WF, LS, ES, Ns, NT>(buf, tw + OFF);
-    SStages<T, S, LEN, W, WF, LS, ES, NT, Ns * R, OFF + (Ns > 1 ? Ns * (R - 1) : 0),
+    if constexpr (use_mstage<T, R, Ns, MF>())
+      mstage<R, S, LEN, W, WF, LS, ES, NT>(buf);
+    else
+      sstage<T, R, S, LEN, W, WF, LS, ES, Ns, NT>(buf, tw + OFF);
+    SStages<T, S, LEN, W, WF, LS, ES, NT, MF, Ns * R, OFF + (Ns > 1 ? Ns * (R - 1) : 0),
             Rest...>::run(buf, tw);
   }
 };
 
-template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, class R_>
+template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, bool MF, class R_>
 struct SStockham;
-template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, int... Rs>
-struct SStockham<T, S, LEN, W, WF, LS, ES, NT, Rad<Rs...>> {
+template <class T, int S, int LEN, int W, bool WF, int LS, int ES, int NT, bool MF, int... Rs>
+struct SStockham<T, S, LEN, W, WF, LS, ES, NT, MF, Rad<Rs...>> {
   __device__ __forceinline__ static void run(cpx<T>* buf, const cpx<T>* tw) {
-    SStages<T, S, LEN, W, WF, LS, ES, NT, 1, 0, Rs...>::run(buf, tw);
+    SStages<T, S, LEN, W, WF, LS, ES, NT, MF, 1, 0, Rs...>::run(buf, tw);
   }
 };
 
-// full n-point DFT of sign S on W lines (layout: element (w, i) at w*LS + i*ES)
-template <class T, int S, class SP, int W, bool WF, int LS, int ES, int NT>
+// full n-point DFT of sign S on W lines (layout: element (w, i) at w*LS + i*ES);
+// MF: first stage on the matrix cores where use_mstage allows it
+template <class T, int S, class SP, int W, bool WF, int LS, int ES, int NT, bool MF = false>
 __device__ __forceinline__ void sfft(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   using R_ = typename SP::radices;
   if constexpr (!SP::blue) {
-    SStockham<T, S, SP::len, W, WF, LS, ES, NT, R_>::run(buf, tw);
+    SStockham<T, S, SP::len, W, WF, LS, ES, NT, MF, R_>::run(buf, tw);
   } else {
     constexpr int n = SP::n, m = SP::len;
     constexpr int chirp_off = TwSizeOf<R_>::v;
@@ -170,7 +292,7 @@ __device__ __forceinline__ void sfft(cpx<T>* buf, const cpx<T>* __restrict__ tw)
       }
     }
     __syncthreads();
-    SStockham<T, -1, m, W, WF, LS, ES, NT, R_>::run(buf, tw);
+    SStockham<T, -1, m, W, WF, LS, ES, NT, false, R_>::run(buf, tw);
     for (int f = threadIdx.x; f < m * W; f += NT) {
       int w, j;
       if (WF) { w = f % W; j = f / W; } else { j = f % m; w = f / m; }
@@ -178,7 +300,7 @@ __device__ __forceinline__ void sfft(cpx<T>* buf, const cpx<T>* __restrict__ tw)
       *e = cmul(*e, D[j]);
     }
     __syncthreads();
-    SStockham<T, +1, m, W, WF, LS, ES, NT, R_>::run(buf, tw);
+    SStockham<T, +1, m, W, WF, LS, ES, NT, false, R_>::run(buf, tw);
     for (int f = threadIdx.x; f < n * W; f += NT) {
       int w, j;
       if (WF) { w = f % W; j = f / W; } else { j = f % n; w = f / n; }

@@ -29,6 +29,7 @@ struct ColGen {
   static constexpr int NT = kThreads;
   static constexpr int CP = 1;   // components per transform call
   static constexpr int SL = 0;
+  static constexpr int WC = 0;   // tile width when known at compile time
   __device__ static int W(int w) { return w; }
   __device__ static int nfft(int n) { return n; }
   __device__ static int ntrial(int n) { return n; }
@@ -55,6 +56,7 @@ struct ColStat {
   static constexpr int NT = NT_;
   static constexpr int CP = 1;
   static constexpr int SL = SL_;
+  static constexpr int WC = W_;
   // only the column-major mapping (axis 0 across the threads) needs the pad
   static constexpr int RL = (SL_ == 1) ? odd_rowlen(W_) : W_;
   __device__ static constexpr int W(int) { return W_; }
@@ -75,10 +77,11 @@ struct ColStat {
 // all D_ components of a W_-column tile side by side in one LDS tile
 // ([row][component][column]) and transformed by one call, so the block's
 // threads share the stages of every component and its loads are issued together
-template <class SP, int NTRIAL, int W_, int D_, int NT_>
+template <class SP, int NTRIAL, int W_, int D_, int NT_, bool MF_ = false>
 struct ColStatCP {
   static constexpr int NT = NT_;
   static constexpr int CP = D_;
+  static constexpr int WC = W_;
   static constexpr int SL = (D_ == 2) ? 1 : 2;   // the layout cells with D_ components use
   static constexpr int RL = (SL == 1) ? odd_rowlen(D_ * W_) : D_ * W_;
   __device__ static constexpr int W(int) { return W_; }
@@ -88,7 +91,7 @@ struct ColStatCP {
   template <class T, int S>
   __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan&, int,
                                                   const cpx<T>* tw) {
-    sfft<T, S, SP, D_ * W_, true, 1, RL, NT_>(lds, tw);
+    sfft<T, S, SP, D_ * W_, true, 1, RL, NT_, MF_>(lds, tw);
   }
 };
 
@@ -109,7 +112,7 @@ struct RowGen {
   }
 };
 
-template <class SP, int NTRIAL, int D_, int RP_, int NT_>
+template <class SP, int NTRIAL, int D_, int RP_, int NT_, bool MF_ = false>
 struct RowStat {
   static constexpr int NT = NT_;
   template <class T>
@@ -122,17 +125,24 @@ struct RowStat {
   template <class T, int S>
   __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan&, int, int,
                                              const cpx<T>* tw) {
-    sfft<T, S, SP, D_ * RP_, false, SP::len, 1, NT_>(lds, tw);
+    sfft<T, S, SP, D_ * RP_, false, SP::len, 1, NT_, MF_>(lds, tw);
   }
 };
 
 __device__ __forceinline__ int kof(int i, int n) { return (i <= (n - 1) / 2) ? i : i - n; }
 __device__ __forceinline__ int posk(int k, int n) { return k < 0 ? k + n : k; }
 
-// unit normal n(k) = xi / |xi| (0 at k = 0); column index -> (k1, h) in 3-D, h in 2-D
+// unit normal n(k) = xi / |xi| (0 at k = 0), split into the part that depends
+// on the column only (column index -> (k1, h) in 3-D, h in 2-D), evaluated once
+// per column, and the axis-0 wavenumber k0 of each position
 template <class T>
-__device__ __forceinline__ void unit_normal(const NormalGeo& g, int k0, int col, T* nv) {
-  T xi0 = T(k0) * T(g.invY[0]), xi1, xi2 = T(0);
+struct ColXi {
+  T x1, x2, c;   // xi_1, xi_2, xi_1^2 + xi_2^2
+};
+
+template <class T>
+__device__ __forceinline__ ColXi<T> col_xi(const NormalGeo& g, int col) {
+  T xi1, xi2 = T(0);
   if (g.d == 3) {
     const int k1 = kof(col / g.H, g.N1);
     const int h = col % g.H;
@@ -141,11 +151,20 @@ __device__ __forceinline__ void unit_normal(const NormalGeo& g, int k0, int col,
   } else {
     xi1 = T(col) * T(g.invY[1]);
   }
-  const T s = xi0 * xi0 + xi1 * xi1 + xi2 * xi2;
-  const T inv = s > T(0) ? T(1) / sqrt(s) : T(0);
+  return ColXi<T>{xi1, xi2, xi1 * xi1 + xi2 * xi2};
+}
+
+__device__ __forceinline__ float inv_sqrt(float s) { return rsqrtf(s); }
+__device__ __forceinline__ double inv_sqrt(double s) { return 1.0 / sqrt(s); }
+
+template <class T>
+__device__ __forceinline__ void unit_normal(const NormalGeo& g, int k0, const ColXi<T>& cx, T* nv) {
+  const T xi0 = T(k0) * T(g.invY[0]);
+  const T s = xi0 * xi0 + cx.c;
+  const T inv = s > T(0) ? inv_sqrt(s) : T(0);
   nv[0] = xi0 * inv;
-  nv[1] = xi1 * inv;
-  nv[2] = xi2 * inv;
+  nv[1] = cx.x1 * inv;
+  nv[2] = cx.x2 * inv;
 }
 
 template <int NT>
@@ -305,15 +324,12 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
     beta = T(s / q.rho);
   }
   cpx<T> s[PMAX];
-  int row[PMAX];
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
-    row[it] = -1;
     int i, w;
     const bool in = pos(it, i, w);
     s[it] = (in && w < ncols) ? rv[it] : cpx<T>{T(0), T(0)};
     if (in) {
-      row[it] = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
       if (a.fuse && w < ncols) {
         // beta = 0 restarts the direction: p = r exactly, whatever p held
         const cpx<T> p = (beta == T(0)) ? rv[it]
@@ -323,6 +339,11 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
       }
     }
   }
+  // with row-major positions and NT a multiple of the tile width every
+  // position of a thread lies in the same column: its part of xi is evaluated once
+  constexpr bool col_fixed = (P::SL == 2) && P::WC > 0 && (NT % P::WC) == 0;
+  ColXi<T> cx0{};
+  if (col_fixed) cx0 = col_xi<T>(a.g, min(col0 + (int)threadIdx.x % W, a.inner - 1));
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
@@ -334,12 +355,13 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
     }
 #pragma unroll
     for (int it = 0; it < PMAX; ++it) {
-      if (row[it] >= 0) {
-        const int f = threadIdx.x + it * NT;
-        const int i = colm ? f % n_in : f / W, w = colm ? f / n_in : f % W;
+      int i, w;
+      if (pos(it, i, w)) {
+        const int row = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
         T nv[3];
-        unit_normal<T>(a.g, kof(i, n_in), min(col0 + w, a.inner - 1), nv);
-        for (int c = 0; c < nc; ++c) lds[row[it] * LW + c * W + w] = cscale(s[it], nv[al0 + c]);
+        unit_normal<T>(a.g, kof(i, n_in),
+                       col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1)), nv);
+        for (int c = 0; c < nc; ++c) lds[row * LW + c * W + w] = cscale(s[it], nv[al0 + c]);
       }
     }
     __syncthreads();
@@ -426,18 +448,20 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   const int ncols = min(W, a.inner - col0);
   const int npos = n_out * W;
   const bool colm = (P::SL == 0) ? (a.si == 1) : (P::SL == 1);
-  cpx<T> acc[PMAX];
-  int row[PMAX];
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    acc[it] = cpx<T>{T(0), T(0)};
+  auto pos = [=](int it, int& i, int& w) __attribute__((always_inline)) {
     const int f = threadIdx.x + it * NT;
-    row[it] = -1;
-    if (f < npos) {
-      const int i = colm ? f % n_out : f / W;
-      row[it] = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
-    }
-  }
+    i = colm ? f % n_out : f / W;
+    w = colm ? f / n_out : f % W;
+    return f < npos;
+  };
+  cpx<T> acc[PMAX];
+#pragma unroll
+  for (int it = 0; it < PMAX; ++it) acc[it] = cpx<T>{T(0), T(0)};
+  // with row-major positions and NT a multiple of the tile width every
+  // position of a thread lies in the same column: its part of xi is evaluated once
+  constexpr bool col_fixed = (P::SL == 2) && P::WC > 0 && (NT % P::WC) == 0;
+  ColXi<T> cx0{};
+  if (col_fixed) cx0 = col_xi<T>(a.g, min(col0 + (int)threadIdx.x % W, a.inner - 1));
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
@@ -458,13 +482,14 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
     P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
 #pragma unroll
     for (int it = 0; it < PMAX; ++it) {
-      if (row[it] >= 0) {
-        const int f = threadIdx.x + it * NT;
-        const int i = colm ? f % n_out : f / W, w = colm ? f / n_out : f % W;
+      int i, w;
+      if (pos(it, i, w)) {
+        const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
         T nv[3];
-        unit_normal<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1), nv);
+        unit_normal<T>(a.g, kof(i, n_out),
+                       col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1)), nv);
         for (int c = 0; c < nc; ++c) {
-          const cpx<T> v = lds[row[it] * LW + c * W + w];
+          const cpx<T> v = lds[row * LW + c * W + w];
           acc[it].x += nv[al0 + c] * v.x;
           acc[it].y += nv[al0 + c] * v.y;
         }
@@ -479,19 +504,21 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
   cpx<T> lv[PMAX];
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
-    const int f = threadIdx.x + it * NT;
-    const int i = colm ? f % n_out : f / W, w = colm ? f / n_out : f % W;
+    int i, w;
+    pos(it, i, w);
     lv[it] = cpx<T>{T(0), T(0)};
     if (ld) lv[it] = ld[sb + (long)min(i, n_out - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_];
   }
+  // Hermitian weight of a column: 1 on the h = 0 plane, else 2
+  const double wt0 = col_fixed ? (((col0 + (int)threadIdx.x % W) % a.g.H) == 0 ? 1.0 : 2.0) : 0.0;
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
-    const int f = threadIdx.x + it * NT;
-    const int i = colm ? f % n_out : f / W, w = colm ? f / n_out : f % W;
-    if (row[it] >= 0 && w < ncols) {
+    int i, w;
+    if (pos(it, i, w) && w < ncols) {
       const int col = col0 + w;
       const long idx = sb + (long)i * a.si + (long)col * a.sc_;
-      const double wt = ((col % a.g.H) == 0) ? 1.0 : 2.0;
+      const int h = col_fixed ? 1 : (a.g.d == 3) ? col % a.g.H : col;   // 2-D: column = h
+      const double wt = col_fixed ? wt0 : (h == 0 ? 1.0 : 2.0);
       cpx<T> qv = cscale(acc[it], a.scale);
       if (a.epi == EPI_STORE) {
         a.q[idx] = qv;

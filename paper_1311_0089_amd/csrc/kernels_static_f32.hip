@@ -28,6 +28,12 @@ RegColCP<T, P1023, 1023, 4, 2, 512> x1023_4;
 RegColCP<T, P1023, 1023, 2, 2, 256> x1023_2;
 RegColCP<T, P1023, 1023, 1, 2, 128> x1023_1;
 RegColCP<T, P1023, 1023, 3, 2, 384> x1023_3;
+RegColCP<T, P1023, 1023, 2, 2, 512> x1023_2w;
+RegColCP<T, P1023, 1023, 1, 2, 256> x1023_1w;
+// first (radix-31) stage on the matrix cores
+RegColCP<T, P1023, 1023, 2, 2, 256, true> x1023_2m;
+RegColCP<T, P1023, 1023, 1, 2, 128, true> x1023_1m;
+RegColCP<T, P1023, 1023, 4, 2, 512, true> x1023_4m;
 RegColCP<T, P255, 255, 8, 3, 384> x255_8;
 RegColCP<T, P255, 255, 4, 3, 192> x255_4;
 RegColCP<T, P255, 255, 16, 3, 768> x255_16;
@@ -41,6 +47,10 @@ RegRow<T, P1023, 1023, 2, 2, 256> r1023_2;
 RegRow<T, P1023, 1023, 2, 4, 512> r1023_2w;
 RegRow<T, P1023, 1023, 2, 1, 128> r1023_2n;
 RegRow<T, P1023, 1023, 2, 3, 384> r1023_2m;
+RegRow<T, P1023, 1023, 2, 1, 256> r1023_2nw;
+RegRow<T, P1023, 1023, 2, 2, 512> r1023_2w2;
+RegRow<T, P1023, 1023, 2, 1, 128, true> r1023_2nm;
+RegRow<T, P1023, 1023, 2, 2, 256, true> r1023_2mm;
 RegRow<T, P1023, 1023, 3, 2, 512> r1023_3;
 RegRow<T, P255, 255, 2, 8, 256> r255_2;
 RegRow<T, P255, 255, 3, 8, 512> r255_3;

@@ -61,7 +61,7 @@ struct RegCol {
 
 // axis-0 expand and project with all D components of a W-column tile in one
 // LDS tile and one transform call (matches cells with D device components)
-template <class T, class SP, int NTRIAL, int W, int D, int NT>
+template <class T, class SP, int NTRIAL, int W, int D, int NT, bool MF = false>
 struct RegColCP {
   static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
   static constexpr size_t lds =
@@ -69,7 +69,7 @@ struct RegColCP {
   static_assert(lds <= 150 * 1024, "column tile exceeds the LDS of a CU");
   static_assert(PMAX <= 32, "too many positions per thread");
   RegColCP() {
-    using P = ColStatCP<SP, NTRIAL, W, D, NT>;
+    using P = ColStatCP<SP, NTRIAL, W, D, NT, MF>;
     add(KK_EXPAND, (const void*)&k_col_expand<T, P, PMAX>);
     add(KK_PROJECT, (const void*)&k_col_project<T, P, PMAX>);
   }
@@ -91,12 +91,12 @@ struct RegColCP {
   }
 };
 
-template <class T, class SP, int NTRIAL, int D, int RP, int NT>
+template <class T, class SP, int NTRIAL, int D, int RP, int NT, bool MF = false>
 struct RegRow {
   static constexpr size_t lds = (size_t)D * RP * SP::len * sizeof(cpx<T>);
   static_assert(lds <= 66 * 1024 + 512, "row tile exceeds the LDS budget");
   RegRow() {
-    using P = RowStat<SP, NTRIAL, D, RP, NT>;
+    using P = RowStat<SP, NTRIAL, D, RP, NT, MF>;
     add(KK_ROW, (const void*)&k_row<T, P, ROW_APPLY>);
     // the FP64 right-hand side and strain synthesis passes of the same shape
     if constexpr (sizeof(T) == 8) {
