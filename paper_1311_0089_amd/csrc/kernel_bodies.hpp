@@ -51,7 +51,7 @@ struct ColGen {
 // those accesses onto few LDS banks
 __host__ __device__ constexpr int odd_rowlen(int lw) { return (lw > 1 && lw % 2 == 0) ? lw + 1 : lw; }
 
-template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0>
+template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0, bool MF_ = false>
 struct ColStat {
   static constexpr int NT = NT_;
   static constexpr int CP = 1;
@@ -65,12 +65,12 @@ struct ColStat {
   __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
   __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
-    sfft<T, S, SP, W_, true, 1, W_, NT_>(lds, tw);
+    sfft<T, S, SP, W_, true, 1, W_, NT_, MF_>(lds, tw);
   }
   template <class T, int S>
   __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan&, int,
                                                   const cpx<T>* tw) {
-    sfft<T, S, SP, W_, true, 1, RL, NT_>(lds, tw);
+    sfft<T, S, SP, W_, true, 1, RL, NT_, MF_>(lds, tw);
   }
 };
 
@@ -299,10 +299,11 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
   // derived from the partials, behind the first loads of those partials
   // (unconditional: positions outside the tile read an element inside it again)
   const bool derive = a.fuse && a.rr_part && !a.sc[item].fresh;
+  const bool xd = a.fuse && a.xdef;
   const double* rr = a.rr_part + (long)item * a.P;
   double ph[8];
   if (derive) partials_head(rr, a.rr_n, ph);
-  cpx<T> rv[PMAX], pv[PMAX];
+  cpx<T> rv[PMAX], pv[PMAX], xv[PMAX];
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
     int i, w;
@@ -311,18 +312,37 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
     if (a.fuse) {
       rv[it] = a.r[idx];
       pv[it] = a.p[idx];
+      if (xd) xv[it] = a.x[idx];
     } else {
       rv[it] = a.c[idx];
     }
   }
+  // the update deferred by the last CG step: x += alpha p with the old p
+  auto x_update = [&]() __attribute__((always_inline)) {
+    const T alpha = T(a.sc[item].alpha);
+#pragma unroll
+    for (int it = 0; it < PMAX; ++it) {
+      int i, w;
+      if (pos(it, i, w) && w < ncols) {
+        cpx<T> x = xv[it];
+        x.x += alpha * pv[it].x;
+        x.y += alpha * pv[it].y;
+        a.x[ibase + (long)i * a.si + (long)(col0 + w) * a.sc_] = x;
+      }
+    }
+  };
   T beta = a.fuse ? T(a.sc[item].beta) : T(0);
   if (derive) {
     // s = (r, r) of the last update; its bookkeeping runs in the projection
     const double s = partials_finish(rr, a.rr_n, ph);
     const ItemScal q = a.sc[item];
-    if (cg_stops(q, s)) return;
+    if (cg_stops(q, s)) {
+      if (xd) x_update();
+      return;
+    }
     beta = T(s / q.rho);
   }
+  if (xd) x_update();
   cpx<T> s[PMAX];
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {

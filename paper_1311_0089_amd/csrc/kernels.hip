@@ -91,15 +91,18 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   const long base = (long)item * a.stride;
   const long step = (long)gridDim.x * blockDim.x;
   cpx<T> pv[CH], qv[CH], xv[CH], rv[CH];
+  const bool xupd = a.xupd != 0;
   auto load = [&](long e0) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       // unconditional (past the end: element count - 1 again, unused)
       const long e = min(e0 + u * step, a.count - 1);
-      pv[u] = a.p[base + e];
       qv[u] = a.q[base + e];
-      xv[u] = a.x[base + e];
       rv[u] = a.r[base + e];
+      if (xupd) {
+        pv[u] = a.p[base + e];
+        xv[u] = a.x[base + e];
+      }
     }
   };
   // alpha = rho / (p, q), derived by every workgroup from the projection's
@@ -130,11 +133,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
     for (int u = 0; u < CH; ++u) {
       const long e = e0 + u * step;
       if (e < a.count) {
-        xv[u].x += alpha * pv[u].x;
-        xv[u].y += alpha * pv[u].y;
+        if (xupd) {
+          xv[u].x += alpha * pv[u].x;
+          xv[u].y += alpha * pv[u].y;
+          a.x[base + e] = xv[u];
+        }
         rv[u].x -= alpha * qv[u].x;
         rv[u].y -= alpha * qv[u].y;
-        a.x[base + e] = xv[u];
         a.r[base + e] = rv[u];
         const double wt = (((e / a.n0) % a.H) == 0) ? 1.0 : 2.0;
         part += wt * ((double)rv[u].x * (double)rv[u].x + (double)rv[u].y * (double)rv[u].y);

@@ -33,6 +33,8 @@ constexpr double kTolSafety = 0.5;
 struct CgFuse {
   const double* rr;
   int rr_n;
+  // the last update left x to this expansion: x += alpha p (old p) here
+  int xdef;
 };
 
 // per-item solver scalars, device resident
@@ -74,6 +76,10 @@ struct ColExpandArgs {
   // from which every workgroup derives beta and the stopping test itself
   const double* rr_part;
   int rr_n, P;
+  // xdef != 0 (fused step): the last update left x += alpha p to this
+  // expansion, applied with the old p (also when the item stops here)
+  cpx<T>* x;
+  int xdef;
   NormalGeo g;
   FftPlan plan;
   const cpx<T>* tw;
@@ -157,6 +163,8 @@ struct CgUpdateArgs {
   // alpha = rho / (p, q) itself
   const double* pq_part;
   int pq_n;
+  // 1: x += alpha p here; 0: the next expansion does it (it reads p anyway)
+  int xupd;
 };
 
 // compile-time specialised pass kernels, registered by kernels_static*.hip

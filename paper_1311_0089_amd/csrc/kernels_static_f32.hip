@@ -74,5 +74,14 @@ RegRow<T, P29, 15, 2, 8, 256> r29_2;
 RegRow<T, P29, 15, 3, 8, 256> r29_3;
 RegRow<T, P509, 255, 2, 4, 512> r509_2;
 RegRow<T, P509, 255, 3, 2, 512> r509_3;
+// first (radix-17 / radix-23) stage on the matrix cores
+RegCol<T, P255, 255, 16, 256, true> c255m;
+RegCol<T, P255, 255, 8, 256, true> c255nm;
+RegCol<T, P253, 127, 16, 256, true> c253m;
+RegCol<T, P253, 127, 8, 256, true> c253nm;
+RegColCP<T, P255, 255, 8, 3, 384, true> x255_8m;
+RegColCP<T, P253, 127, 4, 3, 192, true> x253_4m;
+RegRow<T, P255, 255, 3, 4, 256, true> r255_3nm;
+RegRow<T, P253, 127, 3, 4, 256, true> r253_3nm;
 }  // namespace
 }  // namespace hom

@@ -268,6 +268,8 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   if (cg) {
     a.rr_part = cg->rr;
     a.rr_n = cg->rr_n;
+    a.x = w.x;
+    a.xdef = cg->xdef;
   }
   a.P = partial_slots(c);
   a.g = normal_geo(c);
@@ -549,8 +551,9 @@ template hipError_t pipe_rhs<double>(CellImpl*, Work<double>&, int, const double
 // CG iterations, captured K at a time into a HIP graph
 // ---------------------------------------------------------------------------
 template <class T>
-static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles) {
+static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles, bool xupd) {
   CgUpdateArgs<T> u{};
+  u.xupd = xupd ? 1 : 0;
   u.x = w.x;
   u.r = w.r;
   u.p = w.p;
@@ -570,18 +573,21 @@ static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles) {
 template <class T>
 static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K, bool finalize = true) {
   // one iteration: expansion (beta and stopping test from the last update's
-  // (r, r) partials, p <- r + beta p), the operator's passes, projection
-  // (q, (p, q) partials, bookkeeping of the last update), update (alpha from
-  // the (p, q) partials, x and r, (r, r) partials); after K iterations the
-  // last update is booked so the host reads current scalars
+  // (r, r) partials, x += alpha p left by that update, p <- r + beta p), the
+  // operator's passes, projection (q, (p, q) partials, bookkeeping of the last
+  // update), update (alpha from the (p, q) partials, r, (r, r) partials; x
+  // only in the last iteration, which leaves x current at the end of the
+  // graph); after K iterations the last update is booked so the host reads
+  // current scalars
   hipError_t e = hipSuccess;
   const int P = partial_slots(c);
   const int tiles = project_tiles<T>(c);
   const int ub = update_blocks(c->S);
-  const CgFuse cg{w.part2, ub};
   for (int k = 0; k < K && e == hipSuccess; ++k) {
+    const CgFuse cg{w.part2, ub, k > 0 ? 1 : 0};
     e = pipe_apply<T>(c, w, items, w.p, 1, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part, &cg);
-    if (e == hipSuccess) e = launch_cg_update<T>(update_args<T>(c, w, tiles), items, ub, c->stream);
+    if (e == hipSuccess)
+      e = launch_cg_update<T>(update_args<T>(c, w, tiles, k == K - 1), items, ub, c->stream);
   }
   if (e == hipSuccess && finalize) e = launch_cg_finalize(w.sc, w.part2, P, ub, items, c->stream);
   return e;
@@ -1355,9 +1361,11 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   std::vector<hipEvent_t> ev((size_t)reps * NK * 2, nullptr);
   for (auto& x : ev) (void)hipEventCreate(&x);
   std::vector<int> launched((size_t)reps * NK, 0);
-  const CgFuse cg{w.part2, ub};
   e = reset();
   for (int it = 0; it < reps && e == hipSuccess; ++it) {
+    // as inside a launched graph: x is left to the next expansion except in
+    // the last iteration
+    const CgFuse cg{w.part2, ub, it > 0 ? 1 : 0};
     hipEvent_t* E = ev.data() + (size_t)it * NK * 2;
     int* Ln = launched.data() + (size_t)it * NK;
     auto arm = [&](int k) {
@@ -1386,7 +1394,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     }
     if (e == hipSuccess) {
       arm(5);
-      e = launch_cg_update<T>(update_args<T>(c, w, tiles), L, ub, c->stream);
+      e = launch_cg_update<T>(update_args<T>(c, w, tiles, it == reps - 1), L, ub, c->stream);
     }
     if (e == hipSuccess && it == reps - 1) {
       arm(6);
@@ -1406,14 +1414,16 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   }
   for (int k = 0; k < 7; ++k) ms[7] += ms[k];
   if (c->dd != 3) ms[1] = ms[3] = 0.0;
-  bytes[0] = L * (3.0 * S * esz + (double)c->dd * Q0 * inner * esz);
+  // algorithmic bytes of the steady state inside a graph: the expansion reads
+  // r, p, x and writes p, x and the d fields; the update reads r, q, writes r
+  bytes[0] = L * (5.0 * S * esz + (double)c->dd * Q0 * inner * esz);
   if (c->dd == 3) {
     bytes[1] = L * (double)c->dd * Q0 * c->H * esz * (c->N[1] + Q1);
     bytes[3] = bytes[1];
   }
   bytes[2] = L * 2.0 * c->dd * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
   bytes[4] = L * ((double)c->dd * Q0 * inner * esz + 2.0 * S * esz);
-  bytes[5] = L * 6.0 * S * esz;
+  bytes[5] = L * 3.0 * S * esz;
   for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
   for (auto& x : ev) (void)hipEventDestroy(x);
   (void)hipStreamSynchronize(c->stream);
