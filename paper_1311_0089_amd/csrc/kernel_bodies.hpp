@@ -22,6 +22,20 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return (b % 8) * (n / 8) + b / 8;
 }
 
+// The same for a one-dimensional grid of nt tiles x L items whose blocks share
+// per-tile input (the coefficient rows of the last-axis pass): the L items of
+// a tile follow each other on one XCD, so the shared rows come from its L2.
+__device__ __forceinline__ void xcd_tile_item(int b, int nt, int L, int& tile, int& item) {
+  if (nt % 8 == 0) {
+    const int s = b / 8;
+    tile = (b % 8) * (nt / 8) + s / L;
+    item = s % L;
+  } else {
+    tile = b / L;
+    item = b % L;
+  }
+}
+
 // SL: layout of the scalar spectra (0: given at run time by the strides,
 // 1: column-major, 2: row-major); fixed at compile time in the specialised
 // kernels, so only one thread mapping is built
@@ -30,6 +44,7 @@ struct ColGen {
   static constexpr int CP = 1;   // components per transform call
   static constexpr int SL = 0;
   static constexpr int WC = 0;   // tile width when known at compile time
+  static constexpr int WPE = 1;  // waves per SIMD the register allocation must allow
   __device__ static int W(int w) { return w; }
   __device__ static int nfft(int n) { return n; }
   __device__ static int ntrial(int n) { return n; }
@@ -51,12 +66,13 @@ struct ColGen {
 // those accesses onto few LDS banks
 __host__ __device__ constexpr int odd_rowlen(int lw) { return (lw > 1 && lw % 2 == 0) ? lw + 1 : lw; }
 
-template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0, bool MF_ = false>
+template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0, bool MF_ = false, int WPE_ = 1>
 struct ColStat {
   static constexpr int NT = NT_;
   static constexpr int CP = 1;
   static constexpr int SL = SL_;
   static constexpr int WC = W_;
+  static constexpr int WPE = WPE_;
   // only the column-major mapping (axis 0 across the threads) needs the pad
   static constexpr int RL = (SL_ == 1) ? odd_rowlen(W_) : W_;
   __device__ static constexpr int W(int) { return W_; }
@@ -82,6 +98,7 @@ struct ColStatCP {
   static constexpr int NT = NT_;
   static constexpr int CP = D_;
   static constexpr int WC = W_;
+  static constexpr int WPE = 1;
   static constexpr int SL = (D_ == 2) ? 1 : 2;   // the layout cells with D_ components use
   static constexpr int RL = (SL == 1) ? odd_rowlen(D_ * W_) : D_ * W_;
   __device__ static constexpr int W(int) { return W_; }
@@ -157,14 +174,14 @@ __device__ __forceinline__ ColXi<T> col_xi(const NormalGeo& g, int col) {
 __device__ __forceinline__ float inv_sqrt(float s) { return rsqrtf(s); }
 __device__ __forceinline__ double inv_sqrt(double s) { return 1.0 / sqrt(s); }
 
+// component comp of n(k) (only the components a pass uses are formed, so a
+// compiler hoisting them out of the component loop keeps few registers live)
 template <class T>
-__device__ __forceinline__ void unit_normal(const NormalGeo& g, int k0, const ColXi<T>& cx, T* nv) {
+__device__ __forceinline__ T normal_comp(const NormalGeo& g, int k0, const ColXi<T>& cx, int comp) {
   const T xi0 = T(k0) * T(g.invY[0]);
   const T s = xi0 * xi0 + cx.c;
   const T inv = s > T(0) ? inv_sqrt(s) : T(0);
-  nv[0] = xi0 * inv;
-  nv[1] = cx.x1 * inv;
-  nv[2] = cx.x2 * inv;
+  return (comp == 0 ? xi0 : comp == 1 ? cx.x1 : cx.x2) * inv;
 }
 
 template <int NT>
@@ -275,7 +292,7 @@ __device__ __forceinline__ bool cg_stops(const ItemScal& q, double s) {
 // X_a = F_0^-1 Pad(n_a c) for every component a
 // ---------------------------------------------------------------------------
 template <class T, class P, int PMAX>
-__global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
+__global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
@@ -378,10 +395,9 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
       int i, w;
       if (pos(it, i, w)) {
         const int row = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
-        T nv[3];
-        unit_normal<T>(a.g, kof(i, n_in),
-                       col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1)), nv);
-        for (int c = 0; c < nc; ++c) lds[row * LW + c * W + w] = cscale(s[it], nv[al0 + c]);
+        const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
+        for (int c = 0; c < nc; ++c)
+          lds[row * LW + c * W + w] = cscale(s[it], normal_comp<T>(a.g, kof(i, n_in), cx, al0 + c));
       }
     }
     __syncthreads();
@@ -406,7 +422,7 @@ __global__ __launch_bounds__(P::NT) void k_col_expand(ColExpandArgs<T> a) {
 // length) or forward with truncation (fft length -> trial), per component
 // ---------------------------------------------------------------------------
 template <class T, class P, int S>
-__global__ __launch_bounds__(P::NT) void k_col_plain(ColPlainArgs<T> a) {
+__global__ __launch_bounds__(P::NT, P::WPE) void k_col_plain(ColPlainArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
@@ -456,7 +472,7 @@ __global__ __launch_bounds__(P::NT) void k_col_plain(ColPlainArgs<T> a) {
 // axis 0 forward + truncation + projection q = n . F_0[X], CG epilogues
 // ---------------------------------------------------------------------------
 template <class T, class P, int PMAX>
-__global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
+__global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
@@ -505,13 +521,12 @@ __global__ __launch_bounds__(P::NT) void k_col_project(ColProjectArgs<T> a) {
       int i, w;
       if (pos(it, i, w)) {
         const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
-        T nv[3];
-        unit_normal<T>(a.g, kof(i, n_out),
-                       col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1)), nv);
+        const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
         for (int c = 0; c < nc; ++c) {
           const cpx<T> v = lds[row * LW + c * W + w];
-          acc[it].x += nv[al0 + c] * v.x;
-          acc[it].y += nv[al0 + c] * v.y;
+          const T nvc = normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
+          acc[it].x += nvc * v.x;
+          acc[it].y += nvc * v.y;
         }
       }
     }
@@ -632,11 +647,14 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
   constexpr int CHL = P::template CH<T>;
-  const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
   const int n = P::n(a.n), H = P::H(a.H), RP = P::RP(a.RP), d = P::D(a.d);
   const int ls = P::ls(a.plan.len);
-  const int pair0 = xcd_tile(blockIdx.x, gridDim.x) * RP;
+  // grid: tiles of RP row pairs x items, flattened
+  const int nt = ((a.rows + 1) / 2 + RP - 1) / RP;
+  int tile, item;
+  xcd_tile_item(blockIdx.x, nt, (int)gridDim.x / nt, tile, item);
+  if (a.sc && !a.sc[item].active) return;
+  const int pair0 = tile * RP;
 
   if (MODE == ROW_APPLY || MODE == ROW_SYNTH) {
     // Z(h) = X_a(h) + i X_b(h), Z(n-h) = conj X_a(h) + i conj X_b(h)

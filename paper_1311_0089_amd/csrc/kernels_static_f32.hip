@@ -83,5 +83,8 @@ RegColCP<T, P255, 255, 8, 3, 384, true> x255_8m;
 RegColCP<T, P253, 127, 4, 3, 192, true> x253_4m;
 RegRow<T, P255, 255, 3, 4, 256, true> r255_3nm;
 RegRow<T, P253, 127, 3, 4, 256, true> r253_3nm;
+// wider workgroups on 16-column tiles: fewer positions per thread
+RegCol<T, P255, 255, 16, 384, false, 3> c255w3;
+RegCol<T, P253, 127, 16, 384> c253w3;
 }  // namespace
 }  // namespace hom

@@ -14,7 +14,7 @@
 
 namespace hom {
 
-template <class T, class SP, int NTRIAL, int W, int NT, bool MF = false>
+template <class T, class SP, int NTRIAL, int W, int NT, bool MF = false, int WPE = 1>
 struct RegCol {
   static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
   // the column-major expand / project tiles use the padded row length
@@ -25,13 +25,13 @@ struct RegCol {
   RegCol() {
     // expand / project per scalar layout: column-major for 2-D cells,
     // row-major for 3-D cells; the plain passes do not touch scalars
-    using P2 = ColStat<SP, NTRIAL, W, NT, 1, MF>;
-    using P3 = ColStat<SP, NTRIAL, W, NT, 2, MF>;
+    using P2 = ColStat<SP, NTRIAL, W, NT, 1, MF, WPE>;
+    using P3 = ColStat<SP, NTRIAL, W, NT, 2, MF, WPE>;
     add(KK_EXPAND, (const void*)&k_col_expand<T, P2, PMAX>, 2, lds);
     add(KK_PROJECT, (const void*)&k_col_project<T, P2, PMAX>, 2, lds);
     add(KK_EXPAND, (const void*)&k_col_expand<T, P3, PMAX>, 3, lds_rm);
     add(KK_PROJECT, (const void*)&k_col_project<T, P3, PMAX>, 3, lds_rm);
-    using P = ColStat<SP, NTRIAL, W, NT, 0, MF>;
+    using P = ColStat<SP, NTRIAL, W, NT, 0, MF, WPE>;
     add(KK_PLAIN_INV, (const void*)&k_col_plain<T, P, +1>, 0, lds_rm);
     add(KK_PLAIN_FWD, (const void*)&k_col_plain<T, P, -1>, 0, lds_rm);
   }
