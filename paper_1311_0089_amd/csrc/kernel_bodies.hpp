@@ -22,18 +22,10 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return (b % 8) * (n / 8) + b / 8;
 }
 
-// The same for a one-dimensional grid of nt tiles x L items whose blocks share
-// per-tile input (the coefficient rows of the last-axis pass): the L items of
-// a tile follow each other on one XCD, so the shared rows come from its L2.
-__device__ __forceinline__ void xcd_tile_item(int b, int nt, int L, int& tile, int& item) {
-  if (nt % 8 == 0) {
-    const int s = b / 8;
-    tile = (b % 8) * (nt / 8) + s / L;
-    item = s % L;
-  } else {
-    tile = b / L;
-    item = b % L;
-  }
+// loads in flight per thread for n elements over NT threads (n known at
+// compile time, else 0: the default cap)
+__host__ __device__ constexpr int rounds_ch(int n, int NT, int cap = 8) {
+  return (n <= 0) ? cap : ((n + NT - 1) / NT < cap ? (n + NT - 1) / NT : cap);
 }
 
 // SL: layout of the scalar spectra (0: given at run time by the strides,
@@ -44,6 +36,7 @@ struct ColGen {
   static constexpr int CP = 1;   // components per transform call
   static constexpr int SL = 0;
   static constexpr int WC = 0;   // tile width when known at compile time
+  static constexpr int NF = 0;   // FFT length when known at compile time
   static constexpr int WPE = 1;  // waves per SIMD the register allocation must allow
   __device__ static int W(int w) { return w; }
   __device__ static int nfft(int n) { return n; }
@@ -72,6 +65,7 @@ struct ColStat {
   static constexpr int CP = 1;
   static constexpr int SL = SL_;
   static constexpr int WC = W_;
+  static constexpr int NF = SP::n;
   static constexpr int WPE = WPE_;
   // only the column-major mapping (axis 0 across the threads) needs the pad
   static constexpr int RL = (SL_ == 1) ? odd_rowlen(W_) : W_;
@@ -98,6 +92,7 @@ struct ColStatCP {
   static constexpr int NT = NT_;
   static constexpr int CP = D_;
   static constexpr int WC = W_;
+  static constexpr int NF = SP::n;
   static constexpr int WPE = 1;
   static constexpr int SL = (D_ == 2) ? 1 : 2;   // the layout cells with D_ components use
   static constexpr int RL = (SL == 1) ? odd_rowlen(D_ * W_) : D_ * W_;
@@ -114,10 +109,11 @@ struct ColStatCP {
 
 struct RowGen {
   static constexpr int NT = kThreads;
-  // loads per thread in flight in the load / store phases (the generic FP64
-  // kernel, already short of registers, keeps one)
+  // loads per thread in flight in the load / store phases for n elements (the
+  // generic FP64 kernel, already short of registers, keeps one)
   template <class T>
-  static constexpr int CH = (sizeof(T) == 8) ? 1 : 8;
+  static constexpr int CH(int) { return (sizeof(T) == 8) ? 1 : 8; }
+  static constexpr int NN = 0, HH = 0, DD = 0, RPP = 0;   // sizes known at compile time
   __device__ static int D(int d) { return d; }
   __device__ static int RP(int rp) { return rp; }
   __device__ static int n(int n_) { return n_; }
@@ -133,7 +129,8 @@ template <class SP, int NTRIAL, int D_, int RP_, int NT_, bool MF_ = false>
 struct RowStat {
   static constexpr int NT = NT_;
   template <class T>
-  static constexpr int CH = 8;
+  static constexpr int CH(int n) { return rounds_ch(n, NT_); }
+  static constexpr int NN = SP::n, HH = (NTRIAL + 1) / 2, DD = D_, RPP = RP_;
   __device__ static constexpr int D(int) { return D_; }
   __device__ static constexpr int RP(int) { return RP_; }
   __device__ static constexpr int n(int) { return SP::n; }
@@ -239,7 +236,8 @@ __device__ __forceinline__ double sum_partials_wave(const double* p, int nparts)
 // issues all of its loads (ld) before the first use (use), so a thread keeps CH
 // memory requests in flight instead of waiting for each in turn.  The loads are
 // unconditional (an index past the end reads element n - 1 again, unused):
-// a load under a branch is waited for inside that branch.
+// a load under a branch is waited for inside that branch.  Callers that know
+// n at compile time pass CH no larger than the rounds n needs (rounds_ch).
 template <int NT, int CH, class Ld, class Use>
 __device__ __forceinline__ void in_rounds(int n, const Ld& ld, const Use& use) {
   using V = decltype(ld(0));
@@ -403,7 +401,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
     __syncthreads();
     P::template fft_rows<T, +1>(lds, a.plan, W, a.tw);
     cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride;
-    in_rounds<NT, 8>(
+    in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
         n_fft * W * nc,
         [=](int f) __attribute__((always_inline)) {
           const int w = f % W, t = f / W, c = t % nc, i = t / nc;
@@ -442,7 +440,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_plain(ColPlainArgs<T> a) 
     for (int f = threadIdx.x; f < n_fft * W; f += NT) lds[f] = cpx<T>{T(0), T(0)};
     __syncthreads();
   }
-  in_rounds<NT, 8>(
+  in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
       n_in * W,
       [=](int f) __attribute__((always_inline)) {
         const int i = f / W, w = f % W;
@@ -455,7 +453,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_plain(ColPlainArgs<T> a) 
       });
   __syncthreads();
   P::template fft<T, S>(lds, a.plan, W, a.tw);
-  in_rounds<NT, 8>(
+  in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
       n_out * W,
       [=](int f) __attribute__((always_inline)) {
         const int i = f / W, w = f % W;
@@ -504,7 +502,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
   for (int al0 = 0; al0 < a.d; al0 += CPN) {
     constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
-    in_rounds<NT, 8>(
+    in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
         n_fft * W * nc,
         [=](int f) __attribute__((always_inline)) {
           const int w = f % W, t = f / W, c = t % nc, i = t / nc;
@@ -646,15 +644,15 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
-  constexpr int CHL = P::template CH<T>;
+  // loads in flight: row loads / stores, flux, real rows
+  constexpr int CHR = P::template CH<T>(P::DD * P::RPP * P::HH);
+  constexpr int CHF = P::template CH<T>(P::RPP * P::NN) > 4 ? 4 : P::template CH<T>(P::RPP * P::NN);
+  constexpr int CHN = P::template CH<T>(P::DD * P::RPP * P::NN);
   const int n = P::n(a.n), H = P::H(a.H), RP = P::RP(a.RP), d = P::D(a.d);
   const int ls = P::ls(a.plan.len);
-  // grid: tiles of RP row pairs x items, flattened
-  const int nt = ((a.rows + 1) / 2 + RP - 1) / RP;
-  int tile, item;
-  xcd_tile_item(blockIdx.x, nt, (int)gridDim.x / nt, tile, item);
+  const int item = blockIdx.y;
   if (a.sc && !a.sc[item].active) return;
-  const int pair0 = tile * RP;
+  const int pair0 = xcd_tile(blockIdx.x, gridDim.x) * RP;
 
   if (MODE == ROW_APPLY || MODE == ROW_SYNTH) {
     // Z(h) = X_a(h) + i X_b(h), Z(n-h) = conj X_a(h) + i conj X_b(h)
@@ -665,7 +663,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
         lds[line * ls + x] = cpx<T>{T(0), T(0)};
       }
     }
-    in_rounds<NT, CHL>(
+    in_rounds<NT, CHR>(
         d * RP * H,
         [=](int f) __attribute__((always_inline)) {
           const int line = f / H, h = f % H;
@@ -693,7 +691,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
     __syncthreads();
     P::template fft<T, +1>(lds, a.plan, d * RP, ls, a.tw);
   } else if (MODE == ROW_FWD) {
-    in_rounds<NT, CHL>(
+    in_rounds<NT, CHN>(
         d * RP * n,
         [=](int f) __attribute__((always_inline)) {
           const int line = f / n, x = f % n;
@@ -729,7 +727,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
 
   if (MODE == ROW_APPLY || MODE == ROW_CONST) {
     const T* A = a.A + (long)(item / a.A_group) * a.A_stride;
-    in_rounds<NT, (CHL + 1) / 2>(
+    in_rounds<NT, CHF>(
         RP * n,
         [=](int f) __attribute__((always_inline)) {
           const int lp = f / n, x = f % n;
@@ -764,7 +762,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   // forward transform and split of the two packed real lines
   P::template fft<T, -1>(lds, a.plan, d * RP, ls, a.tw);
   const T half = T(0.5) / T(n);
-  in_rounds<NT, CHL>(
+  in_rounds<NT, CHR>(
       d * RP * H,
       [=](int f) __attribute__((always_inline)) {
         const int line = f / H, h = f % H;

@@ -519,10 +519,7 @@ template <class T>
 hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipStream_t s,
                       const StaticKernel* sk) {
   const long pairs = (a.rows + 1) / 2;
-  // one-dimensional: tiles x items (the kernel maps the items of a tile to one XCD)
-  const int RP = sk ? sk->W : a.RP;
-  if (RP != a.RP) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(ceil_div(pairs, RP) * items));
+  dim3 grid(ceil_div(pairs, a.RP), items);
   if (sk) {
     const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
                    : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
