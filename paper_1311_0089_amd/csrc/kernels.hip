@@ -379,37 +379,57 @@ hipError_t a_field_range(const double* A, int d, int kind, long npts, double* sc
 // ---------------------------------------------------------------------------
 // FP64 energy quadrature W_lm = <e_l . A e_m>, J_l = <A e_l>
 // ---------------------------------------------------------------------------
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_quad(const double* e, long es, long ecs,
-                                                   const double* A, long Acs, int kind, int d,
+                                                   const double* A, long Acs, int kind,
                                                    long npts, int l0, int nl, int m0, int nm,
                                                    double* partials) {
-  double accW[9], accJ[9];
-  for (int t = 0; t < 9; ++t) accW[t] = accJ[t] = 0.0;
+  // D components and at most 3 x 3 load-case pairs: every loop has a
+  // compile-time bound, so the accumulators stay in registers
+  double acc[18];   // W slots l * 3 + m, then J slots 9 + m * 3 + q
+#pragma unroll
+  for (int t = 0; t < 18; ++t) acc[t] = 0.0;
   for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
        p += (long)gridDim.x * blockDim.x) {
-    double el[3][3], jm[3][3];
-    for (int l = 0; l < nl; ++l)
-      for (int q = 0; q < d; ++q) el[l][q] = e[(l0 + l) * es + q * ecs + p];
-    for (int m = 0; m < nm; ++m) {
-      double em[3];
-      for (int q = 0; q < d; ++q) em[q] = e[(m0 + m) * es + q * ecs + p];
-      flux_point<double>(kind, d, A, Acs, p, em, jm[m]);
-      for (int q = 0; q < d; ++q) accJ[m * 3 + q] += jm[m][q];
-    }
-    for (int l = 0; l < nl; ++l)
-      for (int m = 0; m < nm; ++m) {
-        double s = 0.0;
-        for (int q = 0; q < d; ++q) s += el[l][q] * jm[m][q];
-        accW[l * 3 + m] += s;
+    double c[6];
+    load_coef<double>(kind, D, A, Acs, p, c);
+    double el[3][D];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int q = 0; q < D; ++q) el[l][q] = (l < nl) ? e[(l0 + l) * es + q * ecs + p] : 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if (m >= nm) break;
+      double em[D], jm[3];
+#pragma unroll
+      for (int q = 0; q < D; ++q) em[q] = e[(m0 + m) * es + q * ecs + p];
+      flux_coef<double>(kind, D, c, em, jm);
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc[9 + m * 3 + q] += jm[q];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) sum += el[l][q] * jm[q];
+        acc[l * 3 + m] += sum;
       }
+    }
   }
-  for (int t = 0; t < 9; ++t) {
-    const double v = block_sum<kThreads>(accW[t]);
-    if (threadIdx.x == 0) partials[(long)blockIdx.x * 18 + t] = v;
+  // per wave, then across the waves in order (one barrier)
+  __shared__ double red[kThreads / 64][18];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 18; ++t) {
+    double v = acc[t];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[wid][t] = v;
   }
-  for (int t = 0; t < 9; ++t) {
-    const double v = block_sum<kThreads>(accJ[t]);
-    if (threadIdx.x == 0) partials[(long)blockIdx.x * 18 + 9 + t] = v;
+  __syncthreads();
+  if (threadIdx.x < 18) {
+    double v = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
+    partials[(long)blockIdx.x * 18 + threadIdx.x] = v;
   }
 }
 
@@ -592,8 +612,16 @@ hipError_t launch_set_scal(ItemScal* sc, int items, double tol, int max_iter, in
 hipError_t launch_quad(const double* e, long e_stride, long e_cstride, const double* A,
                        long A_cstride, int kind, int d, long npts, int l0, int nl, int m0, int nm,
                        double* partials, int blocks, hipStream_t s) {
-  launch_k(k_quad, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
-                     A_cstride, kind, d, npts, l0, nl, m0, nm, partials);
+  if (nl < 1 || nl > 3 || nm < 1 || nm > 3) return hipErrorInvalidValue;
+  switch (d) {
+    case 1: launch_k(k_quad<1>, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
+                     A_cstride, kind, npts, l0, nl, m0, nm, partials); break;
+    case 2: launch_k(k_quad<2>, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
+                     A_cstride, kind, npts, l0, nl, m0, nm, partials); break;
+    case 3: launch_k(k_quad<3>, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
+                     A_cstride, kind, npts, l0, nl, m0, nm, partials); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t launch_quad_final(const double* partials, int blocks, int nl, int nm, int d, long npts,
