@@ -86,5 +86,10 @@ RegRow<T, P253, 127, 3, 4, 256, true> r253_3nm;
 // wider workgroups on 16-column tiles: fewer positions per thread
 RegCol<T, P255, 255, 16, 384, false, 3> c255w3;
 RegCol<T, P253, 127, 16, 384> c253w3;
+// 1023-point tiles with more waves per workgroup (fewer rounds per stage)
+RegColCP<T, P1023, 1023, 2, 2, 384, true> x1023_2m3;
+RegColCP<T, P1023, 1023, 1, 2, 192, true> x1023_1m3;
+RegRow<T, P1023, 1023, 2, 1, 192, true> r1023_2nm3;
+RegRow<T, P1023, 1023, 2, 1, 256, true> r1023_2nm4;
 }  // namespace
 }  // namespace hom
