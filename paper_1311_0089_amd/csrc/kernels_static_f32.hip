@@ -91,5 +91,8 @@ RegColCP<T, P1023, 1023, 2, 2, 384, true> x1023_2m3;
 RegColCP<T, P1023, 1023, 1, 2, 192, true> x1023_1m3;
 RegRow<T, P1023, 1023, 2, 1, 192, true> r1023_2nm3;
 RegRow<T, P1023, 1023, 2, 1, 256, true> r1023_2nm4;
+RegColCP<T, P1023, 1023, 2, 2, 320, true> x1023_2m5;
+RegRow<T, P1023, 1023, 2, 1, 320, true> r1023_2nm5;
+RegRow<T, P1023, 1023, 2, 1, 384, true> r1023_2nm6;
 }  // namespace
 }  // namespace hom
