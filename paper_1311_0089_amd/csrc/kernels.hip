@@ -128,6 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   }
   const T alpha = T(alpha64);
   double part = 0.0;
+  const bool small = a.count < (1L << 31);
   while (e0 < a.count) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
@@ -141,7 +142,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
         rv[u].x -= alpha * qv[u].x;
         rv[u].y -= alpha * qv[u].y;
         a.r[base + e] = rv[u];
-        const double wt = (((e / a.n0) % a.H) == 0) ? 1.0 : 2.0;
+        // Hermitian weight; 32-bit division where the indices fit (a 64-bit
+        // one costs ~100 instructions per element)
+        const int hcol = small ? ((int)e / a.n0) % a.H : (int)((e / a.n0) % a.H);
+        const double wt = (hcol == 0) ? 1.0 : 2.0;
         part += wt * ((double)rv[u].x * (double)rv[u].x + (double)rv[u].y * (double)rv[u].y);
       }
     }
