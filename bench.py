@@ -1,26 +1,31 @@
 """Benchmark: cell solves of the FFT-Galerkin cell problem on one MI355X.
 
-Default workload: 2-D random two-phase pixel microstructure, N = 1023 x 1023
-(Bernoulli(0.4) pixels smoothed by 3 majority passes, conductivities 100 / 1,
-seed 2), load cases E = e1, e2 solved together, tol 1e-6, FP32-FFT inner CG
-with FP64 refinement.  One step = create the cell (validate + upload A) and
-solve both load cases to A_H; A is resident in HBM before the timed region.
+Default workload (the largest single-GPU configuration): 3-D spheres, N = 255^3,
+60 random non-overlapping spheres of radius 0.06 (seed 3), conductivity 1e3 in
+the spheres and 1 outside, load cases E = e1, e2, e3 solved together as three
+right-hand sides, tol 1e-6, FP32-FFT CG with FP64 residual replacement.  One
+step = create the cell from the device-resident coefficient field (validate,
+FP32 copy) and solve the three load cases to A_H; A is in HBM before the timed
+region.
 
 Printed (one JSON line): voxel-iters/s as `value` (|N| x load cases x CG
 iterations / s), operator applies/s, cell solves/s with p50/p99 step latency,
 A_H error of the mixed path against the FP64 GPU path at tol 1e-10 (itself
 parity-tested against the FP64 oracle), the FP64 path's own solve time at the
-same tolerance, the roofline of the dominant kernel (HIP events around each
-kernel of the CG iteration, algorithmic bytes) and the FP64 CPU oracle timed
-on a bounded sample on this host.  --extra adds the 3-D workloads (spheres
-255^3, lognormal Ga 127^3 on 253^3); --serving N adds N requests of the
-Poisson request stream through the continuous-batching server.
+same tolerance, the roofline of the dominant pass (HIP events recorded by the
+dispatch of each kernel of a CG iteration; bytes from the per-pass model:
+each pass reads and writes the d component fields of its grid once, the flux
+pass also reads A once), and the FP64 CPU oracle timed on a bounded sample on
+this host.  --workload picks another configuration; --extra adds the other
+3-D workload; --serving N adds N requests of the Poisson request stream
+through the continuous-batching server.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import statistics
 import sys
 import threading
@@ -34,6 +39,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("operator applies/s & voxel-iters/s; cell solves/s with p50/p99 at A_H rel err 1e-6")
 HBM_PEAK_GBS = 8000.0
 PREC_NAME = {0: "fp64", 1: "mixed"}
+PASSES = ["expand0", "inv1", "row", "fwd1", "project0"]
 
 
 def parse():
@@ -41,7 +47,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1023, help="grid size per axis (odd)")
+    ap.add_argument("--workload", choices=["spheres", "lognormal", "pixels", "square"],
+                    default="spheres")
+    ap.add_argument("--n", type=int, default=None, help="grid size per axis (odd), pixels only")
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ref", action="store_true", help="skip the FP64 reference solves")
@@ -50,7 +58,7 @@ def parse():
                     help="kernel variants: committed tuning cache (tune if absent), "
                          "re-tune now, or first registered variant")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
-    ap.add_argument("--extra", action="store_true", help="also measure the 3-D workloads")
+    ap.add_argument("--extra", action="store_true", help="also measure the other workloads")
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving stream")
     ap.add_argument("--serving-rate", type=float, default=500.0)
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -67,14 +75,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def make_workload(name, n=None):
+    import hom_inputs as hi
+    if name == "spheres":
+        return hi.cfg3_spheres()
+    if name == "lognormal":
+        return hi.cfg4_lognormal()
+    if name == "pixels":
+        n = n or 1023
+        return hi.cfg2_pixels((n, n), seed=2)
+    return hi.cfg1_square()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle (naive DFT, OpenMP) timed on this host: operator
     applies (one CG iteration each) on the same cell, as many as fit in about
-    budget_s, scaled to voxel-iters/s."""
+    budget_s (at least one), scaled to voxel-iters/s."""
     from oracle import oracle
-    c = oracle.Cell(w.A, w.N)
+    c = oracle.Cell(w.A, w.N, kind=w.kind, scheme=w.scheme)
     d = len(w.N)
-    u = c.apply_G(np.stack([w.A / w.A.max()] * d))
+    u = np.stack([np.full(w.N, 1.0 if a == 0 else 0.0) for a in range(d)])
+    u[0] += np.cos(2 * np.pi * np.arange(w.N[0]) / w.N[0]).reshape((w.N[0],) + (1,) * (d - 1))
     n_apply = 0
     t0 = time.perf_counter()
     while True:
@@ -87,9 +118,10 @@ def cpu_baseline(w, budget_s: float):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     shape = "x".join(str(n) for n in w.N)
     return {"value": npts * n_apply / dt, "unit": "voxel-iters/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n_apply} FP64 operator applies (G A, naive DFT) on the {shape} cell, "
-                      f"one load case, {dt:.1f} s"}
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{n_apply} FP64 operator apply(s) of the oracle (G A, naive DFT) on the "
+                      f"{shape} cell of this workload, one load case, {dt:.1f} s; "
+                      f"voxel-iters/s = grid points x applies / s"}
 
 
 def tune(hom, w, prec, L, mode, out_path):
@@ -106,6 +138,30 @@ def tune(hom, w, prec, L, mode, out_path):
     os.makedirs(os.path.dirname(out_path), exist_ok=True)
     hom.tune_save(out_path)
     return "run"
+
+
+def pass_model_bytes(w, L, real_bytes):
+    """Model HBM bytes of each pass of one batched operator apply: every pass
+    reads and writes the d component fields of its grid once (the half
+    spectrum of a real field counted as one real per grid point) and the flux
+    pass also reads A once.  GaNi: 2 d |N| s per pass and load case; Ga (the
+    pruned pad / truncate passes): the trial / quadrature sizes of each pass."""
+    d = len(w.N)
+    N = list(w.N)
+    Q = [2 * n - 1 for n in N] if w.scheme == 1 else N
+    nA = 1 if w.kind == 0 else (d if w.kind == 1 else d * (d + 1) // 2)
+    s = real_bytes
+    if d == 2:
+        ex = N[0] * N[1] + Q[0] * N[1]
+        row = 2 * Q[0] * N[1]
+        return {"expand0": d * L * s * ex, "row": d * L * s * row + nA * Q[0] * Q[1] * s,
+                "project0": d * L * s * ex}
+    ex = N[0] * N[1] * N[2] + Q[0] * N[1] * N[2]
+    ax1 = Q[0] * N[1] * N[2] + Q[0] * Q[1] * N[2]
+    row = 2 * Q[0] * Q[1] * N[2]
+    return {"expand0": d * L * s * ex, "inv1": d * L * s * ax1,
+            "row": d * L * s * row + nA * Q[0] * Q[1] * Q[2] * s,
+            "fwd1": d * L * s * ax1, "project0": d * L * s * ex}
 
 
 def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
@@ -137,6 +193,7 @@ def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    log(f"{w.name}: {steps} timed steps, {dt * 1e3:.2f} ms/step")
     it_in, it_out = r["info"]["iters_inner"], r["info"]["iters_outer"]
     W = r["W"]
     npts = int(np.prod(w.N))
@@ -147,7 +204,7 @@ def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
            "latency_ms": {"p50": statistics.median(lat) * 1e3,
                           "p99": float(np.percentile(np.array(lat) * 1e3, 99))},
            "A_H": W.tolist(), "rel_resid_true": r["info"]["rel_resid_true"],
-           "status": r["status"]}
+           "rho_A": r["info"]["rho_A"], "status": r["status"]}
     if ref:
         # the FP64 path: at the same tolerance (timed) and at 1e-10 (the A_H reference)
         c64 = hom.Cell(A_dev, w.N, kind=w.kind, scheme=w.scheme, prec=hom.FP64)
@@ -156,20 +213,37 @@ def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
         r64 = c64.solve(w.E, tol=w.tol)
         out["fp64_same_tol_ms"] = (time.perf_counter() - t1) * 1e3
         out["fp64_same_tol_iters"] = r64["info"]["iters_inner"]
-        out["fp64_same_tol_A_H_rel_err"] = float(np.abs(r64["W"] - W).max() / np.abs(W).max())
         rr = c64.solve(w.E, tol=1e-10)
         c64.close()
-        out["A_H_rel_err_vs_fp64_1e-10"] = float(np.abs(W - rr["W"]).max() / np.abs(rr["W"]).max())
-        out["fp64_same_tol_A_H_rel_err"] = float(np.abs(r64["W"] - rr["W"]).max()
-                                                 / np.abs(rr["W"]).max())
+        ref_W = rr["W"]
+        out["A_H_rel_err_vs_fp64_1e-10"] = float(np.abs(W - ref_W).max() / np.abs(ref_W).max())
+        out["fp64_same_tol_A_H_rel_err_vs_fp64_1e-10"] = float(
+            np.abs(r64["W"] - ref_W).max() / np.abs(ref_W).max())
+        log(f"{w.name}: FP64 same tol {out['fp64_same_tol_ms']:.1f} ms; A_H err mixed "
+            f"{out['A_H_rel_err_vs_fp64_1e-10']:.2e}, fp64 "
+            f"{out['fp64_same_tol_A_H_rel_err_vs_fp64_1e-10']:.2e}")
     cell = hom.Cell(A_dev, w.N, kind=w.kind, scheme=w.scheme, prec=prec)
     prof = cell.profile(prec=prec, L=L, reps=20)
     cell.close()
-    kernels = {k: v for k, v in prof.items() if k not in ("iteration", "scalars") and v["ms"] > 0}
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    achieved = kernels[dom]["bytes"] / (kernels[dom]["ms"] * 1e-3) / 1e9
+    real_bytes = 4 if prec == hom.MIXED else 8
+    model = pass_model_bytes(w, L, real_bytes)
+    passes = {k: prof[k] for k in PASSES if prof[k]["ms"] > 0}
+    dom = max(passes, key=lambda k: passes[k]["ms"])
+    achieved = model[dom] / (passes[dom]["ms"] * 1e-3) / 1e9
+    op_ms = sum(v["ms"] for v in passes.values())
+    op_model = sum(model[k] for k in passes)
     out["iteration_profile_us"] = {k: round(v["ms"] * 1e3, 2) for k, v in prof.items()}
-    out["iteration_GBps"] = prof["iteration"]["bytes"] / (prof["iteration"]["ms"] * 1e-3) / 1e9
+    out["pass_model_GBps"] = {k: round(model[k] / (passes[k]["ms"] * 1e-3) / 1e9, 1)
+                              for k in passes}
+    out["operator"] = {"model_bytes": op_model, "us": op_ms * 1e3,
+                       "GBps": op_model / (op_ms * 1e-3) / 1e9,
+                       "frac": op_model / (op_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    # the CG vectors the passes stream besides the model (fused CG steps in
+    # the expansion and projection, the update kernel), reported on their own
+    cg_bytes = sum(prof[k]["bytes"] for k in PASSES if prof[k]["ms"] > 0) - op_model
+    cg_bytes += prof["update"]["bytes"]
+    out["cg_vectors"] = {"bytes_per_iteration": cg_bytes,
+                         "update_us": prof["update"]["ms"] * 1e3}
     # measured HBM bytes per launch of the dominant kernel, from the committed
     # counter summary of this workload while the kernel sources are unchanged
     from paper_1311_0089_amd import traffic
@@ -177,9 +251,11 @@ def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
     tr = rec["slots"].get(dom, {}).get("bytes") if rec else None
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                       "algorithmic_bytes": kernels[dom]["bytes"]}
+                       "model_bytes": model[dom], "kernel_us": passes[dom]["ms"] * 1e3,
+                       "bytes_incl_cg_vectors": prof[dom]["bytes"]}
     log(f"{w.name}: {dt * 1e3:.2f} ms/step, iters {it_in}/{it_out}, profile " +
-        ", ".join(f"{k} {v['ms'] * 1e3:.1f}us" for k, v in prof.items()))
+        ", ".join(f"{k} {v['ms'] * 1e3:.1f}us" for k, v in prof.items()) +
+        f"; operator {out['operator']['GBps']:.0f} GB/s model")
     return out
 
 
@@ -228,6 +304,8 @@ def serving(hom, n_req, rate, budget):
         fields[i] = None
         cells[i] = c
         tickets[i] = (srv.submit(c, r.E, tol=r.tol), r.E.shape[0], r.d)
+        if (i + 1) % 1000 == 0:
+            log(f"serving: {i + 1} submitted, {len(done)} done")
     th.join(timeout=600)
     t_end = time.perf_counter() - t0
     srv.close()
@@ -241,15 +319,24 @@ def serving(hom, n_req, rate, budget):
             "budget_bytes": budget}
 
 
+def config_of(w, args):
+    d = len(w.N)
+    return {"workload": w.name, "N": list(w.N), "load_cases": int(w.E.shape[0]),
+            "tol": w.tol, "contrast": w.info.get("contrast"),
+            "volume_fraction": round(w.info["vf"], 4) if "vf" in w.info else None,
+            "scheme": "Ga" if w.scheme == 1 else "GaNi",
+            "quadrature_grid": [2 * n - 1 for n in w.N] if w.scheme == 1 else list(w.N),
+            "dimension": d, "precision": args.prec}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
-                                   "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU; sharding over several GPUs "
+                                   "is a design only", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
-    import hom_inputs as hi
     import paper_1311_0089_amd as hom
 
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -262,10 +349,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written per launch")
         del a, b
-    n = args.n
-    w = hi.cfg2_pixels((n, n), seed=2)
+    w = make_workload(args.workload, args.n)
     prec = hom.MIXED if args.prec == "mixed" else hom.FP64
-    log(f"workload {w.name} vf={w.info['vf']:.3f} prec={args.prec} tol={w.tol}")
+    log(f"workload {w.name} info={w.info} prec={args.prec} tol={w.tol}")
     tuned = tune(hom, w, prec, w.E.shape[0], args.tune, args.tune_out)
     m = measure(hom, w, prec, args.steps, args.warmup, ref=not args.no_ref,
                 inner_tol=args.inner_tol)
@@ -282,35 +368,41 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if prec == hom.MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": [n, n], "load_cases": int(w.E.shape[0]),
-                   "tol": w.tol, "contrast": 100.0, "volume_fraction": round(w.info["vf"], 4),
-                   "scheme": "GaNi", "precision": args.prec},
+        "config": config_of(w, args),
         "operator_applies_per_s": m["operator_applies_per_s"],
         "cell_solves_per_s": m["cell_solves_per_s"],
         "latency_ms": m["latency_ms"],
         "cg_iterations": {"inner": m["iters_inner"], "outer": m["iters_outer"]},
+        "rho_A": m["rho_A"],
         "A_H": m["A_H"],
         "A_H_rel_err_vs_fp64": m.get("A_H_rel_err_vs_fp64_1e-10"),
         "fp64_path": {k: m[k] for k in m if k.startswith("fp64_")},
         "iteration_profile_us": m["iteration_profile_us"],
-        "iteration_GBps": m["iteration_GBps"],
+        "pass_model_GBps": m["pass_model_GBps"],
+        "operator": m["operator"],
+        "cg_vectors": m["cg_vectors"],
         "kernel_tuning": tuned,
         "roofline": m["roofline"],
     }
     if args.extra:
         extra = {}
-        for make in (hi.cfg3_spheres, hi.cfg4_lognormal):
-            wx = make()
+        others = {"spheres": ["lognormal", "pixels"], "lognormal": ["spheres", "pixels"],
+                  "pixels": ["spheres", "lognormal"], "square": []}[args.workload]
+        for name in others:
+            wx = make_workload(name)
             t = tune(hom, wx, hom.MIXED, wx.E.shape[0], args.tune, args.tune_out)
             mx = measure(hom, wx, hom.MIXED, max(2, args.steps // 3), 1, ref=not args.no_ref,
                          inner_tol=args.inner_tol)
             mx["kernel_tuning"] = t
-            mx["contrast"] = wx.info.get("contrast")
+            mx["config"] = config_of(wx, args)
+            if name == "pixels":
+                mx["note"] = "working set (~60 MB FP32) fits the 256 MB Infinity Cache"
             extra[wx.name] = mx
         out["extra_workloads"] = extra
     if args.serving:
         out["serving"] = serving(hom, args.serving, args.serving_rate, budget=64 << 30)
     if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -97,7 +97,11 @@ hom_status hom_options_default(hom_options* opt);
  *           pointer when A_on_device != 0.  Copied; the caller may free it on return.
  *  opt      options (NULL for defaults); scheme and Y are fixed for the cell
  * Validates A (finite, symmetric positive definite at every point, A2) and
- * records its contrast.  Errors: HOM_EINVAL, HOM_ENOTSPD, HOM_ENOMEM, HOM_EDEVICE. */
+ * records its contrast.  Errors: HOM_EINVAL, HOM_ENOTSPD, HOM_ENOMEM, HOM_EDEVICE.
+ * HOM_EINVAL also for a cell whose last-axis transform (of the quadrature grid,
+ * or for Ga of the trial grid) has a prime factor above 31 and no compile-time
+ * specialised FP64 kernel: the generic FP64 kernel for such lengths is not run
+ * (specialised: 127, and for Ga 61 with trial 31 and 509 with trial 255). */
 hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const double* A,
                            int A_on_device, const hom_options* opt, hom_cell** out);
 

@@ -363,6 +363,12 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
     a.RP = sk->W;
     return launch_row<T>(a, items, mode, sk->lds, c->stream, sk);
   }
+  // The generic FP64 last-axis kernel with a chirp-z (Bluestein) plan faulted
+  // the GPU once in its flux / right-hand-side / synthesis modes (255 rows of
+  // length 127, 4 row pairs per workgroup) and the cause is not known: those
+  // modes are not run.  Lengths with a specialised FP64 kernel are served by
+  // it; other such shapes are rejected when the cell is created.
+  if (sizeof(T) == 8 && pl->p.blue && mode != ROW_FWD) return hipErrorNotSupported;
   size_t lds = 0;
   int RP = 0;
   if ((e = row_shape(pl->p, c->dd, rows, sizeof(cpx<T>), &RP, &lds)) != hipSuccess) return e;
@@ -959,10 +965,30 @@ hom_status hom_options_default(hom_options* o) {
 static hom_status dev_status(hipError_t e) {
   if (e == hipSuccess) return HOM_OK;
   if (e == hipErrorOutOfMemory) return HOM_ENOMEM;
+  if (e == hipErrorNotSupported) return HOM_EINVAL;   // a shape no kernel serves
   return HOM_EDEVICE;
 }
 
 // eigenvalue range of the coefficient at one point; false if not SPD or not finite
+
+// false if a last-axis pass of the cell would need the generic FP64 kernel
+// with a chirp-z plan, which stage_row refuses: the flux, right-hand-side
+// and synthesis passes on the quadrature grid, and (Ga) the synthesis of the
+// strain on the trial grid
+static bool fp64_rows_served(const CellImpl* c) {
+  const int Nl = c->N[c->dd - 1];
+  const int lens[2] = {c->Q[c->dd - 1], Nl};
+  for (int i = 0; i < 2; ++i) {
+    const DevPlan* pl = nullptr;
+    if (get_dev_plan(lens[i], &pl) != hipSuccess) return false;
+    if (!pl->p.blue) continue;
+    for (int k : {KK_ROW, KK_ROW_CONST, KK_ROW_SYNTH}) {
+      if (i == 1 && k != KK_ROW_SYNTH) continue;
+      if (!find_static(k, (int)sizeof(cpx<double>), lens[i], Nl, c->dd, pl->p)) return false;
+    }
+  }
+  return true;
+}
 
 // order the cell stream after work already queued on the caller's stream
 static void wait_user_stream(CellImpl* c) {
@@ -1036,6 +1062,10 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
       delete c;
       return dev_status(e);
     }
+  }
+  if (!fp64_rows_served(c)) {
+    pool_put(c);
+    return HOM_EINVAL;
   }
   c->d = d;
   c->opt = o;

@@ -117,8 +117,24 @@ def test_specialised_operator_matches_oracle(hom, oracle, torch_cuda, N, kind, s
     """Operator parity through the specialised kernels, and agreement of the
     specialised and generic kernels on the same input."""
     a = _apply_case(hom, oracle, torch_cuda, N, kind, scheme, True)
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    if _chirp_length(Q[-1]):
+        # the generic FP64 last-axis kernel of a chirp-z length is not run:
+        # such a cell is rejected when only the generic kernels are enabled
+        with pytest.raises(hom.HomError) as ei:
+            _apply_case(hom, oracle, torch_cuda, N, kind, scheme, False)
+        assert ei.value.code == -1
+        return
     b = _apply_case(hom, oracle, torch_cuda, N, kind, scheme, False)
     assert rel(a, b) < 1e-13
+
+
+def _chirp_length(n):
+    """True if n has a prime factor above 31 (transformed by chirp-z)."""
+    for r in (31, 29, 23, 19, 17, 13, 11, 7, 5, 3, 2):
+        while n % r == 0:
+            n //= r
+    return n != 1
 
 
 # shapes whose passes have several compile-time variants: column tiles of
@@ -310,3 +326,15 @@ def test_invalid_coefficient_rejected(hom, torch_cuda):
     with pytest.raises(hom.HomError) as ei:
         hom.Cell(A, N)
     assert ei.value.code == -1
+
+
+@gpu
+def test_generic_fp64_chirp_rows_rejected(hom, torch_cuda):
+    """A last axis of prime length above 31 with no specialised FP64 kernel
+    (37) is rejected when the cell is created, in both precisions (the mixed
+    path evaluates FP64 residuals); 127 has one and is accepted."""
+    for prec in (hom.FP64, hom.MIXED):
+        with pytest.raises(hom.HomError) as ei:
+            hom.Cell(np.ones((9, 37)), (9, 37), prec=prec)
+        assert ei.value.code == -1
+    hom.Cell(np.ones((9, 127)), (9, 127)).close()
