@@ -354,9 +354,12 @@ static int op_LSD(const hor_cell* c, const void* ctx, const double* u, double* o
     return s;
 }
 
-/* Hestenes-Stiefel CG for M x = b from x (as given) */
+/* Hestenes-Stiefel CG for M x = b from x (as given).  The stopping test is
+ * ||r_i|| <= tol ||r_ref|| with ref2 = (r_ref, r_ref); ref2 <= 0 takes the
+ * initial residual r_0 (for x0 = 0 the two agree, since r_0 = b). */
 static int cg_core(const hor_cell* c, op_fn M, const void* ctx, const double* b, double tol,
-                   int max_iter, double* x, int* iters, double* relres, double* hist) {
+                   int max_iter, double ref2, double* x, int* iters, double* relres,
+                   double* hist) {
     long np = prod(c->d, c->N);
     long n = (long)c->d * np;
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
@@ -366,10 +369,11 @@ static int cg_core(const hor_cell* c, op_fn M, const void* ctx, const double* b,
     int s = M(c, ctx, x, q);
     for (long i = 0; i < n && !s; ++i) r[i] = b[i] - q[i];
     double rho = s ? 0.0 : gdot(n, np, r, r);
-    double rho0 = rho, bb = gdot(n, np, b, b);
+    double bb = gdot(n, np, b, b);
+    double rho0 = (ref2 > 0.0) ? ref2 : rho;
     int it = 0;
-    if (hist && !s) hist[0] = 1.0;
-    if (!s && rho0 > 0.0) {
+    if (hist && !s) hist[0] = (rho0 > 0.0) ? sqrt(rho / rho0) : 0.0;
+    if (!s && rho > 0.0 && sqrt(rho / rho0) > tol) {
         memcpy(p, r, sizeof(double) * (size_t)n);
         for (it = 0; it < max_iter;) {
             s = M(c, ctx, p, q);
@@ -430,7 +434,10 @@ int hor_cg(const hor_cell* c, const double* E, double tol, int max_iter,
         if (!t) s = HOR_ENOMEM;
         else { s = hor_apply_G(c, x, t); memcpy(x, t, sizeof(double) * (size_t)n); free(t); }
     }
-    if (!s) s = cg_core(c, op_GA, NULL, b, tol, max_iter, x, iters, relres, hist);
+    /* the stopping test is relative to ||b||, the initial residual of a cold
+       start, so a warm start aims at the residual a cold solve reaches */
+    double bb = gdot(n, np, b, b);
+    if (!s) s = cg_core(c, op_GA, NULL, b, tol, max_iter, bb, x, iters, relres, hist);
     free(Ef); free(b);
     return s;
 }
@@ -443,7 +450,7 @@ int hor_cg_lsd(const hor_cell* c, const double* E, double lambda, double tol,
     double* Ef = const_field(d, np, E);
     if (!Ef) return HOR_ENOMEM;
     memcpy(e, Ef, sizeof(double) * (size_t)d * (size_t)np);   /* e0 = E */
-    int s = cg_core(c, op_LSD, &lambda, Ef, tol, max_iter, e, iters, NULL, NULL);
+    int s = cg_core(c, op_LSD, &lambda, Ef, tol, max_iter, 0.0, e, iters, NULL, NULL);
     free(Ef);
     return s;
 }

@@ -64,10 +64,11 @@ int hor_apply_G(const hor_cell* c, const double* u, double* out);
 int hor_apply_GA(const hor_cell* c, const double* u, double* out);
 
 /* Conjugate gradients on G A x = -G A E for one load case E[d] with x0 = 0
- * (or x0 = x on entry when warm != 0).  Stops when ||r_i|| / ||r_0|| <= tol.
- * iters/relres receive the iteration count and the final true relative
- * residual ||b - GA x|| / ||b||.  hist (nullable, max_iter+1 entries) receives
- * ||r_i|| / ||r_0||. */
+ * (or x0 = G x, the E_N part of x on entry, when warm != 0).  Stops when
+ * ||r_i|| / ||b|| <= tol (for x0 = 0, r_0 = b; a warm start that already
+ * meets the test returns after 0 iterations).  iters/relres receive the
+ * iteration count and the final true relative residual ||b - GA x|| / ||b||.
+ * hist (nullable, max_iter+1 entries) receives ||r_i|| / ||b||. */
 int hor_cg(const hor_cell* c, const double* E, double tol, int max_iter,
            int warm, double* x, int* iters, double* relres, double* hist);
 

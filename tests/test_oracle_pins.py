@@ -287,6 +287,40 @@ def test_dense_realspace(oracle, N, kind, scheme):
         np.testing.assert_allclose(G @ K @ G, (G @ K @ G).T, atol=1e-12 * np.abs(K).max())
 
 
+# --------------------------------------------- warm start (Sec. 5.3, CG Lemma)
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_warm_start(oracle, scheme):
+    """CG keeps its iterates in E_N and the discrete solution is unique
+    (Sec. 5.2-5.3), so a warm start enters through its E_N part.  The stopping
+    test is relative to ||b|| (the cold start's initial residual).  (i) From
+    the solution of the dense Fourier-Galerkin system (no CG) the test holds at
+    once: 0 iterations, the same field.  (ii) From a gradient field plus
+    constants and a divergence-free field (both outside E_N) CG ends at that
+    same solution: the part outside E_N is projected away."""
+    N = (7, 5)
+    d, kind = 2, 2
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    A = hi.random_spd_field(Q, kind, seed=73, contrast=20.0)
+    c = oracle.Cell(A, N, kind=kind, scheme=scheme)
+    E = np.array([1.0, -0.4])
+    xr = fourier_galerkin_dense(A, kind, N, scheme, E[None])[0][0]
+    scale = np.abs(xr).max()
+    x, it, rr = c.cg(E, tol=1e-10, x0=xr)
+    assert it == 0
+    np.testing.assert_allclose(x, xr, atol=1e-13 * scale)
+    ks = np.meshgrid(*[hi.signed_index(n) for n in N], indexing="ij")
+    xi = [2.0 * k for k in ks]   # xi = k / Y with Y = 1/2
+    phi = np.fft.fftn(rand_field(N, 74))
+    psi = np.fft.fftn(rand_field(N, 75))
+    grad = np.stack([np.fft.ifftn(1j * xi[a] * phi).real for a in range(d)])
+    rot = np.stack([np.fft.ifftn(-1j * xi[1] * psi).real, np.fft.ifftn(1j * xi[0] * psi).real])
+    x0 = grad + rot + np.array([0.7, -1.3])[:, None, None]
+    np.testing.assert_allclose(c.apply_G(rot), 0.0, atol=1e-12 * np.abs(rot).max())
+    x, it, rr = c.cg(E, tol=1e-13, x0=x0)
+    assert it > 0
+    np.testing.assert_allclose(x, xr, atol=1e-10 * scale)
+
+
 # ------------------------------------------------------- T6: A_H structure
 @pytest.mark.parametrize("N,kind,scheme", [((9, 7), 0, 0), ((7, 7), 2, 0), ((5, 5, 5), 1, 0),
                                            ((5, 7), 2, 1), ((3, 5, 3), 0, 1)])
