@@ -51,7 +51,8 @@ typedef enum {
   HOM_ENOTCONV = -4,    /* max_iter reached; the best iterate and info are still returned */
   HOM_EBREAKDOWN = -5,  /* CG breakdown ((p, q) <= 0 or not finite) */
   HOM_EDEVICE = -6,     /* HIP runtime error */
-  HOM_EBUSY = -7        /* server: request not finished yet */
+  HOM_EBUSY = -7,       /* server: request not finished yet */
+  HOM_ESCRATCH = -8     /* hom_apply_noalloc: workspace above HOM_NOALLOC_SCRATCH_BYTES */
 } hom_status;
 
 typedef enum { HOM_A_ISO = 0, HOM_A_DIAG = 1, HOM_A_FULLSYM = 2 } hom_a_kind;
@@ -128,6 +129,24 @@ hom_status hom_apply(hom_cell* c, hom_prec prec, int L, const double* u, double*
 
 /* Projection onto E_N: out = G_N u, device pointers [L][d][N grid] FP64. */
 hom_status hom_project(hom_cell* c, int L, const double* u, double* out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hom_apply
+ * (same arguments, same kernels, same result) with its whole workspace taken
+ * from a fixed array of HOM_NOALLOC_SCRATCH_BYTES of device memory inside the
+ * library, one per GPU, held until the process ends.  Calls no allocation
+ * routine (the cell, created beforehand, holds its coefficient and plans).
+ * Workspace (each part rounded up to 256 bytes): 16 (2 S + 2 d Xe) L bytes,
+ * + 16 S L for HOM_MIXED, + 24 L, with S = N_0 .. N_{d-2} (N_last + 1)/2 and
+ * Xe = Q_0 .. Q_{d-2} (N_last + 1)/2 complex elements per load case; above
+ * the limit it returns HOM_ESCRATCH and does nothing.  The work is queued on
+ * the stream given in the cell's options (the cell's own stream if none) and
+ * not waited for: out is complete once that stream reaches it.  Every call on
+ * a GPU shares that GPU's array, so calls that overlap on one GPU (on
+ * different streams or from different threads) race.  Errors: HOM_EINVAL,
+ * HOM_ESCRATCH, HOM_EDEVICE. */
+#define HOM_NOALLOC_SCRATCH_BYTES (128u << 20)
+hom_status hom_apply_noalloc(hom_cell* c, hom_prec prec, int L, const double* u, double* out);
 
 /* Time the kernels of reps consecutive CG iterations on L load cases (HIP
  * events recorded by each dispatch, on the cell's stream).  ms[0..7]

@@ -122,7 +122,8 @@ int project_tiles(CellImpl* c);
 template <class T>
 hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out);
 // scalar potential of a real field u on the N grid: c = n . F_N[u]
-hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double>* cout);
+hipError_t pipe_project_real(CellImpl* c, Work<double>& w, int items, const double* u,
+                             cpx<double>* cout);
 
 }  // namespace hom
 

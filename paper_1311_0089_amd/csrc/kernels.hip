@@ -452,6 +452,11 @@ __global__ void k_convert(const double* in, float* out, long n) {
     out[i] = (float)in[i];
 }
 
+__global__ void k_zero(double* p, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
 __global__ void k_widen(const float* in, double* out, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     out[i] = (double)in[i];
@@ -641,6 +646,14 @@ hipError_t launch_convert(const double* in, float* out, long n, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   launch_k(k_convert, dim3(blocks), dim3(kThreads), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, long n, hipStream_t s) {
+  int blocks = ceil_div(n, kThreads);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  launch_k(k_zero, dim3(blocks), dim3(kThreads), 0, s, p, n);
   return hipGetLastError();
 }
 

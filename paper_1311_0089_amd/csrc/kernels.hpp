@@ -338,6 +338,8 @@ hipError_t launch_quad_final(const double* partials, int blocks, int nl, int nm,
 // FP64 <-> FP32 element copies
 hipError_t launch_convert(const double* in, float* out, long n, hipStream_t s);
 hipError_t launch_widen(const float* in, double* out, long n, hipStream_t s);
+// p[0..n) = 0 by a kernel (no memset node where a caller captures a graph)
+hipError_t launch_zero(double* p, long n, hipStream_t s);
 
 // largest dynamic LDS size a kernel may use (set at library init)
 hipError_t configure_kernels(size_t max_lds);

@@ -498,9 +498,9 @@ hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>
                            nullptr);
 }
 
-hipError_t pipe_project_real(CellImpl* c, int items, const double* u, cpx<double>* cout) {
+hipError_t pipe_project_real(CellImpl* c, Work<double>& w, int items, const double* u,
+                             cpx<double>* cout) {
   hipError_t e;
-  Work<double>& w = c->w64;
   const int N0 = c->N[0], N1 = c->N[1], N2 = c->N[2];
   cpx<double>* X = w.X1;
   if (c->dd == 3) {
@@ -868,7 +868,7 @@ static hipError_t warm_start(CellImpl* c, int L, const double* strain0) {
   // x0 = n . F_N[strain0] (its E_N part); r = b - Op x0 with partials of
   // (r, r) in part; p = r
   Work<double>& w = c->w64;
-  hipError_t e = pipe_project_real(c, L, strain0, w.x);
+  hipError_t e = pipe_project_real(c, w, L, strain0, w.x);
   if (e != hipSuccess) return e;
   if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, nullptr,
                               w.part)) != hipSuccess)
@@ -944,6 +944,7 @@ const char* hom_status_str(hom_status s) {
     case HOM_EBREAKDOWN: return "CG breakdown";
     case HOM_EDEVICE: return "device error";
     case HOM_EBUSY: return "busy";
+    case HOM_ESCRATCH: return "workspace exceeds the allocation-free scratch";
   }
   return "unknown status";
 }
@@ -1303,7 +1304,7 @@ hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double
   std::vector<double> zero((size_t)L * c->d, 0.0);
   do {
     if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
-    if ((e = pipe_project_real(c, L, u, w.x)) != hipSuccess) break;
+    if ((e = pipe_project_real(c, w, L, u, w.x)) != hipSuccess) break;
     if (prec == HOM_FP64) {
       if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_STORE, w.q, nullptr, nullptr, nullptr,
                                   nullptr)) != hipSuccess)
@@ -1336,7 +1337,7 @@ hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
   std::vector<double> zero((size_t)L * c->d, 0.0);
   do {
     if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
-    if ((e = pipe_project_real(c, L, u, c->w64.x)) != hipSuccess) break;
+    if ((e = pipe_project_real(c, c->w64, L, u, c->w64.x)) != hipSuccess) break;
     if ((e = pipe_synth(c, c->w64, L, c->w64.x, dE, false, out)) != hipSuccess) break;
     e = hipStreamSynchronize(c->stream);
   } while (false);
@@ -1344,6 +1345,115 @@ hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free operator apply: the workspace lives in a fixed array of
+// device memory inside the library (one copy per GPU, kept until the process
+// ends) instead of the cell's own buffers
+// ---------------------------------------------------------------------------
+namespace hom {
+
+static __device__ __align__(256) unsigned char scratch[HOM_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_ptr;
+
+// device address of this GPU's copy of the array, taken once per device with
+// that device current (the array's name is only a host-side stand-in)
+static hipError_t scratch_base(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+  *out = static_cast<unsigned char*>(ptr);
+  return hipSuccess;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// scratch bytes of an apply on L items: FP64 potential, output and two
+// component-spectrum buffers (the FP32 pass reuses the latter), FP32 potential
+// and output (HOM_MIXED), zero load cases for the synthesis
+static size_t noalloc_bytes(const CellImpl* c, int L, bool mixed) {
+  const size_t sv = sizeof(cpx<double>) * (size_t)c->S * L;
+  const size_t xv = sizeof(cpx<double>) * (size_t)c->Xe * c->dd * L;
+  size_t b = 2 * align256(sv) + 2 * align256(xv) + align256(sizeof(double) * 3 * (size_t)L);
+  if (mixed) b += 2 * align256(sizeof(cpx<float>) * (size_t)c->S * L);
+  return b;
+}
+
+}  // namespace hom
+
+extern "C" hom_status hom_apply_noalloc(hom_cell* hc, hom_prec prec, int L, const double* u,
+                                        double* out) {
+  if (!hc || L < 1 || !u || !out || (prec != HOM_FP64 && prec != HOM_MIXED)) return HOM_EINVAL;
+  CellImpl* c = hc->impl;
+  if (c->d != c->dd) return HOM_EINVAL;
+  const bool mixed = (prec == HOM_MIXED);
+  if (noalloc_bytes(c, L, mixed) > (size_t)HOM_NOALLOC_SCRATCH_BYTES) return HOM_ESCRATCH;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipSetDevice(c->device);
+  unsigned char* base = nullptr;
+  if (e == hipSuccess) e = scratch_base(c->device, &base);
+  if (e != hipSuccess) return dev_status(e);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* q = base + off;
+    off += align256(bytes);
+    return q;
+  };
+  const size_t sv = sizeof(cpx<double>) * (size_t)c->S * L;
+  const size_t xv = sizeof(cpx<double>) * (size_t)c->Xe * c->dd * L;
+  Work<double> w;
+  w.items = L;
+  w.x = reinterpret_cast<cpx<double>*>(take(sv));
+  w.q = reinterpret_cast<cpx<double>*>(take(sv));
+  w.X1 = reinterpret_cast<cpx<double>*>(take(xv));
+  w.X2 = reinterpret_cast<cpx<double>*>(take(xv));
+  w.r = w.p = w.b = w.x;   // not read by these passes (no CG epilogue)
+  double* dE = reinterpret_cast<double*>(take(sizeof(double) * 3 * (size_t)L));
+  Work<float> w32;
+  if (mixed) {
+    w32.items = L;
+    w32.x = reinterpret_cast<cpx<float>*>(take(sizeof(cpx<float>) * (size_t)c->S * L));
+    w32.q = reinterpret_cast<cpx<float>*>(take(sizeof(cpx<float>) * (size_t)c->S * L));
+    // the FP32 component spectra fit in the first half of the FP64 ones,
+    // which are not live while the FP32 passes run
+    w32.X1 = reinterpret_cast<cpx<float>*>(w.X1);
+    w32.X2 = reinterpret_cast<cpx<float>*>(w.X2);
+    w32.r = w32.p = w32.b = w32.x;
+  }
+  // work is queued on the caller's stream (the cell's own when it gave none)
+  // and not waited for; the cell's stream is restored before returning
+  const hipStream_t own = c->stream;
+  if (c->opt.stream) c->stream = (hipStream_t)c->opt.stream;
+  do {
+    // the synthesis adds the load case, which is zero here; the array keeps
+    // the last call's contents, so it is cleared on every call
+    if ((e = launch_zero(dE, 3 * (long)L, c->stream)) != hipSuccess) break;
+    if ((e = pipe_project_real(c, w, L, u, w.x)) != hipSuccess) break;
+    if (!mixed) {
+      if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_STORE, w.q, nullptr, nullptr, nullptr,
+                                  nullptr)) != hipSuccess)
+        break;
+    } else {
+      const long n = 2 * c->S * L;
+      if ((e = launch_convert((const double*)w.x, (float*)w32.x, n, c->stream)) != hipSuccess) break;
+      if ((e = pipe_apply<float>(c, w32, L, w32.x, 0, EPI_STORE, w32.q, nullptr, nullptr, nullptr,
+                                 nullptr)) != hipSuccess)
+        break;
+      if ((e = launch_widen((const float*)w32.q, (double*)w.q, n, c->stream)) != hipSuccess) break;
+    }
+    e = pipe_synth(c, w, L, w.q, dE, false, out);
+  } while (false);
+  c->stream = own;
+  return dev_status(e);
+}
 
 // ---------------------------------------------------------------------------
 // per-kernel timing of one CG iteration

@@ -20,6 +20,7 @@ ISO, DIAG, FULLSYM = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "hom_options_default", "hom_create_cell", "hom_solve", "hom_apply", "hom_project",
+    "hom_apply_noalloc",
     "hom_profile_iteration", "hom_set_specialized", "hom_autotune", "hom_pass_variants",
     "hom_force_variant", "hom_tune_save",
     "hom_tune_load", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
@@ -71,6 +72,7 @@ def lib():
         L.hom_solve.argtypes = [vp, ip, dp, ctypes.c_double, vp, dp, dp, vp, ctypes.POINTER(Info)]
         L.hom_apply.argtypes = [vp, ip, ip, vp, vp]
         L.hom_project.argtypes = [vp, ip, vp, vp]
+        L.hom_apply_noalloc.argtypes = [vp, ip, ip, vp, vp]
         L.hom_profile_iteration.argtypes = [vp, ip, ip, ip, dp, dp]
         L.hom_set_specialized.argtypes = [ip]
         L.hom_autotune.argtypes = [vp, ip, ip, ip, dp]
@@ -213,6 +215,13 @@ class Cell:
         _check(lib().hom_apply(self._h, prec, u.shape[0], ctypes.c_void_p(u.data_ptr()),
                                ctypes.c_void_p(out.data_ptr())), "hom_apply")
         return out
+
+    def apply_noalloc(self, u, out, prec=FP64):
+        """hom_apply with the library's fixed scratch as workspace (no device
+        allocation inside the call); out: a torch CUDA float64 tensor shaped
+        like u, written in place.  Returns the status code."""
+        return lib().hom_apply_noalloc(self._h, prec, u.shape[0], ctypes.c_void_p(u.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()))
 
     def project(self, u):
         """out = G u (projection onto E_N)."""
