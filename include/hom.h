@@ -164,7 +164,8 @@ hom_status hom_profile_iteration(hom_cell* c, hom_prec prec, int L, int reps, do
 
 /* Enable (default, 1) or disable (0) the compile-time specialised kernels of
  * the sizes they exist for; disabled, every size runs the generic kernels.
- * Process-wide; for A/B timing and testing. */
+ * Process-wide, for A/B timing and testing only: it takes effect for every
+ * cell and server at its next launch (captured graphs are captured again). */
 hom_status hom_set_specialized(int enable);
 
 /* Autotuner: for each pass of c's CG iteration (L load cases, precision
@@ -184,6 +185,9 @@ hom_status hom_pass_variants(hom_cell* c, hom_prec prec, int32_t* counts);
  * c's shape and precision, process-wide, until changed (testing and A/B
  * timing).  HOM_EINVAL for a variant or pass that does not exist. */
 hom_status hom_force_variant(hom_cell* c, hom_prec prec, int pass, int variant);
+/* The variant pass `pass` of c's iteration runs now (-1: the generic kernel),
+ * as hom_force_variant takes it, so a test can restore it. */
+hom_status hom_current_variant(hom_cell* c, hom_prec prec, int pass, int32_t* variant);
 /* Write / read the tuned choices as JSON ({"arch": ..., "choices": [[pass,
  * element bytes, FFT length, trial length, components, variant], ...]});
  * loading a file tuned on another GPU architecture returns HOM_EINVAL. */

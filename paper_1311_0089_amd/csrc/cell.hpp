@@ -33,12 +33,16 @@ struct Work {
   hipError_t alloc(int items, long S, long Xe, int d, int P);
 };
 
+// a captured CG graph: precision, items, iterations, and the version of the
+// kernel choices it was captured with (tune_version)
 struct GraphKey {
   int prec, items, K;
+  unsigned version;
   bool operator<(const GraphKey& o) const {
     if (prec != o.prec) return prec < o.prec;
     if (items != o.items) return items < o.items;
-    return K < o.K;
+    if (K != o.K) return K < o.K;
+    return version < o.version;
   }
 };
 

@@ -257,14 +257,14 @@ struct cpx2 {
 };
 
 // CG bookkeeping of one completed update from the sum s = (r, r): iteration
-// count, stopping test (relative residual or budget), beta and rho.  One
-// thread of one workgroup per item runs it, in a kernel whose other
-// workgroups do not read these fields.
+// count, stopping test (relative residual or budget), beta and rho; a stop
+// raises `halt`.  One thread of one workgroup per item runs it, in a kernel
+// whose other workgroups do not read these fields.
 __device__ __forceinline__ void cg_book(ItemScal& q, double s) {
   q.iters += 1;
   if (!isfinite(s)) {
     q.status = -5;
-    q.active = 0;
+    q.halt = 1;
     return;
   }
   // beta is kept also when the item stops: a residual replacement of the
@@ -272,9 +272,9 @@ __device__ __forceinline__ void cg_book(ItemScal& q, double s) {
   q.beta = s / q.rho;
   if (sqrt(s / q.rho0) <= q.tol) {
     q.conv = 1;
-    q.active = 0;
+    q.halt = 1;
   } else if (q.iters >= q.max_iter) {
-    q.active = 0;
+    q.halt = 1;
   }
   q.rho = s;
 }
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
   const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
+  if (a.sc && !item_live(a.sc[item])) return;
   const int W = P::W(a.W), n_in = P::ntrial(a.n_in), n_fft = P::nfft(a.n_fft);
   const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
   const int ncols = min(W, a.inner - col0);
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_plain(ColPlainArgs<T> a) 
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
   const int item = blockIdx.z / a.d, comp = blockIdx.z % a.d;
-  if (a.sc && !a.sc[item].active) return;
+  if (a.sc && !item_live(a.sc[item])) return;
   const int W = P::W(a.W), n_fft = P::nfft(a.n_fft);
   const int n_in = (S > 0) ? P::ntrial(a.n_in) : P::nfft(a.n_in);
   const int n_out = (S > 0) ? P::nfft(a.n_out) : P::ntrial(a.n_out);
@@ -475,7 +475,14 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   constexpr int NT = P::NT;
   const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
+  if (a.sc && !item_live_project(a.sc[item])) {
+    // an item whose update broke down stops here: the first workgroup raises
+    // halt for the update of this iteration (no workgroup here reads it)
+    const ItemScal& q0 = a.sc[item];
+    if (q0.active && q0.broke && a.rr_part && blockIdx.x == 0 && threadIdx.x == 0)
+      a.sc[item].halt = 1;
+    return;
+  }
   const int W = P::W(a.W), n_fft = P::nfft(a.n_fft), n_out = P::ntrial(a.n_out);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int col0 = tile * W;
@@ -651,7 +658,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   const int n = P::n(a.n), H = P::H(a.H), RP = P::RP(a.RP), d = P::D(a.d);
   const int ls = P::ls(a.plan.len);
   const int item = blockIdx.y;
-  if (a.sc && !a.sc[item].active) return;
+  if (a.sc && !item_live(a.sc[item])) return;
   const int pair0 = xcd_tile(blockIdx.x, gridDim.x) * RP;
 
   if (MODE == ROW_APPLY || MODE == ROW_SYNTH) {

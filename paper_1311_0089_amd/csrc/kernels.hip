@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -24,10 +25,18 @@ std::vector<StaticKernel>& static_registry() {
   return v;
 }
 void register_static(const StaticKernel& k) { static_registry().push_back(k); }
-static bool g_static_on = true;
+// Kernel choices are process-wide (they depend only on the pass and its
+// sizes); every change bumps a version that captured graphs are keyed by, so
+// a graph captured with the old kernels is never replayed after a change.
+static std::atomic<bool> g_static_on{true};
+static std::atomic<unsigned> g_tune_version{0};
 static size_t g_static_max_lds = 0;
-void set_static_enabled(bool on) { g_static_on = on; }
+void set_static_enabled(bool on) {
+  g_static_on = on;
+  ++g_tune_version;
+}
 bool static_enabled() { return g_static_on; }
+unsigned tune_version() { return g_tune_version.load(); }
 static std::mutex g_tune_mu;
 static std::map<TuneKey, int> g_choice;   // -1: generic kernel, v >= 0: v-th variant
 
@@ -53,6 +62,7 @@ std::vector<const StaticKernel*> static_variants(int kind, int esz, int n, int n
 void set_choice(const TuneKey& key, int v) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_choice[key] = v;
+  ++g_tune_version;
 }
 bool get_choice(const TuneKey& key, int* v) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -84,7 +94,10 @@ const StaticKernel* find_static(int kind, int esz, int n, int ntrial, int d, con
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   const int item = blockIdx.y;
-  if (!a.sc[item].active) return;
+  // the projection's booking is visible to later projections through
+  // `stopped` (the projection never reads `halt`, which it raises itself)
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.sc[item].stopped = a.sc[item].halt;
+  if (!item_live(a.sc[item])) return;
   // rounds of CH elements per thread (grid-stride); the first round's loads go
   // out before alpha is derived
   constexpr int CH = 4;
@@ -114,10 +127,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   load(e0);
   const double g = partials_finish(pq, a.pq_n, ph);
   if (!(g > 0.0) || !isfinite(g)) {
+    // every workgroup derives the breakdown itself; the first one records it
+    // for the passes of later iterations (none of this launch reads it)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.sc[item].gamma = g;
       a.sc[item].status = -5;
-      a.sc[item].active = 0;
+      a.sc[item].broke = 1;
     }
     return;
   }
@@ -157,32 +172,50 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg_init(ItemScal* sc, const double* partials, int P,
-                                                      int nparts, const ItemScal* mask) {
+                                                      int nparts, const ItemScal* mask,
+                                                      const double* ref) {
   const int item = blockIdx.x;
   if (!sc[item].active || (mask && !mask[item].active)) return;
   const double s = sum_partials_wave(partials + (long)item * P, nparts);
+  // the stopping test is relative to (b, b) (ref, for a warm start) or to the
+  // initial residual itself (a cold start, where r_0 = b)
+  const double r0 = ref ? sum_partials_wave(ref + (long)item * P, nparts) : s;
   if (threadIdx.x == 0) {
     ItemScal& q = sc[item];
-    q.rho = q.rho0 = s;
+    q.rho = s;
+    q.rho0 = (r0 > 0.0) ? r0 : s;
+    q.halt = q.stopped = q.broke = 0;
     q.iters = 0;
     q.beta = 0.0;
     q.alpha = 0.0;
     q.fresh = 1;
     q.status = 0;
-    q.conv = (s == 0.0) ? 1 : 0;
-    q.active = (s > 0.0 && isfinite(s) && q.max_iter > 0) ? 1 : 0;
+    const bool met = (s == 0.0) || sqrt(s / q.rho0) <= q.tol;
+    q.conv = met ? 1 : 0;
+    q.active = (!met && isfinite(s) && q.max_iter > 0) ? 1 : 0;
     if (!isfinite(s)) q.status = -5;
   }
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg_finalize(ItemScal* sc, const double* partials,
                                                           int P, int nparts) {
+  // one workgroup per item, after the iterations of a launch: books the last
+  // update unless the item stopped before it, then retires a stopped item
   const int item = blockIdx.x;
-  if (!sc[item].active || sc[item].fresh) return;
-  const double s = sum_partials_wave(partials + (long)item * P, nparts);
+  const ItemScal q0 = sc[item];
+  if (!q0.active) return;
+  const bool book = !q0.fresh && !q0.halt && !q0.broke;
+  const double s = book ? sum_partials_wave(partials + (long)item * P, nparts) : 0.0;
   if (threadIdx.x == 0) {
-    cg_book(sc[item], s);
-    sc[item].fresh = 1;
+    ItemScal& q = sc[item];
+    if (book) {
+      cg_book(q, s);
+      q.fresh = 1;
+    }
+    if (q.halt || q.broke) {
+      q.active = 0;
+      q.stopped = 1;
+    }
   }
 }
 
@@ -244,6 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_inner_start(const cpx<double>* r64
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     inner[item].max_iter = max_iter;
     inner[item].active = 1;
+    inner[item].halt = inner[item].stopped = inner[item].broke = 0;
     if (!keep_dir) {
       inner[item].iters = 0;
       inner[item].beta = 0.0;
@@ -574,8 +608,8 @@ hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hip
 }
 
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                          hipStream_t s, const ItemScal* mask) {
-  launch_k(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask);
+                          hipStream_t s, const ItemScal* mask, const double* ref) {
+  launch_k(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask, ref);
   return hipGetLastError();
 }
 hipError_t launch_cg_finalize(ItemScal* sc, const double* partials, int P, int nparts, int items,

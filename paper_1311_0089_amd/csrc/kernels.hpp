@@ -47,7 +47,27 @@ struct ItemScal {
   int max_iter;
   int fresh;     // 1: beta and the stopping test are current (set at a (re)start and by
                  // the end-of-launch bookkeeping); 0: the next expansion derives them
+  // Stop flags of the captured iterations.  Inside a graph no kernel writes a
+  // field that other workgroups of the same launch read: the projection's
+  // first workgroup books the last update and raises `halt` (read from the
+  // update on, never by the projection); the update's first workgroup copies
+  // `halt` into `stopped` (read by the projections of later iterations) and
+  // raises `broke` on breakdown (read by the passes of later iterations,
+  // never by the update).  `active` changes only outside the iterations: the
+  // end-of-launch bookkeeping clears it once `halt` or `broke` is raised.
+  int halt;
+  int stopped;
+  int broke;
 };
+
+// an item the passes of a CG iteration still work on (the projection tests
+// `stopped` instead of `halt`, which it raises itself)
+__host__ __device__ inline bool item_live(const ItemScal& q) {
+  return q.active && !q.halt && !q.broke;
+}
+__host__ __device__ inline bool item_live_project(const ItemScal& q) {
+  return q.active && !q.stopped && !q.broke;
+}
 
 enum { EPI_STORE = 0, EPI_RHS = 1, EPI_RESID = 2 };
 enum { ROW_APPLY = 0, ROW_CONST = 1, ROW_SYNTH = 2, ROW_FWD = 3 };
@@ -182,6 +202,8 @@ std::vector<StaticKernel>& static_registry();
 void register_static(const StaticKernel& k);
 void set_static_enabled(bool on);
 bool static_enabled();
+// bumped by every change of the kernel choices (set_choice, set_static_enabled)
+unsigned tune_version();
 // entry for (kind, element size, FFT length, trial length, d) whose plan
 // matches p, or nullptr (then the generic kernel runs); follows the tuned
 // choice when one is recorded, else the first registered variant
@@ -290,9 +312,13 @@ hipError_t a_field_range(const double* A, int d, int kind, long npts, double* sc
 // launchers below: hipExtLaunchKernel records them from the dispatch itself.
 void arm_launch_events(hipEvent_t start, hipEvent_t stop);
 
-// mask (nullable): only items active in the mask are touched
+// CG start: rho = (r_0, r_0) from partials; the stopping test is relative to
+// (b, b) from ref (nullable: to rho itself, the cold start where r_0 = b); an
+// item already meeting it does not iterate.  mask (nullable): only items
+// active in the mask are touched
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
-                          hipStream_t s, const ItemScal* mask = nullptr);
+                          hipStream_t s, const ItemScal* mask = nullptr,
+                          const double* ref = nullptr);
 // end-of-launch bookkeeping of the last update: iteration count, stopping
 // test, beta and rho from its (r, r) partials; marks the scalars fresh
 hipError_t launch_cg_finalize(ItemScal* sc, const double* partials, int P, int nparts, int items,

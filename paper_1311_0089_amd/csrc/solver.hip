@@ -601,11 +601,27 @@ static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K, bool finali
 
 template <class T>
 hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
-  GraphKey key{(int)sizeof(T), items, K};
+  GraphKey key{(int)sizeof(T), items, K, tune_version()};
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
     return hipSuccess;
+  }
+  // graphs captured with other kernel choices are never replayed again (the
+  // stream is drained first: one of them may still be running)
+  bool stale = false;
+  for (const auto& g : c->graphs) stale = stale || g.first.version != key.version;
+  if (stale) {
+    hipError_t es = hipStreamSynchronize(c->stream);
+    if (es != hipSuccess) return es;
+  }
+  for (auto g = c->graphs.begin(); g != c->graphs.end();) {
+    if (g->first.version != key.version) {
+      (void)hipGraphExecDestroy(g->second);
+      g = c->graphs.erase(g);
+    } else {
+      ++g;
+    }
   }
   hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
@@ -864,14 +880,14 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
   return hipSuccess;
 }
 
-static hipError_t warm_start(CellImpl* c, int L, const double* strain0) {
+static hipError_t warm_start(CellImpl* c, int L, const double* strain0, double* partials) {
   // x0 = n . F_N[strain0] (its E_N part); r = b - Op x0 with partials of
-  // (r, r) in part; p = r
+  // (r, r) in `partials`; p = r
   Work<double>& w = c->w64;
   hipError_t e = pipe_project_real(c, w, L, strain0, w.x);
   if (e != hipSuccess) return e;
   if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, nullptr,
-                              w.part)) != hipSuccess)
+                              partials)) != hipSuccess)
     return e;
   return hipMemcpyAsync(w.p, w.r, sizeof(cpx<double>) * (size_t)c->S * L,
                         hipMemcpyDeviceToDevice, c->stream);
@@ -1163,9 +1179,17 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
     std::vector<double> bb;
     if (!mixed && (e = sum_partials_host(c, w.part, L, tiles64, bb)) != hipSuccess) break;
     if (!mixed) {
-      if (strain0 && (e = warm_start(c, L, strain0)) != hipSuccess) break;
-      // rho0 = (r0, r0): of b, or of the warm residual written by warm_start
-      if ((e = launch_cg_init(w.sc, w.part, P, tiles64, L, c->stream)) != hipSuccess) break;
+      // rho = (r0, r0) of b, or of the warm residual (partials in part2); the
+      // stopping test is relative to ||b|| either way, so a warm start that
+      // already meets it does not iterate
+      if (strain0) {
+        if ((e = warm_start(c, L, strain0, w.part2)) != hipSuccess) break;
+        if ((e = launch_cg_init(w.sc, w.part2, P, tiles64, L, c->stream, nullptr, w.part)) !=
+            hipSuccess)
+          break;
+      } else if ((e = launch_cg_init(w.sc, w.part, P, tiles64, L, c->stream)) != hipSuccess) {
+        break;
+      }
       if ((e = cg_run<double>(c, L, c->opt.max_iter, hs)) != hipSuccess) break;
       for (auto& s : hs) {
         it_inner = std::max(it_inner, s.iters);
@@ -1181,9 +1205,13 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
       // is kept, so the Krylov recursion goes on instead of restarting.
       Work<float>& w32 = c->w32;
       ItemScal* outer = w.sc;
+      // the recursion's scalars start cleared: an item done before its first
+      // recursion (b = 0, or a warm start that meets the test) reports 0
+      // iterations
+      if ((e = launch_set_scal(w32.sc, L, 0.0, c->opt.max_iter, 0, c->stream)) != hipSuccess) break;
       if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 1, c->stream)) != hipSuccess) break;
       if (strain0) {
-        if ((e = warm_start(c, L, strain0)) != hipSuccess) break;
+        if ((e = warm_start(c, L, strain0, w.part)) != hipSuccess) break;
         if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream)) != hipSuccess)
           break;
       }
@@ -1744,6 +1772,32 @@ extern "C" hom_status hom_force_variant(hom_cell* hc, hom_prec prec, int pass, i
     return HOM_OK;
   }
   return HOM_EINVAL;   // the pass does not exist for this cell (axis 1 of a 2-D cell)
+}
+
+extern "C" hom_status hom_current_variant(hom_cell* hc, hom_prec prec, int pass,
+                                          int32_t* variant) {
+  if (!hc || !variant || (prec != HOM_FP64 && prec != HOM_MIXED) || pass < 0 || pass > 4)
+    return HOM_EINVAL;
+  hom::CellImpl* c = hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return HOM_EDEVICE;
+  const auto keys = (prec == HOM_FP64) ? hom::pass_keys<double>(c) : hom::pass_keys<float>(c);
+  for (const auto& pk : keys) {
+    if (pk.slot != pass) continue;
+    const hom::DevPlan* pl = nullptr;
+    if (hom::get_dev_plan(pk.fft_len, &pl) != hipSuccess) return HOM_EDEVICE;
+    const hom::StaticKernel* sk =
+        hom::find_static(pk.key.kind, pk.key.esz, pk.key.n, pk.key.ntrial, pk.key.d, pl->p);
+    *variant = -1;
+    if (sk) {
+      const auto v = hom::static_variants(pk.key.kind, pk.key.esz, pk.key.n, pk.key.ntrial,
+                                          pk.key.d, pl->p);
+      for (size_t i = 0; i < v.size(); ++i)
+        if (v[i] == sk) *variant = (int32_t)i;
+    }
+    return HOM_OK;
+  }
+  return HOM_EINVAL;
 }
 
 extern "C" hom_status hom_tune_save(const char* path) {

@@ -22,7 +22,7 @@ EXPORTED_SYMBOLS = [
     "hom_options_default", "hom_create_cell", "hom_solve", "hom_apply", "hom_project",
     "hom_apply_noalloc",
     "hom_profile_iteration", "hom_set_specialized", "hom_autotune", "hom_pass_variants",
-    "hom_force_variant", "hom_tune_save",
+    "hom_force_variant", "hom_current_variant", "hom_tune_save",
     "hom_tune_load", "hom_destroy_cell", "hom_status_str", "hom_cell_dims",
     "hom_server_create", "hom_server_submit", "hom_server_poll", "hom_server_times",
     "hom_server_destroy",
@@ -78,6 +78,7 @@ def lib():
         L.hom_autotune.argtypes = [vp, ip, ip, ip, dp]
         L.hom_pass_variants.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32)]
         L.hom_force_variant.argtypes = [vp, ip, ip, ip]
+        L.hom_current_variant.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_int32)]
         L.hom_tune_save.argtypes = [ctypes.c_char_p]
         L.hom_tune_load.argtypes = [ctypes.c_char_p]
         L.hom_destroy_cell.argtypes = [vp]
@@ -249,6 +250,13 @@ class Cell:
         """Run variant `variant` (-1: generic kernel) of pass `pass_index` for
         every cell of this shape and precision (process-wide)."""
         _check(lib().hom_force_variant(self._h, prec, pass_index, variant), "hom_force_variant")
+
+    def current_variant(self, pass_index, prec=FP64):
+        """The variant pass `pass_index` runs now (-1: the generic kernel)."""
+        v = ctypes.c_int32(0)
+        _check(lib().hom_current_variant(self._h, prec, pass_index, ctypes.byref(v)),
+               "hom_current_variant")
+        return int(v.value)
 
     def profile(self, prec=FP64, L=1, reps=20):
         ms = np.zeros(8)
