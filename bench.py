@@ -319,6 +319,23 @@ def serving(hom, n_req, rate, budget):
             "budget_bytes": budget}
 
 
+def golden_error(w, W):
+    """A_H error against the stored oracle result of this workload
+    (tests/golden, written from the FP64 oracle at tol 1e-13), or None."""
+    name = {"pixels-1023x1023": "pixels", "square-15x15-fp64": "square"}.get(w.name)
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json") if name else ""
+    if not name or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    W = np.asarray(W)
+    L = W.shape[0]
+    if not np.array_equal(np.asarray(g["E"])[:L], w.E):
+        return None
+    ref = np.array(g["W"])[:L, :L]
+    return float(np.abs(W - ref).max() / np.abs(ref).max())
+
+
 def config_of(w, args):
     d = len(w.N)
     return {"workload": w.name, "N": list(w.N), "load_cases": int(w.E.shape[0]),
@@ -376,6 +393,7 @@ def main():
         "rho_A": m["rho_A"],
         "A_H": m["A_H"],
         "A_H_rel_err_vs_fp64": m.get("A_H_rel_err_vs_fp64_1e-10"),
+        "A_H_rel_err_vs_oracle": golden_error(w, m["A_H"]),
         "fp64_path": {k: m[k] for k in m if k.startswith("fp64_")},
         "iteration_profile_us": m["iteration_profile_us"],
         "pass_model_GBps": m["pass_model_GBps"],
@@ -397,6 +415,7 @@ def main():
             mx["config"] = config_of(wx, args)
             if name == "pixels":
                 mx["note"] = "working set (~60 MB FP32) fits the 256 MB Infinity Cache"
+                mx["A_H_rel_err_vs_oracle"] = golden_error(wx, mx["A_H"])
             extra[wx.name] = mx
         out["extra_workloads"] = extra
     if args.serving:
