@@ -465,22 +465,29 @@ int hor_ms(const hor_cell* c, const double* E, double lambda, double tol,
     double* g = (double*)malloc(sizeof(double) * (size_t)n);
     if (!Ef || !t || !g) { free(Ef); free(t); free(g); return HOR_ENOMEM; }
     memcpy(e, Ef, sizeof(double) * (size_t)n);
-    double nE = sqrt(gdot(n, np, Ef, Ef));
-    int s = 0, it = 0;
-    for (it = 0; it < max_iter;) {
+    /* ||b|| of the system G A x = b = -G A E (the CG stopping reference) */
+    int s = hor_apply_GA(c, Ef, t);
+    double bb = s ? 0.0 : gdot(n, np, t, t);
+    int it = 0;
+    for (;;) {
+        /* e_new = E - Gamma_lambda (A - lambda I) e, Gamma_lambda = G / lambda;
+           lambda (e_new - e) = b - G A x for x = e - E, the residual of the
+           system, whose norm is the stopping test */
         s = hor_apply_GA(c, e, t);
         if (!s) s = hor_apply_G(c, e, g);
         if (s) break;
-        double diff = 0.0;
+        double rr = 0.0;
         for (long i = 0; i < n; ++i) {
             double en = Ef[i] - (t[i] - lambda * g[i]) / lambda;
-            diff += (en - e[i]) * (en - e[i]);
-            e[i] = en;
+            rr += lambda * lambda * (en - e[i]) * (en - e[i]);
+            t[i] = en;
         }
+        rr /= (double)np;
+        if (!(bb > 0.0) || sqrt(rr / bb) <= tol) break;
+        if (it >= max_iter) { s = HOR_ENOTCONV; break; }
+        memcpy(e, t, sizeof(double) * (size_t)n);
         ++it;
-        if (sqrt(diff / (double)np) <= tol * nE) break;
     }
-    if (!s && it >= max_iter) s = HOR_ENOTCONV;
     if (iters) *iters = it;
     free(Ef); free(t); free(g);
     return s;

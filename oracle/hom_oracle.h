@@ -78,7 +78,10 @@ int hor_cg_lsd(const hor_cell* c, const double* E, double lambda, double tol,
                int max_iter, double* e, int* iters);
 
 /* Moulinec-Suquet Neumann series e_i = E - Gamma_lambda (A - lambda I) e_{i-1}
- * (Sec. 5.3), e_0 = E; stops when ||e_i - e_{i-1}|| <= tol ||E||. */
+ * (Sec. 5.3), e_0 = E.  lambda (e_i - e_{i-1}) is the residual b - G A x of
+ * the system for x = e_{i-1} - E; the series stops before the step whose
+ * residual meets ||r|| <= tol ||b|| (the CG test), so iters counts the steps
+ * taken.  HOR_ENOTCONV after max_iter steps. */
 int hor_ms(const hor_cell* c, const double* E, double lambda, double tol,
            int max_iter, double* e, int* iters);
 

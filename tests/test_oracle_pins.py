@@ -448,3 +448,33 @@ def test_invalid_inputs_rejected(oracle):
     c = oracle.Cell(np.ones((5, 5)), (5, 5))
     with pytest.raises(OracleError):
         c.cg([1.0, 0.0], tol=-1.0)
+
+
+def _loglog_slope(x, y):
+    return float(np.polyfit(np.log(x), np.log(y), 1)[0])
+
+
+def test_ms_iterations_linear_cg_sqrt_in_contrast(oracle):
+    """Sec. 5.3: the Moulinec-Suquet scheme with lambda = (c_A + C_A)/2
+    contracts by (rho_A - 1)/(rho_A + 1) per step, so its step count to a
+    fixed tolerance grows like rho_A; CG's like sqrt(rho_A).  Fitted
+    log-log slopes over rho_A = 10, 100, 1000 on a two-phase pixel cell; MS
+    never beats the contraction bound."""
+    N = (15, 15)
+    tol = 1e-4
+    rhos = [10.0, 100.0, 1000.0]
+    ms, cg = [], []
+    for rho in rhos:
+        A = hi.bernoulli_majority(N, 0.4, 3, rho, 1.0, seed=7)
+        c = oracle.Cell(A, N)
+        E = np.array([1.0, 0.0])
+        _, it_cg, _ = c.cg(E, tol=tol)
+        _, it_ms = c.ms(E, 0.5 * (1.0 + rho), tol=tol, max_iter=200000)
+        cg.append(it_cg)
+        ms.append(it_ms)
+        # ||r_i|| <= q^i ||b|| in the energy-free bound: i >= log(tol) / log(q)
+        # steps are not needed beyond the bound (plus the conditioning factor)
+        q = (rho - 1.0) / (rho + 1.0)
+        assert it_ms <= np.log(tol / np.sqrt(rho)) / np.log(q) + 2
+    assert _loglog_slope(rhos, ms) > 0.75
+    assert _loglog_slope(rhos, cg) < 0.5
