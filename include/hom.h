@@ -121,6 +121,18 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
 hom_status hom_solve(hom_cell* c, int L, const double* E, double tol, double* strain, double* W,
                      double* J, const double* strain0, hom_info* info);
 
+/* The Moulinec-Suquet basic scheme on the same discrete system (Sec. 5.3, the
+ * Neumann series with reference A0 = lambda I): e_{i+1} = E - Gamma_lambda
+ * (A - lambda I) e_i with lambda = (c_A + C_A) / 2 from the coefficient's
+ * eigenvalue range, i.e. x <- x + (b - G A x) / lambda on the fluctuation,
+ * FP64, from x = 0.  Stops once ||b - G A x|| <= tol ||b|| (the test of
+ * hom_solve's CG), after at most max_iter steps (HOM_ENOTCONV then, results
+ * still written); info->iters_inner counts the steps.  Converges at the rate
+ * (rho_A - 1) / (rho_A + 1) per step where CG needs about sqrt(rho_A) times
+ * fewer steps.  Arguments and errors as hom_solve (no warm start). */
+hom_status hom_solve_ms(hom_cell* c, int L, const double* E, double tol, double* strain,
+                        double* W, double* J, hom_info* info);
+
 /* One application of the system operator to L real fields:
  * out = G_N A_N G_N u (Ga: the exact-integration operator), u and out device
  * pointers [L][d][N grid] FP64; prec chooses FP64 or FP32 arithmetic inside.

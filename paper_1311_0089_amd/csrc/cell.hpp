@@ -38,7 +38,9 @@ struct Work {
 struct GraphKey {
   int prec, items, K;
   unsigned version;
+  int solver;   // 0 conjugate gradients, 1 Moulinec-Suquet
   bool operator<(const GraphKey& o) const {
+    if (solver != o.solver) return solver < o.solver;
     if (prec != o.prec) return prec < o.prec;
     if (items != o.items) return items < o.items;
     if (K != o.K) return K < o.K;
@@ -54,6 +56,7 @@ struct CellImpl {
   double Y[3] = {0.5, 0.5, 0.5};
   hom_options opt{};
   double rhoA = 1.0;
+  double Alo = 1.0, Ahi = 1.0;  // eigenvalue range c_A, C_A of the coefficient (A2)
   long S = 0;                 // scalar spectrum elements per item
   long Xe = 0;                // component-spectrum elements per component per item
   long nN = 0, nQ = 0;        // grid points
@@ -123,8 +126,10 @@ int scalar_n0(const CellImpl* c);
 int partial_slots(const CellImpl* c);
 template <class T>
 int project_tiles(CellImpl* c);
+// K captured iterations of conjugate gradients (solver 0) or of the
+// Moulinec-Suquet scheme (solver 1, FP64 only)
 template <class T>
-hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out);
+hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out, int solver = 0);
 // scalar potential of a real field u on the N grid: c = n . F_N[u]
 hipError_t pipe_project_real(CellImpl* c, Work<double>& w, int items, const double* u,
                              cpx<double>* cout);

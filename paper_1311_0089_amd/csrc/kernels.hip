@@ -333,10 +333,57 @@ __global__ __launch_bounds__(kThreads) void k_inner_accumulate(cpx<double>* x64,
   }
 }
 
-__global__ void k_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active) {
+// Moulinec-Suquet step bookkeeping, one wave per item (every lane reads the
+// scalars before lane 0 writes them; no other kernel runs meanwhile): s =
+// (r, r) of the residual r = b - Op x the projection just wrote; the item
+// stops when ||r|| <= tol ||b|| (or the budget is spent), else the step
+// x += r / lambda follows and is counted
+__global__ __launch_bounds__(64) void k_ms_book(ItemScal* sc, const double* partials, int P,
+                                                int nparts) {
+  const int item = blockIdx.x;
+  if (!sc[item].active) return;
+  const double s = sum_partials_wave(partials + (long)item * P, nparts);
+  if (threadIdx.x == 0) {
+    ItemScal& q = sc[item];
+    q.rho = s;
+    if (!isfinite(s)) {
+      q.status = -5;
+      q.active = 0;
+    } else if (s == 0.0 || sqrt(s / q.rho0) <= q.tol) {
+      q.conv = 1;
+      q.active = 0;
+    } else if (q.iters >= q.max_iter) {
+      q.active = 0;
+    } else {
+      q.iters += 1;
+    }
+  }
+}
+
+// x += r / lambda for every item still iterating
+__global__ __launch_bounds__(kThreads) void k_ms_axpy(cpx<double>* x, const cpx<double>* r,
+                                                      long stride, long count,
+                                                      const ItemScal* sc) {
+  const int item = blockIdx.y;
+  if (!sc[item].active) return;
+  const double step = sc[item].step;
+  const long base = (long)item * stride;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x) {
+    cpx<double> xv = x[base + e];
+    const cpx<double> rv = r[base + e];
+    xv.x += step * rv.x;
+    xv.y += step * rv.y;
+    x[base + e] = xv;
+  }
+}
+
+__global__ void k_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active,
+                           double step) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < items) {
     ItemScal q{};
+    q.step = step;
     q.tol = tol;
     q.max_iter = max_iter;
     q.active = active;
@@ -609,17 +656,17 @@ hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hip
 
 hipError_t launch_cg_init(ItemScal* sc, const double* partials, int P, int nparts, int items,
                           hipStream_t s, const ItemScal* mask, const double* ref) {
-  launch_k(k_cg_init, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts, mask, ref);
+  launch_k(k_cg_init, dim3(items), dim3(64), 0, s, sc, partials, P, nparts, mask, ref);
   return hipGetLastError();
 }
 hipError_t launch_cg_finalize(ItemScal* sc, const double* partials, int P, int nparts, int items,
                               hipStream_t s) {
-  launch_k(k_cg_finalize, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts);
+  launch_k(k_cg_finalize, dim3(items), dim3(64), 0, s, sc, partials, P, nparts);
   return hipGetLastError();
 }
 hipError_t launch_outer_check(ItemScal* sc, const double* partials, int P, int nparts, int items,
                               int init, hipStream_t s, const ItemScal* mask) {
-  launch_k(k_outer_check, dim3(items), dim3(kThreads), 0, s, sc, partials, P, nparts,
+  launch_k(k_outer_check, dim3(items), dim3(64), 0, s, sc, partials, P, nparts,
                      init, mask);
   return hipGetLastError();
 }
@@ -635,7 +682,7 @@ hipError_t launch_inner_start(const cpx<double>* r64, cpx<float>* r32, cpx<float
 hipError_t launch_inner_init(ItemScal* inner, const double* partials, int P, int nparts, int items,
                              ItemScal* outer, double eta, double theta, hipStream_t s,
                              const ItemScal* mask) {
-  launch_k(k_inner_init, dim3(items), dim3(kThreads), 0, s, inner, partials, P, nparts,
+  launch_k(k_inner_init, dim3(items), dim3(64), 0, s, inner, partials, P, nparts,
                      outer, eta, theta, mask);
   return hipGetLastError();
 }
@@ -646,10 +693,20 @@ hipError_t launch_inner_accumulate(cpx<double>* x64, const cpx<float>* x32, long
                      stride, count, outer, mask);
   return hipGetLastError();
 }
+hipError_t launch_ms_book(ItemScal* sc, const double* partials, int P, int nparts, int items,
+                          hipStream_t s) {
+  launch_k(k_ms_book, dim3(items), dim3(64), 0, s, sc, partials, P, nparts);
+  return hipGetLastError();
+}
+hipError_t launch_ms_axpy(cpx<double>* x, const cpx<double>* r, long stride, long count,
+                          const ItemScal* sc, int blocks, int items, hipStream_t s) {
+  launch_k(k_ms_axpy, dim3(blocks, items), dim3(kThreads), 0, s, x, r, stride, count, sc);
+  return hipGetLastError();
+}
 hipError_t launch_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active,
-                           hipStream_t s) {
+                           hipStream_t s, double step) {
   launch_k(k_set_scal, dim3(ceil_div(items, 64)), dim3(64), 0, s, sc, items, tol,
-                     max_iter, active);
+                     max_iter, active, step);
   return hipGetLastError();
 }
 hipError_t launch_quad(const double* e, long e_stride, long e_cstride, const double* A,

@@ -58,6 +58,9 @@ struct ItemScal {
   int halt;
   int stopped;
   int broke;
+  // Moulinec-Suquet step 1 / lambda, kept here rather than in a captured
+  // kernel argument: cells of one shape share an engine and its graphs
+  double step;
 };
 
 // an item the passes of a CG iteration still work on (the projection tests
@@ -351,9 +354,16 @@ hipError_t launch_inner_init(ItemScal* inner, const double* partials, int P, int
 hipError_t launch_inner_accumulate(cpx<double>* x64, const cpx<float>* x32, long stride, long count,
                                    const ItemScal* outer, int blocks, int items, hipStream_t s,
                                    const ItemScal* mask = nullptr);
+// Moulinec-Suquet iteration (Sec. 5.3): book the residual of the step
+// (partials of (r, r) from the projection): stop at ||r|| <= tol ||b|| or the
+// budget, else count the step; then x += step * r for items still iterating
+hipError_t launch_ms_book(ItemScal* sc, const double* partials, int P, int nparts, int items,
+                          hipStream_t s);
+hipError_t launch_ms_axpy(cpx<double>* x, const cpx<double>* r, long stride, long count,
+                          const ItemScal* sc, int blocks, int items, hipStream_t s);
 // x = 0, active flags etc.
 hipError_t launch_set_scal(ItemScal* sc, int items, double tol, int max_iter, int active,
-                           hipStream_t s);
+                           hipStream_t s, double step = 0.0);
 // energy quadrature over a grid of npts points for load-case groups
 // (l0..l0+nl) x (m0..m0+nm), nl, nm <= 3; e: [L][d][npts], A: [nA][npts]
 hipError_t launch_quad(const double* e, long e_stride, long e_cstride, const double* A,

@@ -599,9 +599,24 @@ static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K, bool finali
   return e;
 }
 
+// one Moulinec-Suquet iteration per step (FP64): r = b - Op x with the
+// partials of (r, r), the booking (stop at ||r|| <= tol ||b||), x += r / lambda
+static hipError_t ms_body(CellImpl* c, Work<double>& w, int items, int K) {
+  hipError_t e = hipSuccess;
+  const int P = partial_slots(c);
+  const int tiles = project_tiles<double>(c);
+  const int ub = update_blocks(c->S);
+  for (int k = 0; k < K && e == hipSuccess; ++k) {
+    e = pipe_apply<double>(c, w, items, w.x, 0, EPI_RESID, w.r, nullptr, w.b, w.sc, w.part);
+    if (e == hipSuccess) e = launch_ms_book(w.sc, w.part, P, tiles, items, c->stream);
+    if (e == hipSuccess) e = launch_ms_axpy(w.x, w.r, c->S, c->S, w.sc, ub, items, c->stream);
+  }
+  return e;
+}
+
 template <class T>
-hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
-  GraphKey key{(int)sizeof(T), items, K, tune_version()};
+hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out, int solver) {
+  GraphKey key{(int)sizeof(T), items, K, tune_version(), solver};
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
@@ -625,7 +640,8 @@ hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
   }
   hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t eb = cg_body<T>(c, work_of<T>(c), items, K);
+  hipError_t eb = (solver == 1) ? ms_body(c, c->w64, items, K)
+                                 : cg_body<T>(c, work_of<T>(c), items, K);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(c->stream, &g);
   if (eb != hipSuccess) e = eb;
@@ -642,8 +658,8 @@ hipError_t cg_graph(CellImpl* c, int items, int K, hipGraphExec_t* out) {
   return hipSuccess;
 }
 
-template hipError_t cg_graph<float>(CellImpl*, int, int, hipGraphExec_t*);
-template hipError_t cg_graph<double>(CellImpl*, int, int, hipGraphExec_t*);
+template hipError_t cg_graph<float>(CellImpl*, int, int, hipGraphExec_t*, int);
+template hipError_t cg_graph<double>(CellImpl*, int, int, hipGraphExec_t*, int);
 
 // Launch planner.  A captured graph runs K iterations; an item that stops
 // inside it leaves the rest as launches that do nothing but still cost their
@@ -685,12 +701,12 @@ struct IterPlanner {
 
 // K iterations as back-to-back launches of graphs of power-of-two lengths
 template <class T>
-static hipError_t cg_launch(CellImpl* c, int items, int K) {
+static hipError_t cg_launch(CellImpl* c, int items, int K, int solver = 0) {
   hipError_t e = hipSuccess;
   for (int b = 1 << 30; b > 0 && e == hipSuccess; b >>= 1) {
     if (!(K & b)) continue;
     hipGraphExec_t g = nullptr;
-    e = cg_graph<T>(c, items, b, &g);
+    e = cg_graph<T>(c, items, b, &g, solver);
     if (e == hipSuccess) e = hipGraphLaunch(g, c->stream);
   }
   return e;
@@ -739,9 +755,11 @@ static hipError_t upload(CellImpl* c, void* dst, const void* src, size_t bytes, 
   return e;
 }
 
-// run CG until every item is inactive
+// run CG (solver 0) or the Moulinec-Suquet iteration (solver 1) until every
+// item is inactive
 template <class T>
-static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemScal>& hs) {
+static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemScal>& hs,
+                         int solver = 0) {
   Work<T>& w = work_of<T>(c);
   IterPlanner plan(items, c->opt.check_every);
   std::vector<char> live(items, 1);
@@ -754,7 +772,7 @@ static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemS
     for (auto& s : hs) any = any || s.active;
     if (!any) break;
     if (launched > (long)max_iter + plan.Kmax) break;  // the device also stops at max_iter
-    if ((e = cg_launch<T>(c, items, K)) != hipSuccess) return e;
+    if ((e = cg_launch<T>(c, items, K, solver)) != hipSuccess) return e;
     launched += K;
     if ((e = read_scal(c, w.sc, items, hs)) != hipSuccess) return e;
     K = plan.next(hs, live);
@@ -1116,6 +1134,8 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
     return (flags & 1) ? HOM_EINVAL : HOM_ENOTSPD;
   }
   c->rhoA = hi / lo;
+  c->Alo = lo;
+  c->Ahi = hi;
   hom_cell* hc = new (std::nothrow) hom_cell();
   if (!hc) {
     pool_put(c);
@@ -1314,6 +1334,59 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
     info->rho_A = c->rhoA;
     info->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+hom_status hom_solve_ms(hom_cell* hc, int L, const double* E, double tol, double* strain,
+                        double* W, double* J, hom_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!hc || L < 1 || !E || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
+  for (int i = 0; i < L * hc->impl->d; ++i)
+    if (!std::isfinite(E[i])) return HOM_EINVAL;
+  CellImpl* c = hc->impl;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = ensure_work(c, L, false);
+  if (e != hipSuccess) return dev_status(e);
+  wait_user_stream(c);
+  double* dE = nullptr;
+  if ((e = upload_E(c, L, E, &dE)) != hipSuccess) return dev_status(e);
+  Work<double>& w = c->w64;
+  const int P = partial_slots(c);
+  hom_status st = HOM_OK;
+  int iters = 0;
+  double relres = 0.0;
+  std::vector<ItemScal> hs;
+  do {
+    // b = -n . F[A E], x = 0; rho0 = (b, b); the step 1 / lambda with
+    // lambda = (c_A + C_A) / 2 goes to the device scalars (a captured graph
+    // may serve later cells of this shape)
+    if ((e = launch_set_scal(w.sc, L, tol, c->opt.max_iter, 1, c->stream,
+                             2.0 / (c->Alo + c->Ahi))) != hipSuccess)
+      break;
+    if ((e = pipe_rhs<double>(c, w, L, dE, nullptr)) != hipSuccess) break;
+    if ((e = launch_cg_init(w.sc, w.part, P, project_tiles<double>(c), L, c->stream)) !=
+        hipSuccess)
+      break;
+    if ((e = cg_run<double>(c, L, c->opt.max_iter, hs, 1)) != hipSuccess) break;
+    for (auto& q : hs) {
+      iters = std::max(iters, q.iters);
+      if (q.status == -5) st = HOM_EBREAKDOWN;
+      else if (!q.conv && st == HOM_OK) st = HOM_ENOTCONV;
+      // the last booking holds (r, r) of the returned iterate, r = b - Op x
+      if (q.rho0 > 0) relres = std::max(relres, std::sqrt(q.rho / q.rho0));
+    }
+    if ((e = homogenize(c, L, dE, strain, W, J)) != hipSuccess) break;
+    e = hipStreamSynchronize(c->stream);
+  } while (false);
+  if (e != hipSuccess) return dev_status(e);
+  if (info) {
+    info->iters_inner = iters;
+    info->iters_outer = 0;
+    info->rel_resid_true = relres;
+    info->rho_A = c->rhoA;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return st;
 }

@@ -19,7 +19,8 @@ FP64, MIXED = 0, 1
 ISO, DIAG, FULLSYM = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
-    "hom_options_default", "hom_create_cell", "hom_solve", "hom_apply", "hom_project",
+    "hom_options_default", "hom_create_cell", "hom_solve", "hom_solve_ms", "hom_apply",
+    "hom_project",
     "hom_apply_noalloc",
     "hom_profile_iteration", "hom_set_specialized", "hom_autotune", "hom_pass_variants",
     "hom_force_variant", "hom_current_variant", "hom_tune_save",
@@ -70,6 +71,7 @@ def lib():
         L.hom_create_cell.argtypes = [ip, ctypes.POINTER(ctypes.c_int32), ip, vp, ip,
                                       ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.hom_solve.argtypes = [vp, ip, dp, ctypes.c_double, vp, dp, dp, vp, ctypes.POINTER(Info)]
+        L.hom_solve_ms.argtypes = [vp, ip, dp, ctypes.c_double, vp, dp, dp, ctypes.POINTER(Info)]
         L.hom_apply.argtypes = [vp, ip, ip, vp, vp]
         L.hom_project.argtypes = [vp, ip, vp, vp]
         L.hom_apply_noalloc.argtypes = [vp, ip, ip, vp, vp]
@@ -203,6 +205,28 @@ class Cell:
         code = lib().hom_solve(self._h, L, _dptr(E), float(tol), sp, _dptr(W), _dptr(J), s0,
                                ctypes.byref(info))
         _check(code, "hom_solve", allow=allow)
+        out = {"W": W, "J": J, "info": info.as_dict(), "status": code}
+        if want_strain:
+            out["strain"] = strain
+        return out
+
+    def solve_ms(self, E, tol=1e-8, want_strain=False, allow=()):
+        """The Moulinec-Suquet scheme (hom_solve_ms) on load cases E [L][d];
+        returns the same dict as solve()."""
+        import torch
+        E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
+        L = E.shape[0]
+        W = np.zeros((L, L))
+        J = np.zeros((L, self.d))
+        info = Info()
+        strain = None
+        sp = ctypes.c_void_p(None)
+        if want_strain:
+            strain = torch.empty((L, self.d) + self.N, dtype=torch.float64, device="cuda")
+            sp = ctypes.c_void_p(strain.data_ptr())
+        code = lib().hom_solve_ms(self._h, L, _dptr(E), float(tol), sp, _dptr(W), _dptr(J),
+                                  ctypes.byref(info))
+        _check(code, "hom_solve_ms", allow=allow)
         out = {"W": W, "J": J, "info": info.as_dict(), "status": code}
         if want_strain:
             out["strain"] = strain
