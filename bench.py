@@ -59,6 +59,8 @@ def parse():
                          "re-tune now, or first registered variant")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--extra", action="store_true", help="also measure the other workloads")
+    ap.add_argument("--ms-experiment", action="store_true",
+                    help="CG and Moulinec-Suquet steps and times against the contrast")
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving stream")
     ap.add_argument("--serving-rate", type=float, default=500.0)
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -336,6 +338,35 @@ def golden_error(w, W):
     return float(np.abs(W - ref).max() / np.abs(ref).max())
 
 
+def ms_experiment(hom, n=255, rhos=(10.0, 100.0, 1000.0, 10000.0), tol=1e-6):
+    """Steps and solve times of CG (hom_solve) and the Moulinec-Suquet series
+    (hom_solve_ms), FP64, on a two-phase pixel cell n x n for each contrast;
+    fitted log-log slopes of the step counts (Sec. 5.3: about 1/2 for CG, 1
+    for the series)."""
+    import hom_inputs as hi
+    rows = []
+    for rho in rhos:
+        A = hi.bernoulli_majority((n, n), 0.4, 3, rho, 1.0, seed=2)
+        c = hom.Cell(A, (n, n), max_iter=400000)
+        c.solve([[1.0, 0.0]], tol=tol)
+        t0 = time.perf_counter()
+        rc = c.solve([[1.0, 0.0]], tol=tol)
+        t_cg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rm = c.solve_ms([[1.0, 0.0]], tol=tol)
+        t_ms = time.perf_counter() - t0
+        c.close()
+        rows.append({"rho_A": rho, "cg_steps": rc["info"]["iters_inner"], "cg_ms": t_cg * 1e3,
+                     "ms_steps": rm["info"]["iters_inner"], "ms_ms": t_ms * 1e3,
+                     "A_H_11_cg": rc["W"][0, 0], "A_H_11_ms": rm["W"][0, 0]})
+        log(f"ms experiment rho {rho:g}: CG {rows[-1]['cg_steps']} steps {t_cg * 1e3:.1f} ms, "
+            f"MS {rows[-1]['ms_steps']} steps {t_ms * 1e3:.1f} ms")
+    lr = np.log([r["rho_A"] for r in rows])
+    return {"grid": [n, n], "tol": tol, "precision": "fp64", "rows": rows,
+            "slope_cg": float(np.polyfit(lr, np.log([r["cg_steps"] for r in rows]), 1)[0]),
+            "slope_ms": float(np.polyfit(lr, np.log([r["ms_steps"] for r in rows]), 1)[0])}
+
+
 def config_of(w, args):
     d = len(w.N)
     return {"workload": w.name, "N": list(w.N), "load_cases": int(w.E.shape[0]),
@@ -418,6 +449,8 @@ def main():
                 mx["A_H_rel_err_vs_oracle"] = golden_error(wx, mx["A_H"])
             extra[wx.name] = mx
         out["extra_workloads"] = extra
+    if args.ms_experiment:
+        out["ms_vs_cg"] = ms_experiment(hom)
     if args.serving:
         out["serving"] = serving(hom, args.serving, args.serving_rate, budget=64 << 30)
     if not args.no_cpu:

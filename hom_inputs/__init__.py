@@ -178,6 +178,93 @@ def inclusions(N, count, r, a_in, a_out=1.0, seed=3):
     return np.where(inside, a_in, a_out).astype(np.float64)
 
 
+# --------------------------------------------------------------------------
+# coefficients given by their Fourier coefficients: samples on the doubled
+# grid of the truncated series (unit cell [-1/2, 1/2)^d, A(x) = sum_k A^(k)
+# exp(2 pi i k.x), A^(k) = integral of A exp(-2 pi i k.x))
+# --------------------------------------------------------------------------
+
+def trig_samples(M, coef):
+    """Samples on the grid M (FFT order) of the trigonometric polynomial whose
+    coefficients coef (array over Z_M, FFT order) are given."""
+    M = tuple(M)
+    return (np.fft.ifftn(coef) * float(np.prod(M))).real
+
+
+def _interval_coef(k, half_width):
+    """Fourier coefficients of the indicator of [-w, w] on the unit period."""
+    k = np.asarray(k, dtype=np.float64)
+    safe = np.where(k == 0, 1.0, k)
+    return np.where(k == 0, 2.0 * half_width, np.sin(2.0 * np.pi * safe * half_width) / (np.pi * safe))
+
+
+def laminate_step_trig(N, width, a_in, a_out=1.0):
+    """Layer |x_1| < width/2 of a_in in a_out, as samples of its truncated
+    Fourier series on M = 2N-1 (volume fraction width exactly)."""
+    M = tuple(2 * n - 1 for n in N)
+    coef = np.zeros(M, dtype=complex)
+    k0 = signed_index(M[0])
+    line = (a_in - a_out) * _interval_coef(k0, 0.5 * width)
+    line[0] += a_out
+    coef[(slice(None),) + (0,) * (len(M) - 1)] = line
+    return trig_samples(M, coef)
+
+
+def square_inclusion_trig(N, half_width=0.25, a_in=10.0, a_out=1.0):
+    """Centred square / cube max |x_a| < half_width of a_in in a_out, as
+    samples of its truncated Fourier series on M = 2N-1 (a product of
+    sinc-type factors; volume fraction (2 half_width)^d exactly)."""
+    M = tuple(2 * n - 1 for n in N)
+    chi = np.ones(M)
+    for a, m in enumerate(M):
+        shape = [1] * len(M)
+        shape[a] = m
+        chi = chi * _interval_coef(signed_index(m), half_width).reshape(shape)
+    coef = (a_in - a_out) * chi.astype(complex)
+    coef[(0,) * len(M)] += a_out
+    return trig_samples(M, coef)
+
+
+def ball_coef(q, r, d):
+    """Fourier coefficient of the indicator of a disc (d = 2) or ball (d = 3)
+    of radius r at the origin, at wavenumber magnitude q (cycles per cell)."""
+    from scipy.special import j1
+    q = np.asarray(q, dtype=np.float64)
+    z = 2.0 * np.pi * q * r
+    zs = np.where(z == 0, 1.0, z)
+    if d == 2:
+        return np.where(z == 0, np.pi * r * r, 2.0 * np.pi * r * r * j1(zs) / zs)
+    return np.where(z == 0, 4.0 * np.pi * r ** 3 / 3.0,
+                    4.0 * np.pi * r ** 3 * (np.sin(zs) - zs * np.cos(zs)) / zs ** 3)
+
+
+def inclusions_trig(N, count, r, a_in, a_out=1.0, seed=3, centres=None):
+    """The discs / spheres of ``inclusions`` (same RSA centres) as samples of
+    the truncated Fourier series on M = 2N-1: A^(k) = a_out [k = 0] +
+    (a_in - a_out) B^(|k|) sum_c exp(-2 pi i k.c)."""
+    N = tuple(N)
+    d = len(N)
+    M = tuple(2 * n - 1 for n in N)
+    C = rsa_centres(d, count, r, seed) if centres is None else np.asarray(centres)
+    ks = [signed_index(m).astype(np.float64) for m in M]
+    phase = np.zeros(M, dtype=complex)
+    for c in C:
+        term = np.ones((1,) * d, dtype=complex)
+        for a in range(d):
+            shape = [1] * d
+            shape[a] = M[a]
+            term = term * np.exp(-2j * np.pi * ks[a] * (c[a] - 0.5)).reshape(shape)
+        phase += term
+    q2 = np.zeros(M)
+    for a in range(d):
+        shape = [1] * d
+        shape[a] = M[a]
+        q2 = q2 + (ks[a] ** 2).reshape(shape)
+    coef = (a_in - a_out) * ball_coef(np.sqrt(q2), r, d) * phase
+    coef[(0,) * d] += a_out
+    return trig_samples(M, coef)
+
+
 def gaussian_field(M, ell=0.1, sigma=1.5, seed=4):
     """Stationary Gaussian field on the periodic grid M by circulant embedding:
     lambda = DFT of the periodised covariance sigma^2 exp(-|r|^2 / (2 ell^2))

@@ -76,6 +76,17 @@ typedef struct {
                           replacements, default 1e-3 */
   int check_every;     /* iterations per captured graph between host checks, default 16 */
   void* stream;        /* hipStream_t the caller orders work against, or NULL */
+  int a_trig;          /* HOM_GA only, default 0.  1: the coefficient samples on the
+                          M = 2N-1 grid are those of a trigonometric polynomial of T_M,
+                          the truncated Fourier series P_M[A] of a coefficient A given
+                          by its Fourier coefficients (Sec. 4.2-4.3: exact integration
+                          for coefficients of known Fourier form).  The products of
+                          trial functions lie in T_M, so Ga is then the exact Galerkin
+                          method for A itself and A_H an upper bound of A's
+                          homogenized coefficient.  The samples may dip to or below 0
+                          near jumps (the bilinear form stays that of the SPD A): only
+                          finiteness is checked; rho_A reports +inf when some sample is
+                          not positive definite (hom_solve_ms then refuses the cell). */
 } hom_options;
 
 typedef struct {

@@ -34,6 +34,7 @@ __host__ __device__ constexpr int rounds_ch(int n, int NT, int cap = 8) {
 struct ColGen {
   static constexpr int NT = kThreads;
   static constexpr int CP = 1;   // components per transform call
+  static constexpr bool PRE = false;
   static constexpr int SL = 0;
   static constexpr int WC = 0;   // tile width when known at compile time
   static constexpr int NF = 0;   // FFT length when known at compile time
@@ -59,10 +60,14 @@ struct ColGen {
 // those accesses onto few LDS banks
 __host__ __device__ constexpr int odd_rowlen(int lw) { return (lw > 1 && lw % 2 == 0) ? lw + 1 : lw; }
 
-template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0, bool MF_ = false, int WPE_ = 1>
+template <class SP, int NTRIAL, int W_, int NT_, int SL_ = 0, bool MF_ = false, int WPE_ = 1,
+          bool PRE_ = false>
 struct ColStat {
   static constexpr int NT = NT_;
   static constexpr int CP = 1;
+  // projection pass: every component's tile loads go out before the first
+  // transform (held in registers), instead of one component at a time
+  static constexpr bool PRE = PRE_;
   static constexpr int SL = SL_;
   static constexpr int WC = W_;
   static constexpr int NF = SP::n;
@@ -91,6 +96,7 @@ template <class SP, int NTRIAL, int W_, int D_, int NT_, bool MF_ = false>
 struct ColStatCP {
   static constexpr int NT = NT_;
   static constexpr int CP = D_;
+  static constexpr bool PRE = false;
   static constexpr int WC = W_;
   static constexpr int NF = SP::n;
   static constexpr int WPE = 1;
@@ -506,7 +512,49 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
-  for (int al0 = 0; al0 < a.d; al0 += CPN) {
+  if constexpr (P::PRE) {
+    // 3-D cells, one component per transform, sizes known at compile time:
+    // all three tiles are loaded before the first transform
+    constexpr int NL = (P::NF * P::WC + NT - 1) / NT;
+    cpx<T> pre[3][NL];
+    const cpx<T>* X0 = a.X + (long)item * a.X_stride + col0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int f = min((int)threadIdx.x + u * NT, P::NF * P::WC - 1);
+        const int i = f / P::WC, w = f % P::WC;
+        pre[c][u] = X0[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int f = (int)threadIdx.x + u * NT;
+        if (f < P::NF * P::WC) {
+          const int i = f / P::WC, w = f % P::WC;
+          lds[i * LW + w] = (w < ncols) ? pre[c][u] : cpx<T>{T(0), T(0)};
+        }
+      }
+      __syncthreads();
+      P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
+#pragma unroll
+      for (int it = 0; it < PMAX; ++it) {
+        int i, w;
+        if (pos(it, i, w)) {
+          const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
+          const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
+          const cpx<T> v = lds[row * LW + w];
+          const T nvc = normal_comp<T>(a.g, kof(i, n_out), cx, c);
+          acc[it].x += nvc * v.x;
+          acc[it].y += nvc * v.y;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int al0 = 0; al0 < (P::PRE ? 0 : a.d); al0 += CPN) {
     constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
     in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(

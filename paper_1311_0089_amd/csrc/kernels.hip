@@ -47,8 +47,9 @@ std::vector<const StaticKernel*> static_variants(int kind, int esz, int n, int n
     // d: components the kernel is built for (0: any)
     if (k.kind != kind || k.esz != esz || k.n != n || k.ntrial != ntrial) continue;
     if (k.d != 0 && k.d != d) continue;
-    // static LDS of the block reductions sits on top of the dynamic size
-    if (k.lds + 1024 > g_static_max_lds) continue;
+    // the dynamic size a kernel may take (the device limit less 1 KiB for the
+    // static LDS of the block reductions)
+    if (k.lds > g_static_max_lds) continue;
     // the compile-time plan must describe the same tables the host uploaded
     if (k.len != p.len || k.blue != p.blue || k.nst != p.nst) continue;
     bool same = true;
@@ -795,7 +796,7 @@ hipError_t configure_kernels(size_t max_lds) {
   HOM_SET((k_row<double, RowGen, ROW_FWD>));
 #undef HOM_SET
   for (const StaticKernel& k : static_registry()) {
-    if (k.lds > max_lds) continue;  // never selected on this device (see find_static)
+    if (k.lds > max_lds) continue;  // never selected on this device (see static_variants)
     hipError_t e2 = hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)max_lds);
     if (e2 != hipSuccess) e = e2;

@@ -94,5 +94,13 @@ RegRow<T, P1023, 1023, 2, 1, 256, true> r1023_2nm4;
 RegColCP<T, P1023, 1023, 2, 2, 320, true> x1023_2m5;
 RegRow<T, P1023, 1023, 2, 1, 320, true> r1023_2nm5;
 RegRow<T, P1023, 1023, 2, 1, 384, true> r1023_2nm6;
+// wide tiles: longer contiguous runs along the last axis per row of the
+// axis-0 / axis-1 passes (fewer, larger workgroups)
+// projection with every component's tile loaded up front
+RegProjPre<T, P255, 255, 16, 256> p255pre;
+RegProjPre<T, P255, 255, 8, 256> p255pre8;
+RegProjPre<T, P253, 127, 16, 256> p253pre;
+// 16-column tiles with 512 threads: half the positions per thread
+RegCol<T, P255, 255, 16, 512> c255t512;
 }  // namespace
 }  // namespace hom

@@ -37,11 +37,14 @@ static hipError_t ensure_configured() {
   size_t mx = std::max(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
   if (mx < 64 * 1024) mx = 64 * 1024;
   if (mx > 160 * 1024) mx = 160 * 1024;
-  e = configure_kernels(mx);
+  // 1 KiB stays free for the static LDS of the block reductions: a dynamic
+  // size that would take a workgroup's whole LDS is refused for kernels
+  // that also hold static LDS
+  e = configure_kernels(mx - 1024);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     mx = 64 * 1024;
-    e = configure_kernels(mx);
+    e = configure_kernels(mx - 1024);
   }
   g_lds_max = mx - 1024;
   g_configured = (e == hipSuccess);
@@ -994,6 +997,7 @@ hom_status hom_options_default(hom_options* o) {
   o->inner_tol = 1e-3;
   o->check_every = 16;
   o->stream = nullptr;
+  o->a_trig = 0;
   return HOM_OK;
 }
 
@@ -1049,6 +1053,7 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   if (o.prec != HOM_FP64 && o.prec != HOM_MIXED) return HOM_EINVAL;
   if (o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1) return HOM_EINVAL;
   if (!(o.inner_tol > 0 && o.inner_tol < 1)) return HOM_EINVAL;
+  if (o.a_trig != 0 && (o.a_trig != 1 || o.scheme != HOM_GA)) return HOM_EINVAL;
   for (int a = 0; a < d; ++a) {
     if (N[a] < 1 || (N[a] % 2) == 0 || N[a] > (1 << 20)) return HOM_EINVAL;
     if (!(o.Y[a] > 0) || !std::isfinite(o.Y[a])) return HOM_EINVAL;
@@ -1123,18 +1128,21 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
       e = a_field_range(c->A64, d == 1 ? 1 : d, d == 1 ? HOM_A_ISO : kind, nQ, scratch,
                         (double*)hp, c->stream, &lo, &hi, &flags);
   }
-  if (e == hipSuccess && flags == 0) e = launch_convert(c->A64, c->A32, (long)nAd, c->stream);
+  // samples of a trigonometric polynomial (a_trig) need not be positive
+  // definite point by point, only finite
+  const int bad = o.a_trig ? (flags & 1) : flags;
+  if (e == hipSuccess && bad == 0) e = launch_convert(c->A64, c->A32, (long)nAd, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
     return dev_status(e);
   }
-  if (flags != 0) {
+  if (bad != 0) {
     pool_put(c);
     return (flags & 1) ? HOM_EINVAL : HOM_ENOTSPD;
   }
-  c->rhoA = hi / lo;
-  c->Alo = lo;
+  c->rhoA = (flags & 2) ? INFINITY : hi / lo;
+  c->Alo = (flags & 2) ? 0.0 : lo;
   c->Ahi = hi;
   hom_cell* hc = new (std::nothrow) hom_cell();
   if (!hc) {
@@ -1345,6 +1353,8 @@ hom_status hom_solve_ms(hom_cell* hc, int L, const double* E, double tol, double
   for (int i = 0; i < L * hc->impl->d; ++i)
     if (!std::isfinite(E[i])) return HOM_EINVAL;
   CellImpl* c = hc->impl;
+  // lambda = (c_A + C_A) / 2 needs a positive lower eigenvalue bound
+  if (!(c->Alo > 0.0)) return HOM_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess) e = ensure_work(c, L, false);

@@ -59,6 +59,18 @@ struct RegCol {
   }
 };
 
+// axis-0 projection of 3-D cells with every component's tile loaded before
+// the first transform (row-major scalars)
+template <class T, class SP, int NTRIAL, int W, int NT>
+struct RegProjPre {
+  static constexpr int PMAX = (NTRIAL * W + NT - 1) / NT;
+  static constexpr size_t lds = (size_t)SP::len * W * sizeof(cpx<T>);
+  RegProjPre() {
+    using P = ColStat<SP, NTRIAL, W, NT, 2, false, 1, true>;
+    RegCol<T, SP, NTRIAL, W, NT>::add(KK_PROJECT, (const void*)&k_col_project<T, P, PMAX>, 3, lds);
+  }
+};
+
 // axis-0 expand and project with all D components of a W-column tile in one
 // LDS tile and one transform call (matches cells with D device components)
 template <class T, class SP, int NTRIAL, int W, int D, int NT, bool MF = false>

@@ -478,3 +478,68 @@ def test_ms_iterations_linear_cg_sqrt_in_contrast(oracle):
         assert it_ms <= np.log(tol / np.sqrt(rho)) / np.log(q) + 2
     assert _loglog_slope(rhos, ms) > 0.75
     assert _loglog_slope(rhos, cg) < 0.5
+
+
+# ------------------------------- Ga with exact integration (Sec. 4.2-4.3)
+def test_ga_exact_laminate_step(oracle):
+    """A layer |x_1| < 0.15 of contrast 100 given by its Fourier coefficients:
+    Ga on the M-grid samples of the truncated series integrates A u.v exactly
+    (u.v lies in T_M), so the along-layer entry is the exact volume average
+    (vf 0.3, no voxel count) for every N, and the across-layer entry bounds
+    the exact harmonic mean from above and decreases as the nested trial
+    spaces grow (Cea).  The samples dip below 0 near the jumps; the form on
+    T_N is still that of the positive coefficient."""
+    harm = 1.0 / (0.3 / 100.0 + 0.7 / 1.0)
+    prev = np.inf
+    for n in (3, 5, 9, 17, 33):
+        N = (n, 3)
+        A = hi.laminate_step_trig(N, 0.3, 100.0, 1.0)
+        c = oracle.Cell(A, N, scheme=1)
+        _, W, _, _ = c.solve(np.eye(2), tol=1e-14)
+        np.testing.assert_allclose(W[1, 1], 1.0 + 99.0 * 0.3, rtol=1e-13)
+        assert abs(W[0, 1]) < 1e-11
+        assert W[0, 0] >= harm * (1 - 1e-12)
+        assert W[0, 0] < prev
+        prev = W[0, 0]
+    assert A.min() < 0.0
+    assert prev < 1.1 * harm
+
+
+def test_ga_exact_square_bounds(oracle):
+    """Centred square of vf 1/4 and contrast 100 by its Fourier coefficients:
+    W is symmetric under the square's symmetries (W_11 = W_22, W_12 = 0),
+    lies between the Reuss and Voigt means of the exact phases and
+    decreases with N (conforming and nested)."""
+    f, a1, a0 = 0.25, 100.0, 1.0
+    voigt, reuss = f * a1 + (1 - f) * a0, 1.0 / (f / a1 + (1 - f) / a0)
+    prev = np.inf
+    for n in (5, 9, 17):
+        A = hi.square_inclusion_trig((n, n), 0.25, a1, a0)
+        c = oracle.Cell(A, (n, n), scheme=1)
+        _, W, _, _ = c.solve(np.eye(2), tol=1e-14)
+        np.testing.assert_allclose(W[0, 0], W[1, 1], rtol=1e-12)
+        assert abs(W[0, 1]) < 1e-11 * W[0, 0]
+        assert reuss < W[0, 0] < voigt
+        assert W[0, 0] < prev
+        prev = W[0, 0]
+
+
+def test_ga_exact_sphere_above_hashin_shtrikman(oracle):
+    """A centred ball (r = 0.25, contrast 10) by its Fourier coefficients:
+    W is isotropic (cubic symmetry of the cell), decreases with N, and stays
+    above the Hashin-Shtrikman lower bound of the exact volume fraction,
+    which bounds the exact homogenized coefficient that Ga bounds from above."""
+    r, a1, a0 = 0.25, 10.0, 1.0
+    f = 4.0 / 3.0 * np.pi * r ** 3
+    hs = a0 + f / (1.0 / (a1 - a0) + (1.0 - f) / (3.0 * a0))
+    prev = np.inf
+    for n in (3, 5, 7):
+        N = (n, n, n)
+        A = hi.inclusions_trig(N, 1, r, a1, a0, centres=[[0.5, 0.5, 0.5]])
+        c = oracle.Cell(A, N, scheme=1)
+        _, W, _, _ = c.solve(np.eye(3), tol=1e-14)
+        np.testing.assert_allclose(np.diag(W), W[0, 0], rtol=1e-11)
+        assert np.abs(W - np.diag(np.diag(W))).max() < 1e-11 * W[0, 0]
+        assert W[0, 0] > hs
+        assert W[0, 0] < prev
+        prev = W[0, 0]
