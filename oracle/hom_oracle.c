@@ -165,8 +165,10 @@ static int to_real(int d, long np, const double* z, double* out) {
 }
 
 /* Apply Gamma^(k) = xi (x) xi / (xi . xi), Gamma^(0) = 0 (reference A0 = I),
- * in place on the complex vector spectrum z [d][N grid]. */
-static void project_fourier(int d, const long* N, const double* Y, double* z) {
+ * in place on the complex vector spectrum z [d][N grid]; with dual != 0 the
+ * complementary projection onto J_N, I - Gamma^(k) for k != 0 and 0 at k = 0
+ * (G + G_dual + mean = I, the discrete Helmholtz decomposition, Sec. 5.1). */
+static void project_fourier(int d, const long* N, const double* Y, double* z, int dual) {
     long np = prod(d, N);
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {
@@ -190,9 +192,25 @@ static void project_fourier(int d, const long* N, const double* Y, double* z) {
             sr += xi[a] * z[2 * ((long)a * np + p)];
             si += xi[a] * z[2 * ((long)a * np + p) + 1];
         }
+        if (!dual) {
+            for (int a = 0; a < d; ++a) {
+                z[2 * ((long)a * np + p)] = xi[a] * sr / xx;
+                z[2 * ((long)a * np + p) + 1] = xi[a] * si / xx;
+            }
+            continue;
+        }
+        /* (I - xi xi / xx) z as sum_b (xx delta_ab - xi_a xi_b) z_b / xx: a
+           field along an axis-aligned xi is removed exactly */
+        double orr[3] = {0, 0, 0}, oi[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                double m = ((a == b) ? xx : 0.0) - xi[a] * xi[b];
+                orr[a] += m * z[2 * ((long)b * np + p)];
+                oi[a] += m * z[2 * ((long)b * np + p) + 1];
+            }
         for (int a = 0; a < d; ++a) {
-            z[2 * ((long)a * np + p)] = xi[a] * sr / xx;
-            z[2 * ((long)a * np + p) + 1] = xi[a] * si / xx;
+            z[2 * ((long)a * np + p)] = orr[a] / xx;
+            z[2 * ((long)a * np + p) + 1] = oi[a] / xx;
         }
     }
 }
@@ -266,7 +284,7 @@ int hor_apply_G(const hor_cell* c, const double* u, double* out) {
     if (!z) return HOR_ENOMEM;
     int s = 0;
     for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, -1, z + 2 * (long)comp * np);
-    if (!s) project_fourier(d, c->N, c->Y, z);
+    if (!s) project_fourier(d, c->N, c->Y, z, c->dual);
     for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, +1, z + 2 * (long)comp * np);
     if (!s) s = to_real(d, np, z, out);
     free(z);
@@ -314,7 +332,7 @@ int hor_apply_GA(const hor_cell* c, const double* u, double* out) {
     if (!s) {
         if (c->scheme == HOR_GA) trunc_spectrum(d, c->N, c->Q, zq, zn);
         else memcpy(zn, zq, sizeof(double) * 2 * (size_t)d * (size_t)nN);
-        project_fourier(d, c->N, c->Y, zn);
+        project_fourier(d, c->N, c->Y, zn, c->dual);
     }
     for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, +1, zn + 2 * (long)comp * nN);
     if (!s) s = to_real(d, nN, zn, out);

@@ -44,7 +44,11 @@ typedef struct {
     int d;            /* 1, 2 or 3 */
     int scheme;       /* HOR_GANI: A on the N grid; HOR_GA: A on the 2N-1 grid */
     int kind;         /* HOR_ISO / HOR_DIAG / HOR_FULLSYM */
-    int reserved;
+    int dual;         /* 0: the primal problem on E_N (gradients); 1: the dual
+                         problem on J_N (zero-mean divergence-free fields, the
+                         other part of the discrete Helmholtz decomposition of
+                         Sec. 5.1), A then being the resistivity; the projection
+                         becomes I - xi xi / |xi|^2 for k != 0 and 0 at k = 0 */
     long N[3];        /* trial grid (odd) */
     long Q[3];        /* quadrature grid: N (GaNi) or 2N-1 (Ga) */
     double Y[3];      /* cell half-lengths */

@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
 
 class _Cell(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("scheme", ctypes.c_int), ("kind", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("N", ctypes.c_long * 3), ("Q", ctypes.c_long * 3),
+                ("dual", ctypes.c_int), ("N", ctypes.c_long * 3), ("Q", ctypes.c_long * 3),
                 ("Y", ctypes.c_double * 3), ("A", ctypes.POINTER(ctypes.c_double))]
 
 
@@ -94,7 +94,8 @@ class Cell:
     """A periodic cell: trial grid N (odd), coefficient field A on the
     quadrature grid Q (N for GaNi, 2N-1 for Ga) and half-lengths Y."""
 
-    def __init__(self, A: np.ndarray, N, kind: int = ISO, scheme: int = GANI, Y=None):
+    def __init__(self, A: np.ndarray, N, kind: int = ISO, scheme: int = GANI, Y=None,
+                 dual: bool = False):
         N = tuple(int(n) for n in N)
         d = len(N)
         Q = tuple(2 * n - 1 for n in N) if scheme == GA else N
@@ -107,6 +108,7 @@ class Cell:
         self.Y = tuple(Y) if Y is not None else (0.5,) * d
         c = _Cell()
         c.d, c.scheme, c.kind = d, scheme, kind
+        c.dual = 1 if dual else 0
         for a in range(3):
             c.N[a] = N[a] if a < d else 1
             c.Q[a] = Q[a] if a < d else 1

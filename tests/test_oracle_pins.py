@@ -543,3 +543,56 @@ def test_ga_exact_sphere_above_hashin_shtrikman(oracle):
         assert W[0, 0] > hs
         assert W[0, 0] < prev
         prev = W[0, 0]
+
+
+# ------------------------- dual (flux) formulation on J_N (Sec. 5.1, Sec. 6)
+@pytest.mark.parametrize("N", [(9, 7), (5, 7, 3)])
+def test_dual_projection_helmholtz(oracle, N):
+    """The discrete Helmholtz decomposition (Sec. 5.1): G u + G_dual u +
+    mean(u) = u; G_dual is idempotent, orthogonal to G, and its output is
+    divergence-free (xi . j^ = 0) with zero mean."""
+    d = len(N)
+    cp = oracle.Cell(np.ones(N), N)
+    cd = oracle.Cell(np.ones(N), N, dual=True)
+    u = rand_field((d,) + N, 21)
+    v = rand_field((d,) + N, 22)
+    Gu, Du = cp.apply_G(u), cd.apply_G(u)
+    mean = u.reshape(d, -1).mean(axis=1).reshape((d,) + (1,) * d)
+    np.testing.assert_allclose(Gu + Du + mean, u, atol=1e-13)
+    np.testing.assert_allclose(cd.apply_G(Du), Du, atol=1e-13)
+    assert abs(np.mean(Du * cp.apply_G(v))) < 1e-14
+    ks = np.meshgrid(*[hi.signed_index(n) for n in N], indexing="ij")
+    div = sum(2.0 * ks[a] * np.fft.fftn(Du[a]) for a in range(d))
+    assert np.abs(div).max() < 1e-11 * np.abs(np.fft.fftn(Du[0])).max()
+
+
+@pytest.mark.parametrize("N", [(15, 7), (9, 5, 7)])
+def test_dual_laminate_closed_form(oracle, N):
+    """Dual problem with the resistivity B = 1/a(x_1) of a laminate: the flux
+    along x_1 must be constant and across it is free, so the dual energy is
+    diag(<1/a>, 1/<a>, ...) and its inverse the primal closed form."""
+    d = len(N)
+    a = 1.0 + 50.0 * hi.uniform(31, N[0])
+    c = oracle.Cell(hi.laminate(N, 1.0 / a), N, dual=True)
+    _, W, _, _ = c.solve(np.eye(d), tol=1e-14)
+    ref = np.diag([np.mean(1.0 / a)] + [1.0 / np.mean(a)] * (d - 1))
+    np.testing.assert_allclose(W, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_dual_two_sided_bounds_exact_square(oracle):
+    """Ga with both coefficients integrated exactly (Fourier-given square of
+    contrast 20: A for the primal, B = A^-1 for the dual): the primal energy
+    bounds A_H from above and the inverse of the dual energy from below
+    (Sec. 6), and the gap shrinks as the nested trial spaces grow."""
+    a1, a0 = 20.0, 1.0
+    gaps = []
+    for n in (5, 9, 17):
+        N = (n, n)
+        A = hi.square_inclusion_trig(N, 0.25, a1, a0)
+        B = hi.square_inclusion_trig(N, 0.25, 1.0 / a1, 1.0 / a0)
+        _, Wp, _, _ = oracle.Cell(A, N, scheme=1).solve(np.eye(2), tol=1e-14)
+        _, Wd, _, _ = oracle.Cell(B, N, scheme=1, dual=True).solve(np.eye(2), tol=1e-14)
+        lower = np.linalg.inv(Wd)
+        assert np.linalg.eigvalsh(Wp - lower).min() > 0
+        gaps.append(Wp[0, 0] - lower[0, 0])
+    assert gaps[2] < gaps[1] < gaps[0]
