@@ -63,6 +63,9 @@ def parse():
                     help="CG and Moulinec-Suquet steps and times against the contrast")
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving stream")
     ap.add_argument("--serving-rate", type=float, default=500.0)
+    ap.add_argument("--serving-fp64", action="store_true",
+                    help="also solve the 1-in-50 sample one request at a time, plain FP64 "
+                         "and mixed, for comparison with the served form")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="mixed path: fall of the FP32 recursive residual between FP64 "
                          "residual replacements (library default if omitted)")
@@ -261,9 +264,11 @@ def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
     return out
 
 
-def serving(hom, n_req, rate, budget):
+def serving(hom, n_req, rate, budget, prec_name="mixed"):
     """Submit n_req requests of the seeded stream at their Poisson arrival
-    times; report served rate and p50/p99 latency (submit -> done)."""
+    times; report served rate and p50/p99 latency (submit -> done), and the
+    A_H error of the requests whose oracle result is stored
+    (tests/golden/serving_samples.json, every 50th request)."""
     import hom_inputs as hi
     reqs = hi.serving_stream(n_req, rate=rate, seed=5, geometry_pool=16)
     kinds = {}
@@ -279,7 +284,8 @@ def serving(hom, n_req, rate, budget):
             cache[key] = r.field() > 1.0
         fields.append(np.where(cache[key], r.contrast, 1.0))
     log(f"serving: {len(reqs)} requests, {len(cache)} distinct geometries")
-    srv = hom.Server(hbm_budget_bytes=budget, prec=hom.MIXED, check_every=8)
+    prec = hom.MIXED if prec_name == "mixed" else hom.FP64
+    srv = hom.Server(hbm_budget_bytes=budget, prec=prec, check_every=8)
     cells = [None] * len(reqs)
     tickets = {}
     done = {}
@@ -302,18 +308,37 @@ def serving(hom, n_req, rate, budget):
     for i, r in enumerate(reqs):
         while time.perf_counter() - t0 < r.arrival:
             time.sleep(0.0002)
-        c = hom.Cell(fields[i], r.N, prec=hom.MIXED)
+        c = hom.Cell(fields[i], r.N, prec=prec)
         fields[i] = None
         cells[i] = c
         tickets[i] = (srv.submit(c, r.E, tol=r.tol), r.E.shape[0], r.d)
         if (i + 1) % 1000 == 0:
             log(f"serving: {i + 1} submitted, {len(done)} done")
-    th.join(timeout=600)
+    t_join = time.perf_counter()
+    while th.is_alive() and time.perf_counter() - t_join < 600:
+        th.join(timeout=10)
+        log(f"serving: {len(done)} of {len(reqs)} done")
     t_end = time.perf_counter() - t0
     srv.close()
     lat = np.array([(done[i]["times"][2] - done[i]["times"][0]) * 1e3 for i in done])
     ok = sum(1 for v in done.values() if v["status"] == 0)
-    return {"requests": len(reqs), "completed": len(done), "ok": ok,
+    parity = None
+    gpath = os.path.join(ROOT, "tests", "golden", "serving_samples.json")
+    if os.path.exists(gpath):
+        with open(gpath) as fh:
+            gold = {q["idx"]: q for q in json.load(fh)["requests"]}
+        errs = []
+        for i, q in gold.items():
+            if i < len(reqs) and i in done:
+                W = np.asarray(q["W"])
+                errs.append(float(np.abs(done[i]["W"] - W).max() / np.abs(W).max()))
+        if errs:
+            parity = {"checked": len(errs), "of_sampled": len(gold),
+                      "A_H_rel_err_max": max(errs), "A_H_rel_err_median": float(np.median(errs)),
+                      "above_1e-6": int(sum(e > 1e-6 for e in errs)),
+                      "reference": "FP64 oracle at tol 1e-10 (tests/golden/serving_samples.json)"}
+    return {"requests": len(reqs), "completed": len(done), "ok": ok, "precision": prec_name,
+            "oracle_parity": parity,
             "offered_rate_per_s": len(reqs) / reqs[-1].arrival,
             "served_solves_per_s": len(done) / t_end, "wall_s": t_end,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -365,6 +390,39 @@ def ms_experiment(hom, n=255, rhos=(10.0, 100.0, 1000.0, 10000.0), tol=1e-6):
     return {"grid": [n, n], "tol": tol, "precision": "fp64", "rows": rows,
             "slope_cg": float(np.polyfit(lr, np.log([r["cg_steps"] for r in rows]), 1)[0]),
             "slope_ms": float(np.polyfit(lr, np.log([r["ms_steps"] for r in rows]), 1)[0])}
+
+
+def solve_sample_alone(hom, n_req):
+    """Every 50th request of the stream solved one at a time (no server), in
+    plain FP64 and in the mixed form, at the request's tolerance: solves/s of
+    each and the A_H error against the stored oracle results."""
+    import hom_inputs as hi
+    reqs = hi.serving_stream(n_req, rate=500.0, seed=5, geometry_pool=16)[::50]
+    gold = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "serving_samples.json")
+    if os.path.exists(gpath):
+        with open(gpath) as fh:
+            gold = {q["idx"]: np.asarray(q["W"]) for q in json.load(fh)["requests"]}
+    fields = [r.field() for r in reqs]
+    out = {}
+    for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):
+        errs = []
+        t_all = 0.0
+        for r, A in zip(reqs, fields):
+            t0 = time.perf_counter()
+            c = hom.Cell(A, r.N, prec=prec)
+            res = c.solve(r.E, tol=r.tol)
+            c.close()
+            t_all += time.perf_counter() - t0
+            if r.idx in gold:
+                W = gold[r.idx]
+                errs.append(float(np.abs(res["W"] - W).max() / np.abs(W).max()))
+        out[name] = {"requests": len(reqs), "seconds": t_all, "solves_per_s": len(reqs) / t_all,
+                     "oracle_checked": len(errs),
+                     "A_H_rel_err_max": max(errs) if errs else None,
+                     "A_H_rel_err_median": float(np.median(errs)) if errs else None}
+        log(f"sample alone {name}: {len(reqs)} solves in {t_all:.1f} s")
+    return out
 
 
 def config_of(w, args):
@@ -453,6 +511,8 @@ def main():
         out["ms_vs_cg"] = ms_experiment(hom)
     if args.serving:
         out["serving"] = serving(hom, args.serving, args.serving_rate, budget=64 << 30)
+        if args.serving_fp64:
+            out["sample_solved_alone"] = solve_sample_alone(hom, args.serving)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -87,6 +87,16 @@ typedef struct {
                           near jumps (the bilinear form stays that of the SPD A): only
                           finiteness is checked; rho_A reports +inf when some sample is
                           not positive definite (hom_solve_ms then refuses the cell). */
+  int dual;            /* d = 2 only, default 0.  1: the dual (flux) problem: find the
+                          zero-mean divergence-free trigonometric field j~ of J_N (the
+                          other part of the discrete Helmholtz decomposition, Sec. 5.1)
+                          minimising <(E + j~) . A (E + j~)>, with A the resistivity
+                          (the inverse of the conductivity) and E the mean flux; W is
+                          then the dual energy, whose inverse (Ga with exactly
+                          integrated resistivity, a_trig) bounds the homogenized
+                          conductivity from below while the primal Ga bounds it from
+                          above (Sec. 6).  Implemented with the rotated normal
+                          t = (-xi_2, xi_1)/|xi| in place of xi/|xi|. */
 } hom_options;
 
 typedef struct {
@@ -231,7 +241,7 @@ hom_status hom_cell_dims(const hom_cell* c, int32_t* d, int32_t* N, int32_t* Q);
 hom_status hom_server_create(size_t hbm_budget_bytes, const hom_options* opt, hom_server** out);
 /* Queue one request on cell c (the cell must outlive the request).  E [L][d]
  * host, copied.  *ticket receives its id.  HOM_ENOMEM if the request alone
- * exceeds the budget. */
+ * exceeds the budget; HOM_EINVAL for more than d load cases or a dual cell. */
 hom_status hom_server_submit(hom_server* s, hom_cell* c, int L, const double* E, double tol,
                              uint64_t* ticket);
 /* HOM_EBUSY until the request is done; then its status, W [L][L], J [L][d]

@@ -184,6 +184,9 @@ __device__ __forceinline__ T normal_comp(const NormalGeo& g, int k0, const ColXi
   const T xi0 = T(k0) * T(g.invY[0]);
   const T s = xi0 * xi0 + cx.c;
   const T inv = s > T(0) ? inv_sqrt(s) : T(0);
+  // dual (2-D): the divergence-free fields of frequency k are the multiples of
+  // t = (-xi_1, xi_0) / |xi|, the primal ones of n = xi / |xi|
+  if (g.dual) return (comp == 0 ? -cx.x1 : xi0) * inv;
   return (comp == 0 ? xi0 : comp == 1 ? cx.x1 : cx.x2) * inv;
 }
 

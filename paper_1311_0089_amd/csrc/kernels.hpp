@@ -80,6 +80,7 @@ struct NormalGeo {
   int d;
   int N1;        // trial size of axis 1 (3-D only)
   int H;         // half-spectrum bins of the last axis
+  int dual;      // 2-D dual problem: the rotated normal t = (-n_1, n_0) spans J_N
   double invY[3];
 };
 

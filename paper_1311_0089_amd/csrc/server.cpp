@@ -518,6 +518,7 @@ hom_status hom_server_submit(hom_server* s, hom_cell* c, int L, const double* E,
   if (!s || !c || !E || !ticket || L < 1 || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
   CellImpl* cell = c->impl;
   if (L > cell->dd) return HOM_EINVAL;  // a slot holds at most d load cases
+  if (cell->dual) return HOM_EINVAL;    // size classes batch primal cells only
   for (int i = 0; i < L * cell->d; ++i)
     if (!std::isfinite(E[i])) return HOM_EINVAL;
   if (cell->device != s->device) return HOM_EINVAL;

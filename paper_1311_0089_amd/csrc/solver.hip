@@ -232,6 +232,7 @@ static NormalGeo normal_geo(const CellImpl* c) {
   g.d = c->dd;
   g.N1 = (c->dd == 3) ? c->N[1] : 1;
   g.H = c->H;
+  g.dual = c->dual;
   for (int a = 0; a < 3; ++a) g.invY[a] = 1.0 / c->Y[a];
   return g;
 }
@@ -925,7 +926,9 @@ static std::vector<CellImpl*> g_pool;
 static const size_t kPoolMax = 4;
 
 static bool same_shape(const CellImpl* a, const CellImpl& b) {
-  if (a->dd != b.dd || a->scheme != b.scheme || a->kind != b.kind || a->nA != b.nA) return false;
+  if (a->dd != b.dd || a->scheme != b.scheme || a->kind != b.kind || a->nA != b.nA ||
+      a->dual != b.dual)
+    return false;
   for (int i = 0; i < 3; ++i)
     if (a->N[i] != b.N[i] || a->Q[i] != b.Q[i] || a->Y[i] != b.Y[i]) return false;
   return true;
@@ -998,6 +1001,7 @@ hom_status hom_options_default(hom_options* o) {
   o->check_every = 16;
   o->stream = nullptr;
   o->a_trig = 0;
+  o->dual = 0;
   return HOM_OK;
 }
 
@@ -1054,6 +1058,7 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   if (o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1) return HOM_EINVAL;
   if (!(o.inner_tol > 0 && o.inner_tol < 1)) return HOM_EINVAL;
   if (o.a_trig != 0 && (o.a_trig != 1 || o.scheme != HOM_GA)) return HOM_EINVAL;
+  if (o.dual != 0 && (o.dual != 1 || d != 2)) return HOM_EINVAL;
   for (int a = 0; a < d; ++a) {
     if (N[a] < 1 || (N[a] % 2) == 0 || N[a] > (1 << 20)) return HOM_EINVAL;
     if (!(o.Y[a] > 0) || !std::isfinite(o.Y[a])) return HOM_EINVAL;
@@ -1063,6 +1068,7 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   key.d = d;
   key.dd = d < 2 ? 2 : d;
   key.scheme = o.scheme;
+  key.dual = o.dual;
   const int nA_user = (kind == HOM_A_ISO) ? 1 : (kind == HOM_A_DIAG) ? d : d * (d + 1) / 2;
   // d = 1 runs as a 2-D cell with a single grid point along the second axis;
   // its one coefficient acts as an isotropic one (e_2 vanishes identically)
@@ -1086,6 +1092,7 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
     c->d = key.d;
     c->dd = key.dd;
     c->scheme = key.scheme;
+    c->dual = key.dual;
     c->kind = key.kind;
     c->nA = key.nA;
     for (int a = 0; a < 3; ++a) {

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("prec", ctypes.c_int), ("Y", ctypes.c_double * 3),
                 ("max_iter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("a_trig", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("a_trig", ctypes.c_int), ("dual", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -127,7 +127,7 @@ def tune_load(path: str) -> bool:
 
 
 def make_options(scheme=GANI, prec=FP64, Y=None, max_iter=10000, max_outer=100, inner_tol=1e-3,
-                 check_every=16, stream=None, a_trig=False) -> Options:
+                 check_every=16, stream=None, a_trig=False, dual=False) -> Options:
     o = Options()
     lib().hom_options_default(ctypes.byref(o))
     o.scheme, o.prec = scheme, prec
@@ -137,6 +137,7 @@ def make_options(scheme=GANI, prec=FP64, Y=None, max_iter=10000, max_outer=100, 
     o.max_iter, o.max_outer, o.inner_tol, o.check_every = max_iter, max_outer, inner_tol, check_every
     o.stream = stream
     o.a_trig = 1 if a_trig else 0
+    o.dual = 1 if dual else 0
     return o
 
 
@@ -148,7 +149,7 @@ class Cell:
     scheme: GANI (A on N) or GA (A on 2N-1); prec: FP64 or MIXED."""
 
     def __init__(self, A, N, kind=ISO, scheme=GANI, prec=FP64, Y=None, max_iter=10000,
-                 max_outer=100, inner_tol=1e-3, check_every=16, a_trig=False):
+                 max_outer=100, inner_tol=1e-3, check_every=16, a_trig=False, dual=False):
         import torch
         self.N = tuple(int(n) for n in N)
         self.d = len(self.N)
@@ -156,7 +157,7 @@ class Cell:
         self.kind, self.scheme, self.prec = kind, scheme, prec
         self._h = ctypes.c_void_p(None)
         o = make_options(scheme, prec, Y, max_iter, max_outer, inner_tol, check_every,
-                         _current_stream(), a_trig)
+                         _current_stream(), a_trig, dual)
         Nc = (ctypes.c_int32 * 3)(*(list(self.N) + [1] * (3 - self.d)))
         if isinstance(A, torch.Tensor) and A.is_cuda:
             At = A.to(torch.float64).contiguous()

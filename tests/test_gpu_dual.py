@@ -1,0 +1,90 @@
+"""The dual (flux) formulation on the GPU (2-D, the dual option): parity with
+the oracle's dual problem (the projection onto the divergence-free fields of
+J_N, Sec. 5.1), the laminate closed form, and the two-sided bounds of Ga with
+exactly integrated coefficient and resistivity (Sec. 6)."""
+import numpy as np
+import pytest
+
+import hom_inputs as hi
+
+gpu = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def hom():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1311_0089_amd as h
+    h.lib()
+    return h
+
+
+@gpu
+@pytest.mark.parametrize("N,kind,scheme", [((15, 13), 0, 0), ((31, 29), 2, 0), ((9, 11), 1, 1),
+                                           ((63, 63), 0, 0)])
+def test_dual_matches_oracle(hom, oracle, N, kind, scheme):
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    B = hi.random_spd_field(Q, kind, seed=131 + kind, contrast=50.0)
+    ocell = oracle.Cell(B, N, kind=kind, scheme=scheme, dual=True)
+    x, W, J, _ = ocell.solve(np.eye(2), tol=1e-13)
+    g = hom.Cell(B, N, kind=kind, scheme=scheme, dual=True)
+    r = g.solve(np.eye(2), tol=1e-13, want_strain=True)
+    assert rel(r["W"], W) < 1e-10
+    assert rel(r["strain"].cpu().numpy(), x + np.eye(2)[:, :, None, None]) < 1e-10
+    m = hom.Cell(B, N, kind=kind, scheme=scheme, dual=True, prec=hom.MIXED)
+    assert rel(m.solve(np.eye(2), tol=1e-8)["W"], W) < 1e-6
+    # the operator: one apply of the dual G B G against the oracle's
+    import torch
+    u = np.stack([ocell.apply_G(hi.normal(140 + l, 2 * int(np.prod(N))).reshape((2,) + N))
+                  for l in range(2)])
+    ref = np.stack([ocell.apply_GA(u[l]) for l in range(2)])
+    out = g.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    assert rel(out, ref) < 1e-13
+
+
+@gpu
+def test_dual_laminate_closed_form(hom):
+    N = (255, 127)
+    a = 1.0 + 99.0 * hi.uniform(5, N[0])
+    g = hom.Cell(hi.laminate(N, 1.0 / a), N, dual=True)
+    W = g.solve(np.eye(2), tol=1e-12)["W"]
+    ref = np.diag([np.mean(1.0 / a), 1.0 / np.mean(a)])
+    assert np.abs(W - ref).max() / ref.max() < 1e-10
+
+
+@gpu
+def test_two_sided_bounds_exact_square(hom):
+    """Centred square of vf 1/4, contrast 100, given by its Fourier series:
+    primal Ga (coefficient) above, the inverse of dual Ga (resistivity) below,
+    the gap shrinking from N = 31 to 63 to 127."""
+    a1, a0 = 100.0, 1.0
+    gaps = []
+    for n in (31, 63, 127):
+        N = (n, n)
+        A = hi.square_inclusion_trig(N, 0.25, a1, a0)
+        B = hi.square_inclusion_trig(N, 0.25, 1.0 / a1, 1.0 / a0)
+        Wp = hom.Cell(A, N, scheme=hom.GA, a_trig=True).solve(np.eye(2), tol=1e-10)["W"]
+        Wd = hom.Cell(B, N, scheme=hom.GA, a_trig=True, dual=True).solve(np.eye(2),
+                                                                          tol=1e-10)["W"]
+        lower = np.linalg.inv(Wd)
+        assert np.linalg.eigvalsh(Wp - lower).min() > 0
+        gaps.append(Wp[0, 0] - lower[0, 0])
+    assert gaps[2] < gaps[1] < gaps[0]
+
+
+@gpu
+def test_dual_rejected_in_3d_and_by_the_server(hom):
+    with pytest.raises(hom.HomError):
+        hom.Cell(np.ones((5, 5, 5)), (5, 5, 5), dual=True)
+    srv = hom.Server(1 << 30)
+    c = hom.Cell(np.ones((15, 15)), (15, 15), dual=True, prec=hom.MIXED)
+    with pytest.raises(hom.HomError):
+        srv.submit(c, np.eye(2))
+    srv.close()

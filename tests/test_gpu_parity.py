@@ -436,3 +436,45 @@ def test_cell_half_lengths(hom, oracle, torch_cuda, N, Y):
     assert rel(r["W"], W) < 1e-10
     ref = x + np.eye(d).reshape((d, d) + (1,) * d)
     assert rel(r["strain"].cpu().numpy(), ref) < 1e-10
+
+
+@gpu
+def test_autotune_and_cache_round_trip(hom, oracle, torch_cuda, tmp_path):
+    """hom_autotune times every variant of every pass inside whole CG
+    iterations and keeps the fastest; the result still matches the oracle,
+    and hom_tune_save / hom_tune_load restore the same choices (a cache from
+    another architecture is refused)."""
+    torch = torch_cuda
+    N = (15, 15, 255)
+    A = hi.random_spd_field(N, 0, seed=141, contrast=30.0)
+    g = hom.Cell(A, N, prec=hom.MIXED)
+    counts = g.pass_variants(hom.MIXED)
+    before = [g.current_variant(p, prec=hom.MIXED) if counts[p] else None for p in range(5)]
+    best = g.autotune(prec=hom.MIXED, L=2, reps=3)
+    assert all(b > 0 for b in best)
+    chosen = [g.current_variant(p, prec=hom.MIXED) if counts[p] else None for p in range(5)]
+    path = str(tmp_path / "tune.json")
+    hom.tune_save(path)
+    # scramble, then load: the saved choices come back
+    for p in range(5):
+        if counts[p]:
+            g.force_variant(p, (chosen[p] + 1) % counts[p] if chosen[p] >= 0 else 0, prec=hom.MIXED)
+    assert hom.tune_load(path)
+    assert [g.current_variant(p, prec=hom.MIXED) if counts[p] else None for p in range(5)] == chosen
+    ocell = oracle.Cell(A, N)
+    u = np.stack([ocell.apply_G(rand_field((3,) + N, 150 + l)) for l in range(2)])
+    ref = np.stack([ocell.apply_GA(u[l]) for l in range(2)])
+    out = g.apply(torch.from_numpy(u).cuda(), prec=hom.MIXED).cpu().numpy()
+    assert rel(out, ref) < FP32_OP
+    import json
+    with open(path) as fh:
+        d = json.load(fh)
+    d["arch"] = "gfx000"
+    other = str(tmp_path / "other.json")
+    with open(other, "w") as fh:
+        json.dump(d, fh)
+    assert not hom.tune_load(other)
+    # leave the process with the committed choices
+    for p in range(5):
+        if counts[p] and before[p] is not None:
+            g.force_variant(p, before[p], prec=hom.MIXED)
