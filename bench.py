@@ -243,11 +243,12 @@ def measure(hom, w, prec, steps, warmup, ref=True, inner_tol=None):
     out["operator"] = {"model_bytes": op_model, "us": op_ms * 1e3,
                        "GBps": op_model / (op_ms * 1e-3) / 1e9,
                        "frac": op_model / (op_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    # the CG vectors the passes stream besides the model (fused CG steps in
-    # the expansion and projection, the update kernel), reported on their own
-    cg_bytes = sum(prof[k]["bytes"] for k in PASSES if prof[k]["ms"] > 0) - op_model
-    cg_bytes += prof["update"]["bytes"]
+    # the CG vectors streamed besides the operator's passes (the direction
+    # step, the update, p read by the projection for (p, q)), on their own
+    s_bytes = prof["update"]["bytes"] / 3.0          # one scalar spectrum, all items
+    cg_bytes = prof["direction"]["bytes"] + prof["update"]["bytes"] + s_bytes
     out["cg_vectors"] = {"bytes_per_iteration": cg_bytes,
+                         "direction_us": prof["direction"]["ms"] * 1e3,
                          "update_us": prof["update"]["ms"] * 1e3}
     # measured HBM bytes per launch of the dominant kernel, from the committed
     # counter summary of this workload while the kernel sources are unchanged

@@ -182,16 +182,16 @@ hom_status hom_project(hom_cell* c, int L, const double* u, double* out);
 hom_status hom_apply_noalloc(hom_cell* c, hom_prec prec, int L, const double* u, double* out);
 
 /* Time the kernels of reps consecutive CG iterations on L load cases (HIP
- * events recorded by each dispatch, on the cell's stream).  ms[0..7]
- * receives the mean duration per launch of: axis-0 expand (with p <- r +
- * beta p and the x += alpha p the previous update left to it), axis-1
- * inverse, last-axis flux pass, axis-1 forward, axis-0 project (with the
- * bookkeeping of the last update), CG update (with alpha; r only, x in the
- * last iteration of a launch), the end-of-launch bookkeeping per iteration
- * (one per launch of 16 iterations); ms[7] the sum, one iteration.
- * bytes[0..7] receives the algorithmic HBM bytes of the same launches in
- * the steady state of a launch (each input read once, each output written
- * once). */
+ * events recorded by each dispatch, on the cell's stream).  ms[0..8]
+ * receives the mean duration per launch of: axis-0 expand, axis-1 inverse,
+ * last-axis flux pass, axis-1 forward, axis-0 project (with the bookkeeping
+ * of the last update), CG update (with alpha; r only, x in the last
+ * iteration of a launch), the end-of-launch bookkeeping per iteration (one
+ * per launch of 16 iterations), ms[7] the sum, one iteration, and ms[8] the
+ * direction step (beta, the stopping test, x += alpha p left by the last
+ * update, p <- r + beta p).  bytes[0..8] receives the algorithmic HBM bytes
+ * of the same launches in the steady state of a launch (each input read
+ * once, each output written once). */
 hom_status hom_profile_iteration(hom_cell* c, hom_prec prec, int L, int reps, double* ms,
                                  double* bytes);
 

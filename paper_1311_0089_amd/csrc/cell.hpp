@@ -113,7 +113,7 @@ template <class T>
 hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemScal* sc);
 // q = Op(in) with epilogue epi
 template <class T>
-hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse, int epi,
+hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int epi,
                       cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
                       double* partials, const CgFuse* cg = nullptr);
 // real strain on grid G (G = N or Q) from the potential: e = E + F_G^-1 Pad(n c)

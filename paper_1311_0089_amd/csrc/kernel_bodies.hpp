@@ -295,8 +295,8 @@ __device__ __forceinline__ bool cg_stops(const ItemScal& q, double s) {
 }
 
 // ---------------------------------------------------------------------------
-// axis 0 from the scalar potential (optionally fusing p <- r + beta p):
-// X_a = F_0^-1 Pad(n_a c) for every component a
+// axis 0 from the scalar potential: X_a = F_0^-1 Pad(n_a c) for every
+// component a
 // ---------------------------------------------------------------------------
 template <class T, class P, int PMAX>
 __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a) {
@@ -319,69 +319,19 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
     w = colm ? f / n_in : f % W;
     return f < npos;
   };
-  // every load of the fill goes out before the stopping test and beta are
-  // derived from the partials, behind the first loads of those partials
-  // (unconditional: positions outside the tile read an element inside it again)
-  const bool derive = a.fuse && a.rr_part && !a.sc[item].fresh;
-  const bool xd = a.fuse && a.xdef;
-  const double* rr = a.rr_part + (long)item * a.P;
-  double ph[8];
-  if (derive) partials_head(rr, a.rr_n, ph);
-  cpx<T> rv[PMAX], pv[PMAX], xv[PMAX];
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    int i, w;
-    pos(it, i, w);
-    const long idx = ibase + (long)min(i, n_in - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_;
-    if (a.fuse) {
-      rv[it] = a.r[idx];
-      pv[it] = a.p[idx];
-      if (xd) xv[it] = a.x[idx];
-    } else {
-      rv[it] = a.c[idx];
-    }
-  }
-  // the update deferred by the last CG step: x += alpha p with the old p
-  auto x_update = [&]() __attribute__((always_inline)) {
-    const T alpha = T(a.sc[item].alpha);
-#pragma unroll
-    for (int it = 0; it < PMAX; ++it) {
-      int i, w;
-      if (pos(it, i, w) && w < ncols) {
-        cpx<T> x = xv[it];
-        x.x += alpha * pv[it].x;
-        x.y += alpha * pv[it].y;
-        a.x[ibase + (long)i * a.si + (long)(col0 + w) * a.sc_] = x;
-      }
-    }
-  };
-  T beta = a.fuse ? T(a.sc[item].beta) : T(0);
-  if (derive) {
-    // s = (r, r) of the last update; its bookkeeping runs in the projection
-    const double s = partials_finish(rr, a.rr_n, ph);
-    const ItemScal q = a.sc[item];
-    if (cg_stops(q, s)) {
-      if (xd) x_update();
-      return;
-    }
-    beta = T(s / q.rho);
-  }
-  if (xd) x_update();
+  // every load goes out first (unconditional: positions outside the tile read
+  // an element inside it again); positions outside the tile contribute 0
   cpx<T> s[PMAX];
 #pragma unroll
   for (int it = 0; it < PMAX; ++it) {
     int i, w;
-    const bool in = pos(it, i, w);
-    s[it] = (in && w < ncols) ? rv[it] : cpx<T>{T(0), T(0)};
-    if (in) {
-      if (a.fuse && w < ncols) {
-        // beta = 0 restarts the direction: p = r exactly, whatever p held
-        const cpx<T> p = (beta == T(0)) ? rv[it]
-                                        : cpx<T>{rv[it].x + beta * pv[it].x, rv[it].y + beta * pv[it].y};
-        a.p[ibase + (long)i * a.si + (long)(col0 + w) * a.sc_] = p;
-        s[it] = p;
-      }
-    }
+    pos(it, i, w);
+    s[it] = a.c[ibase + (long)min(i, n_in - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_];
+  }
+#pragma unroll
+  for (int it = 0; it < PMAX; ++it) {
+    int i, w;
+    if (!pos(it, i, w) || w >= ncols) s[it] = cpx<T>{T(0), T(0)};
   }
   // with row-major positions and NT a multiple of the tile width every
   // position of a thread lies in the same column: its part of xi is evaluated once

@@ -172,6 +172,63 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
 }
 
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_cg_direction(CgDirArgs<T> a) {
+  const int item = blockIdx.y;
+  if (!item_live(a.sc[item])) return;
+  constexpr int CH = 4;
+  const long base = (long)item * a.stride;
+  const long step = (long)gridDim.x * blockDim.x;
+  const bool xd = a.xdef != 0;
+  cpx<T> rv[CH], pv[CH], xv[CH];
+  auto load = [&](long e0) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const long e = min(e0 + u * step, a.count - 1);
+      rv[u] = a.r[base + e];
+      pv[u] = a.p[base + e];
+      if (xd) xv[u] = a.x[base + e];
+    }
+  };
+  // beta and the stopping test, derived by every workgroup in the same order
+  // from the last update's partials (their first loads go out ahead of the
+  // data's); the projection's first workgroup books the same decision later
+  const ItemScal q = a.sc[item];
+  const bool derive = !q.fresh;
+  double ph[8];
+  const double* rr = a.rr_part + (long)item * a.P;
+  if (derive) partials_head(rr, a.rr_n, ph);
+  long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  load(e0);
+  bool stop = false;
+  T beta = T(q.beta);
+  if (derive) {
+    const double s = partials_finish(rr, a.rr_n, ph);
+    stop = cg_stops(q, s);
+    beta = T(s / q.rho);
+  }
+  const T alpha = T(q.alpha);
+  while (e0 < a.count) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const long e = e0 + u * step;
+      if (e < a.count) {
+        if (xd) {
+          xv[u].x += alpha * pv[u].x;
+          xv[u].y += alpha * pv[u].y;
+          a.x[base + e] = xv[u];
+        }
+        // an item that stops keeps p (x is final); beta = 0 restarts: p = r
+        if (!stop)
+          a.p[base + e] = (beta == T(0)) ? rv[u]
+                                         : cpx<T>{rv[u].x + beta * pv[u].x, rv[u].y + beta * pv[u].y};
+      }
+    }
+    e0 += CH * step;
+    if (e0 < a.count) load(e0);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_cg_init(ItemScal* sc, const double* partials, int P,
                                                       int nparts, const ItemScal* mask,
                                                       const double* ref) {
@@ -650,6 +707,12 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
 }
 
 template <class T>
+hipError_t launch_cg_direction(const CgDirArgs<T>& a, int items, int blocks, hipStream_t s) {
+  launch_k((k_cg_direction<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s) {
   launch_k((k_cg_update<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
   return hipGetLastError();
@@ -813,6 +876,8 @@ template hipError_t launch_col_project<float>(const ColProjectArgs<float>&, int,
 template hipError_t launch_col_project<double>(const ColProjectArgs<double>&, int, size_t, hipStream_t, const StaticKernel*);
 template hipError_t launch_row<float>(const RowArgs<float>&, int, int, size_t, hipStream_t, const StaticKernel*);
 template hipError_t launch_row<double>(const RowArgs<double>&, int, int, size_t, hipStream_t, const StaticKernel*);
+template hipError_t launch_cg_direction<float>(const CgDirArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_cg_direction<double>(const CgDirArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_cg_update<float>(const CgUpdateArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_cg_update<double>(const CgUpdateArgs<double>&, int, int, hipStream_t);
 

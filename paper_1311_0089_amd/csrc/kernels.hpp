@@ -28,12 +28,12 @@ constexpr int kThreads = 256;
 constexpr double kTolSafety = 0.5;
 
 // a CG iteration's fused scalar work: the (r, r) partials of the last update
-// (rr, rr_n per item, stride P) from which the expansion derives beta and the
-// stopping test and the projection does the bookkeeping
+// (rr, rr_n per item, stride P) from which the direction step derives beta and
+// the stopping test and the projection does the bookkeeping
 struct CgFuse {
   const double* rr;
   int rr_n;
-  // the last update left x to this expansion: x += alpha p (old p) here
+  // the last update left x to the direction step: x += alpha p (old p) there
   int xdef;
 };
 
@@ -90,20 +90,10 @@ struct ColExpandArgs {
   // scalar spectra: element (axis-0 index i, column) at i * si + column * sc
   // (row-major: si = inner, sc = 1; column-major: si = 1, sc = n_in)
   const cpx<T>* c;  // scalar spectrum
-  const cpx<T>* r;  // fuse: p <- r + beta p, then expand p (c must equal p)
-  cpx<T>* p;
   cpx<T>* X;        // [item][d][n_fft][inner]
   long c_stride, X_stride, X_cstride;
-  int n_in, n_fft, inner, W, fuse;
+  int n_in, n_fft, inner, W;
   int si, sc_;      // scalar strides (see above); si == 1 maps axis 0 across threads
-  // fused CG step (fuse != 0): partials of (r, r) left by the last update,
-  // from which every workgroup derives beta and the stopping test itself
-  const double* rr_part;
-  int rr_n, P;
-  // xdef != 0 (fused step): the last update left x += alpha p to this
-  // expansion, applied with the old p (also when the item stops here)
-  cpx<T>* x;
-  int xdef;
   NormalGeo g;
   FftPlan plan;
   const cpx<T>* tw;
@@ -191,6 +181,22 @@ struct CgUpdateArgs {
   int xupd;
 };
 
+// the direction step of a CG iteration, a streaming kernel ahead of the
+// expansion: beta and the stopping test from the (r, r) partials of the last
+// update (unless the scalars are fresh), x += alpha p with the old p when the
+// last update left it (xdef), then p <- r + beta p
+template <class T>
+struct CgDirArgs {
+  cpx<T>* x;
+  const cpx<T>* r;
+  cpx<T>* p;
+  long stride, count;
+  ItemScal* sc;
+  const double* rr_part;
+  int rr_n, P;
+  int xdef;
+};
+
 // compile-time specialised pass kernels, registered by kernels_static*.hip
 enum { KK_EXPAND = 0, KK_PROJECT = 1, KK_PLAIN_INV = 2, KK_PLAIN_FWD = 3, KK_ROW = 4,
        KK_ROW_CONST = 5, KK_ROW_SYNTH = 6 };
@@ -244,6 +250,8 @@ hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipS
                       const StaticKernel* sk = nullptr);
 template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s);
+template <class T>
+hipError_t launch_cg_direction(const CgDirArgs<T>& a, int items, int blocks, hipStream_t s);
 
 // Eigenvalue range [lo, hi] of the coefficient at one point (v holds its
 // nA values: kind 0 a I, kind 1 diagonal, kind 2 symmetric in Voigt order);

@@ -420,7 +420,7 @@ hipError_t hom_server::refine_and_retire(SizeClass* k) {
   if (err == hipSuccess)
     err = launch_inner_accumulate(w.x, w32.x, e->S, e->S, w.sc, ub, k->items, e->stream, k->mask);
   if (err == hipSuccess)
-    err = pipe_apply<double>(e, w, k->items, w.x, 0, EPI_RESID, w.r, nullptr, w.b, k->mask,
+    err = pipe_apply<double>(e, w, k->items, w.x, EPI_RESID, w.r, nullptr, w.b, k->mask,
                              w.part);
   if (err == hipSuccess)
     err = launch_outer_check(w.sc, w.part, P, project_tiles<double>(e), k->items, 0, e->stream,

@@ -250,15 +250,13 @@ static int scalar_sc(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 
 int scalar_n0(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 1; }
 
 template <class T>
-static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse,
-                               int G0, ItemScal* sc, const CgFuse* cg = nullptr) {
+static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int G0,
+                               ItemScal* sc) {
   const DevPlan* p0;
   hipError_t e = get_dev_plan(G0, &p0);
   if (e != hipSuccess) return e;
   ColExpandArgs<T> a{};
-  a.c = fuse ? w.p : in;
-  a.r = w.r;
-  a.p = w.p;
+  a.c = in;
   a.X = w.X1;
   a.c_stride = c->S;
   a.si = scalar_si(c);
@@ -268,14 +266,6 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.n_in = c->N[0];
   a.n_fft = G0;
   a.inner = (int)inner0(c);
-  a.fuse = fuse;
-  if (cg) {
-    a.rr_part = cg->rr;
-    a.rr_n = cg->rr_n;
-    a.x = w.x;
-    a.xdef = cg->xdef;
-  }
-  a.P = partial_slots(c);
   a.g = normal_geo(c);
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
@@ -445,12 +435,12 @@ int project_tiles(CellImpl* c) {
 
 // q = Op(in) on the quadrature grid
 template <class T>
-hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int fuse, int epi,
+hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int epi,
                       cpx<T>* out, const cpx<T>* pdot, const cpx<T>* b, ItemScal* sc,
                       double* partials, const CgFuse* cg) {
   hipError_t e;
   const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
-  if ((e = stage_expand<T>(c, w, items, in, fuse, Q0, sc, cg)) != hipSuccess) return e;
+  if ((e = stage_expand<T>(c, w, items, in, Q0, sc)) != hipSuccess) return e;
   if (c->dd == 3) {
     if ((e = stage_axis1<T>(c, w, items, +1, Q0, Q1, w.X1, w.X2, sc)) != hipSuccess) return e;
     if ((e = stage_row<T>(c, items, ROW_APPLY, w.X2, w.X2, Q0, Q1, Q2, nullptr, nullptr, nullptr,
@@ -491,7 +481,7 @@ hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>
   const int G0 = onQ ? c->Q[0] : c->N[0];
   const int G1 = onQ ? c->Q[1] : c->N[1];
   const int G2 = onQ ? c->Q[2] : c->N[2];
-  if ((e = stage_expand<double>(c, w, items, cin, 0, G0, nullptr)) != hipSuccess) return e;
+  if ((e = stage_expand<double>(c, w, items, cin, G0, nullptr)) != hipSuccess) return e;
   if (c->dd == 3) {
     if ((e = stage_axis1<double>(c, w, items, +1, G0, G1, w.X1, w.X2, nullptr)) != hipSuccess)
       return e;
@@ -546,10 +536,10 @@ hipError_t pipe_project_real(CellImpl* c, Work<double>& w, int items, const doub
                                nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
-template hipError_t pipe_apply<float>(CellImpl*, Work<float>&, int, const cpx<float>*, int, int,
+template hipError_t pipe_apply<float>(CellImpl*, Work<float>&, int, const cpx<float>*, int,
                                       cpx<float>*, const cpx<float>*, const cpx<float>*, ItemScal*,
                                       double*, const CgFuse*);
-template hipError_t pipe_apply<double>(CellImpl*, Work<double>&, int, const cpx<double>*, int, int,
+template hipError_t pipe_apply<double>(CellImpl*, Work<double>&, int, const cpx<double>*, int,
                                        cpx<double>*, const cpx<double>*, const cpx<double>*,
                                        ItemScal*, double*, const CgFuse*);
 template hipError_t pipe_rhs<float>(CellImpl*, Work<float>&, int, const double*, ItemScal*);
@@ -581,21 +571,39 @@ static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles, bool xupd
 }
 
 template <class T>
+static CgDirArgs<T> direction_args(CellImpl* c, Work<T>& w, int ub, bool xdef) {
+  CgDirArgs<T> a{};
+  a.x = w.x;
+  a.r = w.r;
+  a.p = w.p;
+  a.stride = c->S;
+  a.count = c->S;
+  a.sc = w.sc;
+  a.rr_part = w.part2;
+  a.rr_n = ub;
+  a.P = partial_slots(c);
+  a.xdef = xdef ? 1 : 0;
+  return a;
+}
+
+template <class T>
 static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K, bool finalize = true) {
-  // one iteration: expansion (beta and stopping test from the last update's
-  // (r, r) partials, x += alpha p left by that update, p <- r + beta p), the
-  // operator's passes, projection (q, (p, q) partials, bookkeeping of the last
-  // update), update (alpha from the (p, q) partials, r, (r, r) partials; x
-  // only in the last iteration, which leaves x current at the end of the
-  // graph); after K iterations the last update is booked so the host reads
-  // current scalars
+  // one iteration: direction step (beta and stopping test from the last
+  // update's (r, r) partials, x += alpha p left by that update, p <- r + beta
+  // p), the operator's passes on p, projection (q, (p, q) partials,
+  // bookkeeping of the last update), update (alpha from the (p, q) partials,
+  // r, (r, r) partials; x only in the last iteration, which leaves x current
+  // at the end of the graph); after K iterations the last update is booked so
+  // the host reads current scalars
   hipError_t e = hipSuccess;
   const int P = partial_slots(c);
   const int tiles = project_tiles<T>(c);
   const int ub = update_blocks(c->S);
   for (int k = 0; k < K && e == hipSuccess; ++k) {
     const CgFuse cg{w.part2, ub, k > 0 ? 1 : 0};
-    e = pipe_apply<T>(c, w, items, w.p, 1, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part, &cg);
+    e = launch_cg_direction<T>(direction_args<T>(c, w, ub, k > 0), items, ub, c->stream);
+    if (e == hipSuccess)
+      e = pipe_apply<T>(c, w, items, w.p, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part, &cg);
     if (e == hipSuccess)
       e = launch_cg_update<T>(update_args<T>(c, w, tiles, k == K - 1), items, ub, c->stream);
   }
@@ -611,7 +619,7 @@ static hipError_t ms_body(CellImpl* c, Work<double>& w, int items, int K) {
   const int tiles = project_tiles<double>(c);
   const int ub = update_blocks(c->S);
   for (int k = 0; k < K && e == hipSuccess; ++k) {
-    e = pipe_apply<double>(c, w, items, w.x, 0, EPI_RESID, w.r, nullptr, w.b, w.sc, w.part);
+    e = pipe_apply<double>(c, w, items, w.x, EPI_RESID, w.r, nullptr, w.b, w.sc, w.part);
     if (e == hipSuccess) e = launch_ms_book(w.sc, w.part, P, tiles, items, c->stream);
     if (e == hipSuccess) e = launch_ms_axpy(w.x, w.r, c->S, c->S, w.sc, ub, items, c->stream);
   }
@@ -908,7 +916,7 @@ static hipError_t warm_start(CellImpl* c, int L, const double* strain0, double* 
   Work<double>& w = c->w64;
   hipError_t e = pipe_project_real(c, w, L, strain0, w.x);
   if (e != hipSuccess) return e;
-  if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, nullptr,
+  if ((e = pipe_apply<double>(c, w, L, w.x, EPI_RESID, w.r, nullptr, w.b, nullptr,
                               partials)) != hipSuccess)
     return e;
   return hipMemcpyAsync(w.p, w.r, sizeof(cpx<double>) * (size_t)c->S * L,
@@ -1288,7 +1296,7 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
           if ((e = launch_inner_accumulate(w.x, w32.x, c->S, c->S, outer, ub, L, c->stream,
                                            w.mask)) != hipSuccess)
             break;
-          if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.r, nullptr, w.b, w.mask,
+          if ((e = pipe_apply<double>(c, w, L, w.x, EPI_RESID, w.r, nullptr, w.b, w.mask,
                                       w.part)) != hipSuccess)
             break;
           if ((e = launch_outer_check(outer, w.part, P, tiles64, L, 0, c->stream, w.mask)) !=
@@ -1329,7 +1337,7 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
         bb.push_back(ho[i].rho0);
       }
     } else {
-      if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_RESID, w.q, nullptr, w.b, nullptr,
+      if ((e = pipe_apply<double>(c, w, L, w.x, EPI_RESID, w.q, nullptr, w.b, nullptr,
                                   w.part2)) != hipSuccess)
         break;
       if ((e = sum_partials_host(c, w.part2, L, tiles64, rr)) != hipSuccess) break;
@@ -1424,14 +1432,14 @@ hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double
     if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
     if ((e = pipe_project_real(c, w, L, u, w.x)) != hipSuccess) break;
     if (prec == HOM_FP64) {
-      if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_STORE, w.q, nullptr, nullptr, nullptr,
+      if ((e = pipe_apply<double>(c, w, L, w.x, EPI_STORE, w.q, nullptr, nullptr, nullptr,
                                   nullptr)) != hipSuccess)
         break;
     } else {
       Work<float>& w32 = c->w32;
       const long n = 2 * c->S * L;
       if ((e = launch_convert((const double*)w.x, (float*)w32.x, n, c->stream)) != hipSuccess) break;
-      if ((e = pipe_apply<float>(c, w32, L, w32.x, 0, EPI_STORE, w32.q, nullptr, nullptr, nullptr,
+      if ((e = pipe_apply<float>(c, w32, L, w32.x, EPI_STORE, w32.q, nullptr, nullptr, nullptr,
                                  nullptr)) != hipSuccess)
         break;
       if ((e = launch_widen((const float*)w32.q, (double*)w.q, n, c->stream)) != hipSuccess) break;
@@ -1556,13 +1564,13 @@ extern "C" hom_status hom_apply_noalloc(hom_cell* hc, hom_prec prec, int L, cons
     if ((e = launch_zero(dE, 3 * (long)L, c->stream)) != hipSuccess) break;
     if ((e = pipe_project_real(c, w, L, u, w.x)) != hipSuccess) break;
     if (!mixed) {
-      if ((e = pipe_apply<double>(c, w, L, w.x, 0, EPI_STORE, w.q, nullptr, nullptr, nullptr,
+      if ((e = pipe_apply<double>(c, w, L, w.x, EPI_STORE, w.q, nullptr, nullptr, nullptr,
                                   nullptr)) != hipSuccess)
         break;
     } else {
       const long n = 2 * c->S * L;
       if ((e = launch_convert((const double*)w.x, (float*)w32.x, n, c->stream)) != hipSuccess) break;
-      if ((e = pipe_apply<float>(c, w32, L, w32.x, 0, EPI_STORE, w32.q, nullptr, nullptr, nullptr,
+      if ((e = pipe_apply<float>(c, w32, L, w32.x, EPI_STORE, w32.q, nullptr, nullptr, nullptr,
                                  nullptr)) != hipSuccess)
         break;
       if ((e = launch_widen((const float*)w32.q, (double*)w.q, n, c->stream)) != hipSuccess) break;
@@ -1601,7 +1609,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     if (e2 == hipSuccess) e2 = launch_cg_init(w.sc, w.part, P, tiles, L, c->stream);
     return e2;
   };
-  for (int i = 0; i < 8; ++i) ms[i] = bytes[i] = 0.0;
+  for (int i = 0; i < 9; ++i) ms[i] = bytes[i] = 0.0;
   const double esz = sizeof(cpx<T>), Ts = sizeof(T);
   const long inner = inner0(c);
   const long rows = (c->dd == 3) ? (long)Q0 * Q1 : Q0;
@@ -1614,8 +1622,9 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   // slots: 0 expand, 1 axis-1 inverse, 2 row, 3 axis-1 forward, 4 project,
   // 5 update (alpha and beta are derived inside these kernels), 6 the
   // end-of-launch bookkeeping (once per launch of up to 16 iterations, shown
-  // per iteration as 1/16 of its duration), 7 whole iteration
-  const int NK = 7;
+  // per iteration as 1/16 of its duration), 7 the direction step; ms[7] and
+  // bytes[7] are then moved to slot 8 and slot 7 holds the whole iteration
+  const int NK = 8;
   std::vector<hipEvent_t> ev((size_t)reps * NK * 2, nullptr);
   for (auto& x : ev) (void)hipEventCreate(&x);
   std::vector<int> launched((size_t)reps * NK, 0);
@@ -1630,8 +1639,12 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
       arm_launch_events(E[2 * k], E[2 * k + 1]);
       Ln[k] = 1;
     };
-    arm(0);
-    e = stage_expand<T>(c, w, L, w.p, 1, Q0, w.sc, &cg);
+    arm(7);
+    e = launch_cg_direction<T>(direction_args<T>(c, w, ub, it > 0), L, ub, c->stream);
+    if (e == hipSuccess) {
+      arm(0);
+      e = stage_expand<T>(c, w, L, w.p, Q0, w.sc);
+    }
     if (e == hipSuccess && c->dd == 3) {
       arm(1);
       e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc);
@@ -1670,11 +1683,16 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
       ms[k] += (k == 6) ? t / 16.0 : t / reps;
     }
   }
-  for (int k = 0; k < 7; ++k) ms[7] += ms[k];
+  ms[8] = ms[7];
+  ms[7] = 0.0;
   if (c->dd != 3) ms[1] = ms[3] = 0.0;
-  // algorithmic bytes of the steady state inside a graph: the expansion reads
-  // r, p, x and writes p, x and the d fields; the update reads r, q, writes r
-  bytes[0] = L * (5.0 * S * esz + (double)c->dd * Q0 * inner * esz);
+  for (int k = 0; k < 7; ++k) ms[7] += ms[k];
+  ms[7] += ms[8];
+  // algorithmic bytes of the steady state inside a graph: the direction step
+  // reads r, p, x and writes p, x; the expansion reads p and writes the d
+  // fields; the update reads r, q, writes r
+  bytes[8] = L * 5.0 * S * esz;
+  bytes[0] = L * (S * esz + (double)c->dd * Q0 * inner * esz);
   if (c->dd == 3) {
     bytes[1] = L * (double)c->dd * Q0 * c->H * esz * (c->N[1] + Q1);
     bytes[3] = bytes[1];
@@ -1683,6 +1701,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   bytes[4] = L * ((double)c->dd * Q0 * inner * esz + 2.0 * S * esz);
   bytes[5] = L * 3.0 * S * esz;
   for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
+  bytes[7] += bytes[8];
   for (auto& x : ev) (void)hipEventDestroy(x);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(dE);

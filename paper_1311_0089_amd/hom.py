@@ -285,11 +285,12 @@ class Cell:
         return int(v.value)
 
     def profile(self, prec=FP64, L=1, reps=20):
-        ms = np.zeros(8)
-        by = np.zeros(8)
+        ms = np.zeros(9)
+        by = np.zeros(9)
         _check(lib().hom_profile_iteration(self._h, prec, L, reps, _dptr(ms), _dptr(by)),
                "hom_profile_iteration")
-        names = ["expand0", "inv1", "row", "fwd1", "project0", "update", "scalars", "iteration"]
+        names = ["expand0", "inv1", "row", "fwd1", "project0", "update", "scalars", "iteration",
+                 "direction"]
         return {n: {"ms": float(m), "bytes": float(b)} for n, m, b in zip(names, ms, by)}
 
 

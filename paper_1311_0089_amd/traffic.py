@@ -33,6 +33,7 @@ SLOTS = {
     "fwd1": ("hom::k_col_plain<float", ", -1>"),
     "project0": ("hom::k_col_project<float", None),
     "update": ("hom::k_cg_update<float>", None),
+    "direction": ("hom::k_cg_direction<float>", None),
 }
 
 
