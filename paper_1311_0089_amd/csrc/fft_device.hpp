@@ -160,6 +160,30 @@ struct Dft<T, 8, S> {
   }
 };
 
+// R = 15 by the prime-factor (Good-Thomas) mapping 15 = 3 x 5, which needs
+// no twiddles between the two factors: with n = (5 n1 + 3 n2) mod 15 and
+// k = (10 k1 + 6 k2) mod 15, y_k = sum_n1 w3^(S n1 k1) sum_n2 w5^(S n2 k2)
+// v_n (the indices of the Chinese remainder theorem for the coprime 3, 5)
+template <class T, int S>
+struct Dft<T, 15, S> {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    cpx<T> y[3][5];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 5; ++n2) y[n1][n2] = v[(5 * n1 + 3 * n2) % 15];
+      Dft<T, 5, S>::run(y[n1]);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 5; ++k2) {
+      cpx<T> z[3] = {y[0][k2], y[1][k2], y[2][k2]};
+      Dft<T, 3, S>::run(z);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) v[(10 * k1 + 6 * k2) % 15] = z[k1];
+    }
+  }
+};
+
 // Odd R: pair j with R - j.  y_0 = v_0 + sum s_j; for k = 1..(R-1)/2,
 // a_k = v_0 + sum_j s_j cos(2 pi j k / R), b_k = sum_j d_j sin(2 pi j k / R),
 // y_k = a_k + S i b_k, y_{R-k} = a_k - S i b_k, with s_j = v_j + v_{R-j},
@@ -308,6 +332,7 @@ __device__ void stockham(cpx<T>* buf, const FftPlan& P, const LdsLines& L,
       case 9: stockham_stage<T, 9, S>(buf, P.len, L, Ns, t); break;
       case 11: stockham_stage<T, 11, S>(buf, P.len, L, Ns, t); break;
       case 13: stockham_stage<T, 13, S>(buf, P.len, L, Ns, t); break;
+      case 15: stockham_stage<T, 15, S>(buf, P.len, L, Ns, t); break;
       case 17: stockham_stage<T, 17, S>(buf, P.len, L, Ns, t); break;
       case 19: stockham_stage<T, 19, S>(buf, P.len, L, Ns, t); break;
       case 23: stockham_stage<T, 23, S>(buf, P.len, L, Ns, t); break;

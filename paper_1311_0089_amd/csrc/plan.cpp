@@ -7,7 +7,7 @@
 
 namespace hom {
 
-static const int kRadices[] = {31, 29, 23, 19, 17, 13, 11, 9, 7, 5, 3, 8, 4, 2};
+static const int kRadices[] = {31, 29, 23, 19, 17, 15, 13, 11, 9, 7, 5, 3, 8, 4, 2};
 
 bool radix_supported(int r) {
   for (int x : kRadices)
@@ -18,8 +18,9 @@ bool radix_supported(int r) {
 std::vector<int> factorize(int n) {
   std::vector<int> f;
   int m = n;
-  // odd radices, largest first; 9 before 3 so 27 -> 9 3, 81 -> 9 9
-  for (int r : {31, 29, 23, 19, 17, 13, 11, 9, 7, 5, 3}) {
+  // odd radices, largest first; 15 (a register 3 x 5 prime-factor butterfly)
+  // before 5 and 3, so 255 -> 17 15; 9 before 3 so 27 -> 9 3, 81 -> 9 9
+  for (int r : {31, 29, 23, 19, 17, 15, 13, 11, 9, 7, 5, 3}) {
     while (m % r == 0) {
       f.push_back(r);
       m /= r;

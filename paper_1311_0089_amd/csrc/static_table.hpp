@@ -136,11 +136,11 @@ struct RegRow {
 
 // plans
 using P1023 = SPlan<1023, 1023, 0, Rad<31, 11, 3>>;
-using P255 = SPlan<255, 255, 0, Rad<17, 5, 3>>;
+using P255 = SPlan<255, 255, 0, Rad<17, 15>>;
 using P127 = SPlan<127, 256, 1, Rad<8, 8, 4>>;
 using P63 = SPlan<63, 63, 0, Rad<9, 7>>;
 using P31 = SPlan<31, 31, 0, Rad<31>>;
-using P15 = SPlan<15, 15, 0, Rad<5, 3>>;
+using P15 = SPlan<15, 15, 0, Rad<15>>;
 using P253 = SPlan<253, 253, 0, Rad<23, 11>>;
 using P125 = SPlan<125, 125, 0, Rad<5, 5, 5>>;
 using P61 = SPlan<61, 128, 1, Rad<8, 8, 2>>;
