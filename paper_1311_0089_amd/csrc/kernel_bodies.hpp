@@ -115,6 +115,7 @@ struct ColStatCP {
 
 struct RowGen {
   static constexpr int NT = kThreads;
+  static constexpr bool ILV = false;
   // loads per thread in flight in the load / store phases for n elements (the
   // generic FP64 kernel, already short of registers, keeps one)
   template <class T>
@@ -131,9 +132,13 @@ struct RowGen {
   }
 };
 
-template <class SP, int NTRIAL, int D_, int RP_, int NT_, bool MF_ = false>
+template <class SP, int NTRIAL, int D_, int RP_, int NT_, bool MF_ = false, bool ILV_ = false>
 struct RowStat {
   static constexpr int NT = NT_;
+  // one-dimensional grid with the items of a row tile on consecutive
+  // workgroups: they run together, so the coefficient rows they share come
+  // from the cache after the first read
+  static constexpr bool ILV = ILV_;
   template <class T>
   static constexpr int CH(int n) { return rounds_ch(n, NT_); }
   static constexpr int NN = SP::n, HH = (NTRIAL + 1) / 2, DD = D_, RPP = RP_;
@@ -658,9 +663,9 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
   constexpr int CHN = P::template CH<T>(P::DD * P::RPP * P::NN);
   const int n = P::n(a.n), H = P::H(a.H), RP = P::RP(a.RP), d = P::D(a.d);
   const int ls = P::ls(a.plan.len);
-  const int item = blockIdx.y;
+  const int item = P::ILV ? (int)blockIdx.x % a.items : (int)blockIdx.y;
   if (a.sc && !item_live(a.sc[item])) return;
-  const int pair0 = xcd_tile(blockIdx.x, gridDim.x) * RP;
+  const int pair0 = (P::ILV ? (int)blockIdx.x / a.items : xcd_tile(blockIdx.x, gridDim.x)) * RP;
 
   if (MODE == ROW_APPLY || MODE == ROW_SYNTH) {
     // Z(h) = X_a(h) + i X_b(h), Z(n-h) = conj X_a(h) + i conj X_b(h)

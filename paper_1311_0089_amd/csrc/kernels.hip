@@ -684,14 +684,17 @@ hipError_t launch_col_project(const ColProjectArgs<T>& a, int items, size_t lds,
 }
 
 template <class T>
-hipError_t launch_row(const RowArgs<T>& a, int items, int mode, size_t lds, hipStream_t s,
+hipError_t launch_row(const RowArgs<T>& a0, int items, int mode, size_t lds, hipStream_t s,
                       const StaticKernel* sk) {
+  RowArgs<T> a = a0;
+  a.items = items;
   const long pairs = (a.rows + 1) / 2;
   dim3 grid(ceil_div(pairs, a.RP), items);
   if (sk) {
     const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
                    : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
     if (sk->kind != kind) return hipErrorInvalidValue;
+    if (sk->ilv) grid = dim3(ceil_div(pairs, a.RP) * items, 1);
     auto fn = reinterpret_cast<void (*)(RowArgs<T>)>(const_cast<void*>(sk->fn));
     launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();

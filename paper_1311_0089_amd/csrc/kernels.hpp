@@ -156,6 +156,7 @@ struct RowArgs {
   int kind;             // 0 iso, 1 diag, 2 full symmetric (Voigt)
   const double* E;      // [item][d] (ROW_CONST, ROW_SYNTH)
   int d, rows, n, H, RP;
+  int items;            // items of the launch (set by the launcher)
   FftPlan plan;
   const cpx<T>* tw;
   ItemScal* sc;
@@ -207,6 +208,7 @@ struct StaticKernel {
   int NT;                       // workgroup size
   size_t lds;                   // dynamic LDS bytes
   int len, blue, nst, rad[kMaxStages];  // the compile-time FFT plan
+  int ilv;                      // row kernels: items interleaved on a 1-D grid
 };
 std::vector<StaticKernel>& static_registry();
 void register_static(const StaticKernel& k);

@@ -103,15 +103,15 @@ struct RegColCP {
   }
 };
 
-template <class T, class SP, int NTRIAL, int D, int RP, int NT, bool MF = false>
+template <class T, class SP, int NTRIAL, int D, int RP, int NT, bool MF = false, bool ILV = false>
 struct RegRow {
   static constexpr size_t lds = (size_t)D * RP * SP::len * sizeof(cpx<T>);
   static_assert(lds <= 66 * 1024 + 512, "row tile exceeds the LDS budget");
   RegRow() {
-    using P = RowStat<SP, NTRIAL, D, RP, NT, MF>;
+    using P = RowStat<SP, NTRIAL, D, RP, NT, MF, ILV>;
     add(KK_ROW, (const void*)&k_row<T, P, ROW_APPLY>);
     // the FP64 right-hand side and strain synthesis passes of the same shape
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (sizeof(T) == 8 && !ILV) {
       add(KK_ROW_CONST, (const void*)&k_row<T, P, ROW_CONST>);
       add(KK_ROW_SYNTH, (const void*)&k_row<T, P, ROW_SYNTH>);
     }
@@ -129,6 +129,7 @@ struct RegRow {
     k.lds = lds;
     k.len = SP::len;
     k.blue = SP::blue;
+    k.ilv = ILV ? 1 : 0;
     RegCol<T, SP, NTRIAL, 1, 256>::fill(k, typename SP::radices{});
     register_static(k);
   }
