@@ -59,6 +59,9 @@ def parse():
                          "re-tune now, or first registered variant")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--extra", action="store_true", help="also measure the other workloads")
+    ap.add_argument("--bounds", action="store_true",
+                    help="also the two-sided bounds of exactly integrated primal and dual Ga "
+                         "(2-D square 63..255, 3-D spheres 33..127)")
     ap.add_argument("--ms-experiment", action="store_true",
                     help="CG and Moulinec-Suquet steps and times against the contrast")
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving stream")
@@ -393,6 +396,53 @@ def ms_experiment(hom, n=255, rhos=(10.0, 100.0, 1000.0, 10000.0), tol=1e-6):
             "slope_ms": float(np.polyfit(lr, np.log([r["ms_steps"] for r in rows]), 1)[0])}
 
 
+def bounds_experiment(hom, tol=1e-6):
+    """Two-sided bounds of the homogenized coefficient from Ga with exactly
+    integrated coefficients (Sec. 6): the primal problem with the Fourier-given
+    conductivity bounds A_H from above, the inverse of the dual (flux) problem
+    with the Fourier-given resistivity from below; both energies stay bounds
+    for an inexact solve (any admissible field has at least the minimal
+    energy).  2-D: centred square of vf 1/4, contrast 100; 3-D: the 60 spheres
+    of the sphere workload (r = 0.06, contrast 1000).  Mixed precision."""
+    import hom_inputs as hi
+    cases = []
+    for n in (63, 127, 255):
+        N = (n, n)
+        cases.append(("square", N, lambda N=N: hi.square_inclusion_trig(N, 0.25, 100.0, 1.0),
+                      lambda N=N: hi.square_inclusion_trig(N, 0.25, 0.01, 1.0)))
+    for n in (33, 63, 127):
+        N = (n, n, n)
+        cases.append(("spheres", N, lambda N=N: hi.inclusions_trig(N, 60, 0.06, 1000.0, 1.0, seed=3),
+                      lambda N=N: hi.inclusions_trig(N, 60, 0.06, 1e-3, 1.0, seed=3)))
+    rows = []
+    for name, N, fa, fb in cases:
+        d = len(N)
+        row = {"cell": name, "N": list(N), "M": [2 * n - 1 for n in N]}
+        Ws = {}
+        for side, make in (("primal", fa), ("dual", fb)):
+            A = make()
+            c = hom.Cell(A, N, scheme=hom.GA, prec=hom.MIXED, a_trig=True, dual=(side == "dual"))
+            c.solve(np.eye(d), tol=tol)
+            t0 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                r = c.solve(np.eye(d), tol=tol)
+            dt = (time.perf_counter() - t0) / reps
+            c.close()
+            Ws[side] = r["W"]
+            row[side + "_ms"] = dt * 1e3
+            row[side + "_iters"] = r["info"]["iters_inner"]
+        upper = float(Ws["primal"][0, 0])
+        lower = float(np.linalg.inv(Ws["dual"])[0, 0])
+        row.update({"upper_11": upper, "lower_11": lower, "gap_rel": (upper - lower) / upper,
+                    "bracket_ok": bool(np.linalg.eigvalsh(Ws["primal"] - np.linalg.inv(Ws["dual"])).min() > 0)})
+        rows.append(row)
+        log(f"bounds {name} {N}: A_H_11 in [{lower:.6f}, {upper:.6f}] (gap {row['gap_rel']:.2e}); "
+            f"primal {row['primal_ms']:.1f} ms / {row['primal_iters']} it, dual {row['dual_ms']:.1f} ms / "
+            f"{row['dual_iters']} it")
+    return {"tol": tol, "precision": "mixed", "rows": rows}
+
+
 def solve_sample_alone(hom, n_req):
     """Every 50th request of the stream solved one at a time (no server), in
     plain FP64 and in the mixed form, at the request's tolerance: solves/s of
@@ -510,6 +560,8 @@ def main():
         out["extra_workloads"] = extra
     if args.ms_experiment:
         out["ms_vs_cg"] = ms_experiment(hom)
+    if args.bounds:
+        out["two_sided_bounds"] = bounds_experiment(hom)
     if args.serving:
         out["serving"] = serving(hom, args.serving, args.serving_rate, budget=64 << 30)
         if args.serving_fp64:

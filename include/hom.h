@@ -87,7 +87,7 @@ typedef struct {
                           near jumps (the bilinear form stays that of the SPD A): only
                           finiteness is checked; rho_A reports +inf when some sample is
                           not positive definite (hom_solve_ms then refuses the cell). */
-  int dual;            /* d = 2 only, default 0.  1: the dual (flux) problem: find the
+  int dual;            /* d = 2 or 3, default 0.  1: the dual (flux) problem: find the
                           zero-mean divergence-free trigonometric field j~ of J_N (the
                           other part of the discrete Helmholtz decomposition, Sec. 5.1)
                           minimising <(E + j~) . A (E + j~)>, with A the resistivity
@@ -95,8 +95,14 @@ typedef struct {
                           then the dual energy, whose inverse (Ga with exactly
                           integrated resistivity, a_trig) bounds the homogenized
                           conductivity from below while the primal Ga bounds it from
-                          above (Sec. 6).  Implemented with the rotated normal
-                          t = (-xi_2, xi_1)/|xi| in place of xi/|xi|. */
+                          above (Sec. 6).  In 2-D the divergence-free fields of a
+                          frequency are the multiples of the rotated normal
+                          t = (-xi_2, xi_1)/|xi|, used in place of xi/|xi|; in 3-D they
+                          form a plane, spanned by an orthonormal pair t_1, t_2 orthogonal
+                          to xi, so the CG iterate holds two potentials per frequency
+                          (twice the CG vector memory; the first-axis passes then run the
+                          generic kernels, the projection transforming the component
+                          spectra once per potential). */
 } hom_options;
 
 typedef struct {
@@ -160,7 +166,9 @@ hom_status hom_solve_ms(hom_cell* c, int L, const double* E, double tol, double*
  * For u in E_N this is the operator of the linear system (Sec. 5.2). */
 hom_status hom_apply(hom_cell* c, hom_prec prec, int L, const double* u, double* out);
 
-/* Projection onto E_N: out = G_N u, device pointers [L][d][N grid] FP64. */
+/* Projection onto E_N: out = G_N u, device pointers [L][d][N grid] FP64 (a dual
+ * cell projects onto its trial space J_N instead; hom_apply likewise uses the
+ * cell's own projection). */
 hom_status hom_project(hom_cell* c, int L, const double* u, double* out);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -53,7 +53,8 @@ struct CellImpl {
   int N[3] = {1, 1, 1};       // trial grid (device dims)
   int Q[3] = {1, 1, 1};       // quadrature grid
   int scheme = HOM_GANI, kind = HOM_A_ISO, nA = 1;
-  int dual = 0;               // 2-D dual (flux) problem on J_N
+  int dual = 0;               // dual (flux) problem on J_N
+  int npot = 1;               // potentials per frequency (2: 3-D dual)
   double Y[3] = {0.5, 0.5, 0.5};
   hom_options opt{};
   double rhoA = 1.0;

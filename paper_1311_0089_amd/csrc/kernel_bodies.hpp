@@ -195,6 +195,34 @@ __device__ __forceinline__ T normal_comp(const NormalGeo& g, int k0, const ColXi
   return (comp == 0 ? xi0 : comp == 1 ? cx.x1 : cx.x2) * inv;
 }
 
+// 3-D dual problem: the divergence-free fields of frequency k != 0 are
+// t_1 c_1 + t_2 c_2 with t_1, t_2 an orthonormal basis of the plane
+// orthogonal to xi.  With j the axis of the smallest |xi_j| (the first on
+// ties, decided in FP64 so that both precisions take the same basis):
+// t_1 = e_j x xi / |e_j x xi| and t_2 = n x t_1 = (|xi|^2 e_j - xi_j xi) /
+// (|xi| |e_j x xi|).  t_1 is odd and t_2 even in k, so the two potentials of
+// a real field keep fixed symmetries.  Component comp of t_(pot+1); 0 at k = 0.
+template <class T>
+__device__ __forceinline__ T dual3_comp(const NormalGeo& g, int k0, int col, int comp, int pot) {
+  const int k1 = kof(col / g.H, g.N1), h = col % g.H;
+  const double d0 = fabs(k0 * g.invY[0]), d1 = fabs(k1 * g.invY[1]), d2 = fabs(h * g.invY[2]);
+  const int j = (d0 <= d1 && d0 <= d2) ? 0 : (d1 <= d2) ? 1 : 2;
+  const T x0 = T(k0 * g.invY[0]), x1 = T(k1 * g.invY[1]), x2 = T(h * g.invY[2]);
+  const T s = x0 * x0 + x1 * x1 + x2 * x2;
+  const T xj = (j == 0) ? x0 : (j == 1) ? x1 : x2;
+  const T m = s - xj * xj;
+  if (!(m > T(0))) return T(0);
+  const T xc = (comp == 0) ? x0 : (comp == 1) ? x1 : x2;
+  if (pot == 0) {
+    // (e_j x xi)_c = eps_(c j l) xi_l with l the third axis
+    if (comp == j) return T(0);
+    const int l = 3 - j - comp;
+    const T xl = (l == 0) ? x0 : (l == 1) ? x1 : x2;
+    return ((j == (comp + 1) % 3) ? xl : -xl) * inv_sqrt(m);
+  }
+  return ((comp == j ? s : T(0)) - xc * xj) * inv_sqrt(s * m);
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[NT / 64];
@@ -341,6 +369,8 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
   // with row-major positions and NT a multiple of the tile width every
   // position of a thread lies in the same column: its part of xi is evaluated once
   constexpr bool col_fixed = (P::SL == 2) && P::WC > 0 && (NT % P::WC) == 0;
+  // two potentials per frequency (3-D dual) only in the generic kernels
+  constexpr bool multi = (P::WC == 0);
   ColXi<T> cx0{};
   if (col_fixed) cx0 = col_xi<T>(a.g, min(col0 + (int)threadIdx.x % W, a.inner - 1));
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
@@ -357,6 +387,19 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
       int i, w;
       if (pos(it, i, w)) {
         const int row = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
+        if (multi && a.g.npot == 2) {
+          // 3-D dual (generic kernels only): X_a = t1_a c_1 + t2_a c_2
+          const int col = min(col0 + w, a.inner - 1);
+          const cpx<T> s1 = (w < ncols) ? a.c[ibase + a.g.pot_stride + (long)min(i, n_in - 1) * a.si +
+                                                (long)col * a.sc_]
+                                          : cpx<T>{T(0), T(0)};
+          for (int c = 0; c < nc; ++c) {
+            const cpx<T> u = cscale(s[it], dual3_comp<T>(a.g, kof(i, n_in), col, al0 + c, 0));
+            const cpx<T> v = cscale(s1, dual3_comp<T>(a.g, kof(i, n_in), col, al0 + c, 1));
+            lds[row * LW + c * W + w] = cpx<T>{u.x + v.x, u.y + v.y};
+          }
+          continue;
+        }
         const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
         for (int c = 0; c < nc; ++c)
           lds[row * LW + c * W + w] = cscale(s[it], normal_comp<T>(a.g, kof(i, n_in), cx, al0 + c));
@@ -459,9 +502,6 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
     w = colm ? f / n_out : f % W;
     return f < npos;
   };
-  cpx<T> acc[PMAX];
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) acc[it] = cpx<T>{T(0), T(0)};
   // with row-major positions and NT a multiple of the tile width every
   // position of a thread lies in the same column: its part of xi is evaluated once
   constexpr bool col_fixed = (P::SL == 2) && P::WC > 0 && (NT % P::WC) == 0;
@@ -470,31 +510,69 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
-  if constexpr (P::PRE) {
-    // 3-D cells, one component per transform, sizes known at compile time:
-    // all three tiles are loaded before the first transform
-    constexpr int NL = (P::NF * P::WC + NT - 1) / NT;
-    cpx<T> pre[3][NL];
-    const cpx<T>* X0 = a.X + (long)item * a.X_stride + col0;
+  // two potentials per frequency (3-D dual, generic kernels only): each is
+  // projected in turn, the transforms of the components repeated
+  const int npot = (P::WC == 0) ? a.g.npot : 1;
+  double part = 0.0;
+  for (int pot = 0; pot < npot; ++pot) {
+    cpx<T> acc[PMAX];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int it = 0; it < PMAX; ++it) acc[it] = cpx<T>{T(0), T(0)};
+    if constexpr (P::PRE) {
+      // 3-D cells, one component per transform, sizes known at compile time:
+      // all three tiles are loaded before the first transform
+      constexpr int NL = (P::NF * P::WC + NT - 1) / NT;
+      cpx<T> pre[3][NL];
+      const cpx<T>* X0 = a.X + (long)item * a.X_stride + col0;
 #pragma unroll
-      for (int u = 0; u < NL; ++u) {
-        const int f = min((int)threadIdx.x + u * NT, P::NF * P::WC - 1);
-        const int i = f / P::WC, w = f % P::WC;
-        pre[c][u] = X0[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
-      }
-    }
+      for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-      for (int u = 0; u < NL; ++u) {
-        const int f = (int)threadIdx.x + u * NT;
-        if (f < P::NF * P::WC) {
+        for (int u = 0; u < NL; ++u) {
+          const int f = min((int)threadIdx.x + u * NT, P::NF * P::WC - 1);
           const int i = f / P::WC, w = f % P::WC;
-          lds[i * LW + w] = (w < ncols) ? pre[c][u] : cpx<T>{T(0), T(0)};
+          pre[c][u] = X0[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
         }
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+          const int f = (int)threadIdx.x + u * NT;
+          if (f < P::NF * P::WC) {
+            const int i = f / P::WC, w = f % P::WC;
+            lds[i * LW + w] = (w < ncols) ? pre[c][u] : cpx<T>{T(0), T(0)};
+          }
+        }
+        __syncthreads();
+        P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
+#pragma unroll
+        for (int it = 0; it < PMAX; ++it) {
+          int i, w;
+          if (pos(it, i, w)) {
+            const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
+            const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
+            const cpx<T> v = lds[row * LW + w];
+            const T nvc = normal_comp<T>(a.g, kof(i, n_out), cx, c);
+            acc[it].x += nvc * v.x;
+            acc[it].y += nvc * v.y;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int al0 = 0; al0 < (P::PRE ? 0 : a.d); al0 += CPN) {
+      constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
+      const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
+      in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
+          n_fft * W * nc,
+          [=](int f) __attribute__((always_inline)) {
+            const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+            return X[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
+          },
+          [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+            const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+            lds[i * LW + c * W + w] = (w < ncols) ? v : cpx<T>{T(0), T(0)};
+          });
       __syncthreads();
       P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
 #pragma unroll
@@ -503,87 +581,59 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
         if (pos(it, i, w)) {
           const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
           const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
-          const cpx<T> v = lds[row * LW + w];
-          const T nvc = normal_comp<T>(a.g, kof(i, n_out), cx, c);
-          acc[it].x += nvc * v.x;
-          acc[it].y += nvc * v.y;
+          for (int c = 0; c < nc; ++c) {
+            const cpx<T> v = lds[row * LW + c * W + w];
+            const T nvc = (npot == 2) ? dual3_comp<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1),
+                                                      al0 + c, pot)
+                                      : normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
+            acc[it].x += nvc * v.x;
+            acc[it].y += nvc * v.y;
+          }
         }
       }
       __syncthreads();
     }
-  }
-  for (int al0 = 0; al0 < (P::PRE ? 0 : a.d); al0 += CPN) {
-    constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
-    const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
-    in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
-        n_fft * W * nc,
-        [=](int f) __attribute__((always_inline)) {
-          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
-          return X[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
-        },
-        [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
-          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
-          lds[i * LW + c * W + w] = (w < ncols) ? v : cpx<T>{T(0), T(0)};
-        });
-    __syncthreads();
-    P::template fft_rows<T, -1>(lds, a.plan, W, a.tw);
+    const long sb = (long)item * a.s_stride + pot * a.g.pot_stride;
+    // the epilogue's loads (p for (p, q), b for the residual) all go out first
+    const cpx<T>* ld = (a.epi == EPI_STORE) ? a.p : (a.epi == EPI_RESID) ? a.b : nullptr;
+    cpx<T> lv[PMAX];
 #pragma unroll
     for (int it = 0; it < PMAX; ++it) {
       int i, w;
-      if (pos(it, i, w)) {
-        const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
-        const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
-        for (int c = 0; c < nc; ++c) {
-          const cpx<T> v = lds[row * LW + c * W + w];
-          const T nvc = normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
-          acc[it].x += nvc * v.x;
-          acc[it].y += nvc * v.y;
-        }
-      }
+      pos(it, i, w);
+      lv[it] = cpx<T>{T(0), T(0)};
+      if (ld) lv[it] = ld[sb + (long)min(i, n_out - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_];
     }
-    __syncthreads();
-  }
-  double part = 0.0;
-  const long sb = (long)item * a.s_stride;
-  // the epilogue's loads (p for (p, q), b for the residual) all go out first
-  const cpx<T>* ld = (a.epi == EPI_STORE) ? a.p : (a.epi == EPI_RESID) ? a.b : nullptr;
-  cpx<T> lv[PMAX];
+    // Hermitian weight of a column: 1 on the h = 0 plane, else 2
+    const double wt0 = col_fixed ? (((col0 + (int)threadIdx.x % W) % a.g.H) == 0 ? 1.0 : 2.0) : 0.0;
 #pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    int i, w;
-    pos(it, i, w);
-    lv[it] = cpx<T>{T(0), T(0)};
-    if (ld) lv[it] = ld[sb + (long)min(i, n_out - 1) * a.si + (long)(col0 + min(w, ncols - 1)) * a.sc_];
-  }
-  // Hermitian weight of a column: 1 on the h = 0 plane, else 2
-  const double wt0 = col_fixed ? (((col0 + (int)threadIdx.x % W) % a.g.H) == 0 ? 1.0 : 2.0) : 0.0;
-#pragma unroll
-  for (int it = 0; it < PMAX; ++it) {
-    int i, w;
-    if (pos(it, i, w) && w < ncols) {
-      const int col = col0 + w;
-      const long idx = sb + (long)i * a.si + (long)col * a.sc_;
-      const int h = col_fixed ? 1 : (a.g.d == 3) ? col % a.g.H : col;   // 2-D: column = h
-      const double wt = col_fixed ? wt0 : (h == 0 ? 1.0 : 2.0);
-      cpx<T> qv = cscale(acc[it], a.scale);
-      if (a.epi == EPI_STORE) {
-        a.q[idx] = qv;
-        if (a.p) {
-          const cpx<T> pv = lv[it];
-          part += wt * ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
+    for (int it = 0; it < PMAX; ++it) {
+      int i, w;
+      if (pos(it, i, w) && w < ncols) {
+        const int col = col0 + w;
+        const long idx = sb + (long)i * a.si + (long)col * a.sc_;
+        const int h = col_fixed ? 1 : (a.g.d == 3) ? col % a.g.H : col;   // 2-D: column = h
+        const double wt = col_fixed ? wt0 : (h == 0 ? 1.0 : 2.0);
+        cpx<T> qv = cscale(acc[it], a.scale);
+        if (a.epi == EPI_STORE) {
+          a.q[idx] = qv;
+          if (a.p) {
+            const cpx<T> pv = lv[it];
+            part += wt * ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
+          }
+        } else if (a.epi == EPI_RHS) {
+          qv = cpx<T>{-qv.x, -qv.y};
+          a.q[idx] = qv;
+          if (a.r) a.r[idx] = qv;
+          if (a.pp) a.pp[idx] = qv;
+          if (a.x) a.x[idx] = cpx<T>{T(0), T(0)};
+          part += wt * ((double)qv.x * (double)qv.x + (double)qv.y * (double)qv.y);
+        } else {  // EPI_RESID: r = b - q
+          const cpx<T> bv = lv[it];
+          const cpx<T> rv = cpx<T>{bv.x - qv.x, bv.y - qv.y};
+          a.r[idx] = rv;
+          part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
         }
-      } else if (a.epi == EPI_RHS) {
-        qv = cpx<T>{-qv.x, -qv.y};
-        a.q[idx] = qv;
-        if (a.r) a.r[idx] = qv;
-        if (a.pp) a.pp[idx] = qv;
-        if (a.x) a.x[idx] = cpx<T>{T(0), T(0)};
-        part += wt * ((double)qv.x * (double)qv.x + (double)qv.y * (double)qv.y);
-      } else {  // EPI_RESID: r = b - q
-        const cpx<T> bv = lv[it];
-        const cpx<T> rv = cpx<T>{bv.x - qv.x, bv.y - qv.y};
-        a.r[idx] = rv;
-        part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
       }
     }
   }

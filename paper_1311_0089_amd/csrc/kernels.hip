@@ -172,6 +172,53 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
   if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
 }
 
+// each thread takes one pair (k, -k) of the h = 0 plane and writes both of its
+// elements: c(k) <- (c(k) + sigma conj(c(-k))) / 2, c(-k) <- sigma conj(c(k))
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_sym_h0(SymArgs<T> a) {
+  const int item = blockIdx.y;
+  if (a.sc && !item_live_project(a.sc[item])) return;
+  const long n = (long)a.N0 * a.N1;
+  for (long f = (long)blockIdx.x * blockDim.x + threadIdx.x; f < n * a.npot;
+       f += (long)gridDim.x * blockDim.x) {
+    const int pot = (int)(f / n);
+    const long pi = f % n;
+    const int i0 = (int)(pi / a.N1), i1 = (int)(pi % a.N1);
+    const int m0 = i0 ? a.N0 - i0 : 0, m1 = i1 ? a.N1 - i1 : 0;
+    if ((long)m0 * a.N1 + m1 < pi) continue;   // the pair's first element takes it
+    const T sg = (a.npot == 2 && pot == 1) ? T(1) : T(-1);
+    const long base = (long)item * a.stride + pot * a.pot_stride;
+    const long e = base + i0 * a.s0 + i1 * a.s1, em = base + m0 * a.s0 + m1 * a.s1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cpx<T>* v = a.v[k];
+      if (!v) continue;
+      const cpx<T> A = v[e], B = v[em];
+      const cpx<T> h{T(0.5) * (A.x + sg * B.x), T(0.5) * (A.y - sg * B.y)};
+      v[e] = h;
+      v[em] = cpx<T>{sg * h.x, -sg * h.y};
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_norm_parts(const cpx<T>* v, long stride, long count,
+                                                          int n0, int H, double* part, int P,
+                                                          const ItemScal* sc) {
+  const int item = blockIdx.y;
+  if (sc && !item_live_project(sc[item])) return;
+  double s = 0.0;
+  const bool small = count < (1L << 31);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x) {
+    const cpx<T> x = v[(long)item * stride + e];
+    const int h = small ? ((int)e / n0) % H : (int)((e / n0) % H);
+    s += (h == 0 ? 1.0 : 2.0) * ((double)x.x * (double)x.x + (double)x.y * (double)x.y);
+  }
+  s = block_sum<kThreads>(s);
+  if (threadIdx.x == 0) part[(long)item * P + blockIdx.x] = s;
+}
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_cg_direction(CgDirArgs<T> a) {
   const int item = blockIdx.y;
@@ -807,6 +854,25 @@ hipError_t launch_convert(const double* in, float* out, long n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_sym_h0(const SymArgs<T>& a, int items, hipStream_t s) {
+  int blocks = ceil_div((long)a.N0 * a.N1 * a.npot, kThreads);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  launch_k((k_sym_h0<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_norm_parts(const cpx<T>* v, long stride, long count, int n0, int H,
+                             double* part, int P, int blocks, int items, const ItemScal* sc,
+                             hipStream_t s) {
+  if (blocks < 1 || blocks > P) return hipErrorInvalidValue;
+  launch_k((k_norm_parts<T>), dim3(blocks, items), dim3(kThreads), 0, s, v, stride, count, n0, H,
+           part, P, sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(double* p, long n, hipStream_t s) {
   int blocks = ceil_div(n, kThreads);
   if (blocks > 4096) blocks = 4096;
@@ -881,6 +947,12 @@ template hipError_t launch_row<float>(const RowArgs<float>&, int, int, size_t, h
 template hipError_t launch_row<double>(const RowArgs<double>&, int, int, size_t, hipStream_t, const StaticKernel*);
 template hipError_t launch_cg_direction<float>(const CgDirArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_cg_direction<double>(const CgDirArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_sym_h0<float>(const SymArgs<float>&, int, hipStream_t);
+template hipError_t launch_sym_h0<double>(const SymArgs<double>&, int, hipStream_t);
+template hipError_t launch_norm_parts<float>(const cpx<float>*, long, long, int, int, double*, int,
+                                             int, int, const ItemScal*, hipStream_t);
+template hipError_t launch_norm_parts<double>(const cpx<double>*, long, long, int, int, double*,
+                                              int, int, int, const ItemScal*, hipStream_t);
 template hipError_t launch_cg_update<float>(const CgUpdateArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_cg_update<double>(const CgUpdateArgs<double>&, int, int, hipStream_t);
 

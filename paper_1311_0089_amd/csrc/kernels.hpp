@@ -80,7 +80,9 @@ struct NormalGeo {
   int d;
   int N1;        // trial size of axis 1 (3-D only)
   int H;         // half-spectrum bins of the last axis
-  int dual;      // 2-D dual problem: the rotated normal t = (-n_1, n_0) spans J_N
+  int dual;      // dual problem on J_N (2-D: the rotated normal t = (-n_1, n_0))
+  int npot;      // potentials per frequency: 1, or 2 for the 3-D dual problem
+  long pot_stride;   // elements between the potentials of an item
   double invY[3];
 };
 
@@ -254,6 +256,34 @@ template <class T>
 hipError_t launch_cg_update(const CgUpdateArgs<T>& a, int items, int blocks, hipStream_t s);
 template <class T>
 hipError_t launch_cg_direction(const CgDirArgs<T>& a, int items, int blocks, hipStream_t s);
+
+// The potentials of real fields obey c(-k) = sigma conj(c(k)) on the h = 0
+// plane of the half spectrum, where k and -k are both stored (sigma = -1 for
+// an odd basis vector: n, the 2-D rotated normal, t_1 of the 3-D dual; +1 for
+// the even t_2).  The last-axis inverse transform keeps only the real part of
+// that plane, so the operator annihilates a component of the other symmetry.
+// Rounding leaves one in a computed right-hand side; where the exact
+// right-hand side vanishes (a load case the cell does not perturb) it is all
+// there is, and CG cannot reduce it.  SymArgs names up to three vectors of
+// one layout that are given the exact symmetry.
+template <class T>
+struct SymArgs {
+  cpx<T>* v[3];         // vectors (null: unused)
+  long stride;          // item stride
+  long pot_stride;      // between the potentials of an item
+  int npot;             // potentials per frequency
+  int N0, N1;           // extents of the plane (2-D cells: N1 = 1)
+  long s0, s1;          // element strides of the plane's two axes
+  const ItemScal* sc;   // selection (null: every item; else item_live_project)
+};
+template <class T>
+hipError_t launch_sym_h0(const SymArgs<T>& a, int items, hipStream_t s);
+// part[item][b] for b < blocks: the Hermitian-weighted (v, v) of a share of
+// the item's count elements (weight 1 where h = (e / n0) % H is 0, else 2)
+template <class T>
+hipError_t launch_norm_parts(const cpx<T>* v, long stride, long count, int n0, int H,
+                             double* part, int P, int blocks, int items, const ItemScal* sc,
+                             hipStream_t s);
 
 // Eigenvalue range [lo, hi] of the coefficient at one point (v holds its
 // nA values: kind 0 a I, kind 1 diagonal, kind 2 symmetric in Voigt order);

@@ -196,6 +196,10 @@ hipError_t cell_setup(CellImpl* c) {
     c->S *= c->N[a];
     c->Xe *= c->Q[a];
   }
+  // the 3-D dual problem has two potentials per frequency, stored one after
+  // the other: every CG vector kernel sees them as one spectrum of 2S elements
+  c->npot = (c->dual && dd == 3) ? 2 : 1;
+  c->S *= c->npot;
   // plans for every length used
   const DevPlan* p = nullptr;
   for (int a = 0; a < dd; ++a) {
@@ -233,8 +237,18 @@ static NormalGeo normal_geo(const CellImpl* c) {
   g.N1 = (c->dd == 3) ? c->N[1] : 1;
   g.H = c->H;
   g.dual = c->dual;
+  g.npot = c->npot;
+  g.pot_stride = c->S / c->npot;
   for (int a = 0; a < 3; ++a) g.invY[a] = 1.0 / c->Y[a];
   return g;
+}
+
+// the compile-time expand / project kernels serve one potential per
+// frequency; a cell with two (3-D dual) runs the generic ones
+static const StaticKernel* col_static(const CellImpl* c, int kind, int esz, int n,
+                                      const FftPlan& p) {
+  if (c->npot > 1) return nullptr;
+  return find_static(kind, esz, n, c->N[0], c->dd, p);
 }
 
 static long inner0(const CellImpl* c) { return (c->dd == 3) ? (long)c->N[1] * c->H : c->H; }
@@ -270,7 +284,7 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
-  const StaticKernel* sk = find_static(KK_EXPAND, sizeof(cpx<T>), G0, c->N[0], c->dd, p0->p);
+  const StaticKernel* sk = col_static(c, KK_EXPAND, sizeof(cpx<T>), G0, p0->p);
   if (sk) {
     a.W = sk->W;
     return launch_col_expand<T>(a, items, sk->lds, c->stream, sk);
@@ -408,7 +422,7 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
-  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), G0, c->N[0], c->dd, p0->p);
+  const StaticKernel* sk = col_static(c, KK_PROJECT, sizeof(cpx<T>), G0, p0->p);
   if (sk) {
     a.W = sk->W;
     if (tiles) *tiles = (a.inner + sk->W - 1) / sk->W;
@@ -426,7 +440,7 @@ int project_tiles(CellImpl* c) {
   const DevPlan* p0;
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
   const int inner = (int)inner0(c);
-  const StaticKernel* sk = find_static(KK_PROJECT, sizeof(cpx<T>), c->Q[0], c->N[0], c->dd, p0->p);
+  const StaticKernel* sk = col_static(c, KK_PROJECT, sizeof(cpx<T>), c->Q[0], p0->p);
   if (sk) return (inner + sk->W - 1) / sk->W;
   ColShape sh;
   if (col_shape(p0->p, c->N[0], inner, sizeof(cpx<T>), &sh) != hipSuccess) return 0;
@@ -471,8 +485,27 @@ hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemSc
                           sc)) != hipSuccess)
       return e;
   }
-  return stage_project<T>(c, w, items, w.X1, Q0, EPI_RHS, w.b, nullptr, w.r, w.p, w.x, nullptr,
-                          w.part, sc, nullptr);
+  if ((e = stage_project<T>(c, w, items, w.X1, Q0, EPI_RHS, w.b, nullptr, w.r, w.p, w.x, nullptr,
+                            w.part, sc, nullptr)) != hipSuccess)
+    return e;
+  // b (and r = p = b) given the exact symmetry of the potential of a real
+  // field on the h = 0 plane; (b, b) again, in the first project_tiles
+  // partial slots, where the callers sum it
+  SymArgs<T> sa{};
+  sa.v[0] = w.b;
+  sa.v[1] = w.r;
+  sa.v[2] = w.p;
+  sa.stride = c->S;
+  sa.npot = c->npot;
+  sa.pot_stride = c->S / c->npot;
+  sa.N0 = c->N[0];
+  sa.N1 = (c->dd == 3) ? c->N[1] : 1;
+  sa.s0 = scalar_si(c);
+  sa.s1 = (c->dd == 3) ? c->H : 0;
+  sa.sc = sc;
+  if ((e = launch_sym_h0<T>(sa, items, c->stream)) != hipSuccess) return e;
+  return launch_norm_parts<T>(w.b, c->S, c->S, scalar_n0(c), c->H, w.part, partial_slots(c),
+                              project_tiles<T>(c), items, sc, c->stream);
 }
 
 hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>* cin,
@@ -1066,7 +1099,7 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   if (o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1) return HOM_EINVAL;
   if (!(o.inner_tol > 0 && o.inner_tol < 1)) return HOM_EINVAL;
   if (o.a_trig != 0 && (o.a_trig != 1 || o.scheme != HOM_GA)) return HOM_EINVAL;
-  if (o.dual != 0 && (o.dual != 1 || d != 2)) return HOM_EINVAL;
+  if (o.dual != 0 && (o.dual != 1 || d < 2)) return HOM_EINVAL;
   for (int a = 0; a < d; ++a) {
     if (N[a] < 1 || (N[a] % 2) == 0 || N[a] > (1 << 20)) return HOM_EINVAL;
     if (!(o.Y[a] > 0) || !std::isfinite(o.Y[a])) return HOM_EINVAL;
@@ -1748,11 +1781,14 @@ static std::vector<PassKey> pass_keys(const CellImpl* c) {
   const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
   const int Glast = (dd == 3) ? Q2 : Q1;
   std::vector<PassKey> v;
-  v.push_back({0, TuneKey{KK_EXPAND, esz, Q0, c->N[0], dd}, Q0});
+  // a cell with two potentials per frequency runs the generic expand and
+  // project kernels: their variants are not its to time or force
+  const bool col = (c->npot == 1);
+  if (col) v.push_back({0, TuneKey{KK_EXPAND, esz, Q0, c->N[0], dd}, Q0});
   if (dd == 3) v.push_back({1, TuneKey{KK_PLAIN_INV, esz, Q1, c->N[1], 0}, Q1});
   v.push_back({2, TuneKey{KK_ROW, esz, Glast, c->N[dd - 1], dd}, Glast});
   if (dd == 3) v.push_back({3, TuneKey{KK_PLAIN_FWD, esz, Q1, c->N[1], 0}, Q1});
-  v.push_back({4, TuneKey{KK_PROJECT, esz, Q0, c->N[0], dd}, Q0});
+  if (col) v.push_back({4, TuneKey{KK_PROJECT, esz, Q0, c->N[0], dd}, Q0});
   return v;
 }
 

@@ -1,4 +1,4 @@
-"""The dual (flux) formulation on the GPU (2-D, the dual option): parity with
+"""The dual (flux) formulation on the GPU (the dual option, 2-D and 3-D): parity with
 the oracle's dual problem (the projection onto the divergence-free fields of
 J_N, Sec. 5.1), the laminate closed form, and the two-sided bounds of Ga with
 exactly integrated coefficient and resistivity (Sec. 6)."""
@@ -28,25 +28,34 @@ def hom():
 
 @gpu
 @pytest.mark.parametrize("N,kind,scheme", [((15, 13), 0, 0), ((31, 29), 2, 0), ((9, 11), 1, 1),
-                                           ((63, 63), 0, 0)])
+                                           ((63, 63), 0, 0), ((9, 7, 5), 0, 0),
+                                           ((11, 9, 13), 2, 0), ((7, 9, 5), 1, 1),
+                                           ((5, 7, 9), 2, 1)])
 def test_dual_matches_oracle(hom, oracle, N, kind, scheme):
+    d = len(N)
     Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
     B = hi.random_spd_field(Q, kind, seed=131 + kind, contrast=50.0)
     ocell = oracle.Cell(B, N, kind=kind, scheme=scheme, dual=True)
-    x, W, J, _ = ocell.solve(np.eye(2), tol=1e-13)
+    x, W, J, _ = ocell.solve(np.eye(d), tol=1e-13)
     g = hom.Cell(B, N, kind=kind, scheme=scheme, dual=True)
-    r = g.solve(np.eye(2), tol=1e-13, want_strain=True)
+    r = g.solve(np.eye(d), tol=1e-13, want_strain=True)
     assert rel(r["W"], W) < 1e-10
-    assert rel(r["strain"].cpu().numpy(), x + np.eye(2)[:, :, None, None]) < 1e-10
+    E = np.eye(d).reshape((d, d) + (1,) * d)
+    assert rel(r["strain"].cpu().numpy(), x + E) < 1e-10
     m = hom.Cell(B, N, kind=kind, scheme=scheme, dual=True, prec=hom.MIXED)
-    assert rel(m.solve(np.eye(2), tol=1e-8)["W"], W) < 1e-6
+    assert rel(m.solve(np.eye(d), tol=1e-8)["W"], W) < 1e-6
     # the operator: one apply of the dual G B G against the oracle's
     import torch
-    u = np.stack([ocell.apply_G(hi.normal(140 + l, 2 * int(np.prod(N))).reshape((2,) + N))
-                  for l in range(2)])
-    ref = np.stack([ocell.apply_GA(u[l]) for l in range(2)])
+    u = np.stack([ocell.apply_G(hi.normal(140 + l, d * int(np.prod(N))).reshape((d,) + N))
+                  for l in range(d)])
+    ref = np.stack([ocell.apply_GA(u[l]) for l in range(d)])
     out = g.apply(torch.from_numpy(u).cuda()).cpu().numpy()
     assert rel(out, ref) < 1e-13
+    # the projection onto J_N (twice: idempotent) against the oracle's
+    v = hi.normal(150, d * int(np.prod(N))).reshape((1, d) + N)
+    pv = g.project(torch.from_numpy(v).cuda()).cpu().numpy()
+    assert rel(pv[0], ocell.apply_G(v[0])) < 1e-13
+    assert rel(g.project(torch.from_numpy(pv).cuda()).cpu().numpy(), pv) < 1e-13
 
 
 @gpu
@@ -80,9 +89,46 @@ def test_two_sided_bounds_exact_square(hom):
 
 
 @gpu
-def test_dual_rejected_in_3d_and_by_the_server(hom):
+@pytest.mark.parametrize("N", [(63, 31, 15), (255, 127, 63)])
+def test_dual_laminate_closed_form_3d(hom, N):
+    """3-D laminate of resistivity 1/a(x_1): dual energy diag(<1/a>, 1/<a>,
+    1/<a>) in both precisions, at the 255-point first axis of the sphere
+    workload."""
+    a = 1.0 + 99.0 * hi.uniform(7, N[0])
+    ref = np.diag([np.mean(1.0 / a), 1.0 / np.mean(a), 1.0 / np.mean(a)])
+    for prec, tol, bar in ((hom.FP64, 1e-12, 1e-10), (hom.MIXED, 1e-8, 1e-6)):
+        g = hom.Cell(hi.laminate(N, 1.0 / a), N, dual=True, prec=prec)
+        W = g.solve(np.eye(3), tol=tol)["W"]
+        assert np.abs(W - ref).max() / ref.max() < bar
+
+
+@gpu
+def test_two_sided_bounds_exact_cube(hom, oracle):
+    """Centred cube of vf 1/8, contrast 100, by its Fourier series: primal Ga
+    above, the inverse of dual Ga below, the gap shrinking from N = 9 to 17
+    to 33 (M = 17, 33, 65); the N = 9 pair equals the oracle's."""
+    a1, a0 = 100.0, 1.0
+    gaps = []
+    for n in (9, 17, 33):
+        N = (n, n, n)
+        A = hi.square_inclusion_trig(N, 0.25, a1, a0)
+        B = hi.square_inclusion_trig(N, 0.25, 1.0 / a1, 1.0 / a0)
+        Wp = hom.Cell(A, N, scheme=hom.GA, a_trig=True).solve(np.eye(3), tol=1e-10)["W"]
+        Wd = hom.Cell(B, N, scheme=hom.GA, a_trig=True, dual=True).solve(np.eye(3),
+                                                                          tol=1e-10)["W"]
+        if n == 9:
+            _, Wd_o, _, _ = oracle.Cell(B, N, scheme=1, dual=True).solve(np.eye(3), tol=1e-12)
+            assert rel(Wd, Wd_o) < 1e-8
+        lower = np.linalg.inv(Wd)
+        assert np.linalg.eigvalsh(Wp - lower).min() > 0
+        gaps.append(Wp[0, 0] - lower[0, 0])
+    assert gaps[2] < gaps[1] < gaps[0]
+
+
+@gpu
+def test_dual_rejected_in_1d_and_by_the_server(hom):
     with pytest.raises(hom.HomError):
-        hom.Cell(np.ones((5, 5, 5)), (5, 5, 5), dual=True)
+        hom.Cell(np.ones(5), (5,), dual=True)
     srv = hom.Server(1 << 30)
     c = hom.Cell(np.ones((15, 15)), (15, 15), dual=True, prec=hom.MIXED)
     with pytest.raises(hom.HomError):
