@@ -39,8 +39,16 @@ static long kof(long i, long n) { return (i <= (n - 1) / 2) ? i : i - n; }
 /* storage position of signed index k on an axis of length n */
 static long pos(long k, long n) { return ((k % n) + n) % n; }
 
+/* components of a field: d (vector fields of the scalar problem) or
+ * d(d+1)/2 (symmetric strain / stress tensors in Mandel form, elasticity) */
+static int ncomp(const hor_cell* c) {
+    return (c->kind == HOR_ELASTIC) ? c->d * (c->d + 1) / 2 : c->d;
+}
+
 static int valid_cell(const hor_cell* c) {
     if (!c || c->d < 1 || c->d > 3 || !c->A) return 0;
+    if (c->kind < HOR_ISO || c->kind > HOR_ELASTIC) return 0;
+    if (c->kind == HOR_ELASTIC && (c->d < 2 || c->dual)) return 0;
     for (int a = 0; a < c->d; ++a) {
         if (c->N[a] < 1 || (c->N[a] % 2) == 0) return 0;
         long q = (c->scheme == HOR_GA) ? 2 * c->N[a] - 1 : c->N[a];
@@ -143,7 +151,7 @@ int hor_dft_all(int d, const long* n, int sign, double* data) {
 /* Fourier-space pieces                                                */
 /* ------------------------------------------------------------------ */
 
-/* complex [d][grid] <- real [d][grid] */
+/* complex [d][grid] <- real [d][grid] (d: the component count) */
 static double* to_complex(int d, long np, const double* u) {
     double* z = (double*)calloc(2 * (size_t)d * (size_t)np, sizeof(double));
     if (!z) return NULL;
@@ -164,11 +172,85 @@ static int to_real(int d, long np, const double* z, double* out) {
     return HOR_OK;
 }
 
+/* Elasticity (the extension of the scheme beyond the scalar setting named in
+ * Sec. 6): strain and stress fields are symmetric d x d tensors, stored as
+ * Mandel vectors z [d(d+1)/2][grid] (order 11, 22, 33, 23, 13, 12 as in
+ * voigt(), off-diagonal entries times sqrt 2, so that z . z' = Z : Z').  The
+ * trial space is the compatible strains, symmetric gradients of periodic
+ * displacements: at frequency k != 0 the tensors sym(xi (x) u), u in C^d.
+ * The orthogonal projection of Z onto them is sym(xi (x) u) with u the
+ * least-squares solution of sym(xi (x) u) = Z, i.e. K u = Z xi with
+ * K = (|xi|^2 I + xi xi^T) / 2, whose inverse is (2 / |xi|^2)(I - xi xi^T /
+ * (2 |xi|^2)); k = 0 (the mean) is removed.  In place on z. */
+static void project_compatible(int d, const long* N, const double* Y, double* z) {
+    const int m = d * (d + 1) / 2;
+    long np = prod(d, N);
+    const double r2 = sqrt(2.0);
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < np; ++p) {
+        long rem = p;
+        double xi[3] = {0, 0, 0};
+        int zero = 1;
+        for (int a = d - 1; a >= 0; --a) {
+            long i = rem % N[a];
+            rem /= N[a];
+            long k = kof(i, N[a]);
+            if (k != 0) zero = 0;
+            xi[a] = (double)k / Y[a];
+        }
+        if (zero) {
+            for (int q = 0; q < m; ++q) z[2 * ((long)q * np + p)] = z[2 * ((long)q * np + p) + 1] = 0.0;
+            continue;
+        }
+        /* Z from its Mandel vector (real and imaginary parts) */
+        double Zr[3][3], Zi[3][3];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                int q = voigt(d, a, b);
+                double f = (a == b) ? 1.0 : 1.0 / r2;
+                Zr[a][b] = f * z[2 * ((long)q * np + p)];
+                Zi[a][b] = f * z[2 * ((long)q * np + p) + 1];
+            }
+        double xx = 0.0;
+        for (int a = 0; a < d; ++a) xx += xi[a] * xi[a];
+        /* t = Z xi, then u = K^-1 t */
+        double tr[3] = {0, 0, 0}, ti[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                tr[a] += Zr[a][b] * xi[b];
+                ti[a] += Zi[a][b] * xi[b];
+            }
+        double xtr = 0.0, xti = 0.0;
+        for (int a = 0; a < d; ++a) {
+            xtr += xi[a] * tr[a];
+            xti += xi[a] * ti[a];
+        }
+        double ur[3], ui[3];
+        for (int a = 0; a < d; ++a) {
+            ur[a] = (2.0 / xx) * (tr[a] - xi[a] * xtr / (2.0 * xx));
+            ui[a] = (2.0 / xx) * (ti[a] - xi[a] * xti / (2.0 * xx));
+        }
+        /* sym(xi (x) u) back to Mandel form */
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b) {
+                int q = voigt(d, a, b);
+                double f = (a == b) ? 1.0 : r2;
+                z[2 * ((long)q * np + p)] = f * 0.5 * (xi[a] * ur[b] + ur[a] * xi[b]);
+                z[2 * ((long)q * np + p) + 1] = f * 0.5 * (xi[a] * ui[b] + ui[a] * xi[b]);
+            }
+    }
+}
+
 /* Apply Gamma^(k) = xi (x) xi / (xi . xi), Gamma^(0) = 0 (reference A0 = I),
  * in place on the complex vector spectrum z [d][N grid]; with dual != 0 the
  * complementary projection onto J_N, I - Gamma^(k) for k != 0 and 0 at k = 0
  * (G + G_dual + mean = I, the discrete Helmholtz decomposition, Sec. 5.1). */
-static void project_fourier(int d, const long* N, const double* Y, double* z, int dual) {
+static void project_fourier(int d, const long* N, const double* Y, double* z, int dual,
+                            int elastic) {
+    if (elastic) {
+        project_compatible(d, N, Y, z);
+        return;
+    }
     long np = prod(d, N);
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {
@@ -218,6 +300,19 @@ static void project_fourier(int d, const long* N, const double* Y, double* z, in
 /* pointwise flux j = A e on a grid of np points: e, j real [d][np] */
 static void flux(const hor_cell* c, long np, const double* e, double* j) {
     int d = c->d;
+    if (c->kind == HOR_ELASTIC) {
+        /* isotropic Hooke law sigma = lambda tr(eps) I + 2 mu eps, Mandel form:
+           the first d components are the normal ones */
+        const int m = d * (d + 1) / 2;
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < np; ++p) {
+            double lam = c->A[p], mu = c->A[np + p], tr = 0.0;
+            for (int a = 0; a < d; ++a) tr += e[(long)a * np + p];
+            for (int q = 0; q < m; ++q)
+                j[(long)q * np + p] = 2.0 * mu * e[(long)q * np + p] + ((q < d) ? lam * tr : 0.0);
+        }
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {
         for (int a = 0; a < d; ++a) {
@@ -230,9 +325,10 @@ static void flux(const hor_cell* c, long np, const double* e, double* j) {
 
 /* zero-padding of Fourier coefficients from Z_N to Z_M (trigonometric
  * polynomial of T_N seen on the finer grid); zin [d][N], zout [d][M] */
-static void pad_spectrum(int d, const long* N, const long* M, const double* zin, double* zout) {
+static void pad_spectrum(int d, int nc, const long* N, const long* M, const double* zin,
+                         double* zout) {
     long nN = prod(d, N), nM = prod(d, M);
-    memset(zout, 0, sizeof(double) * 2 * (size_t)d * (size_t)nM);
+    memset(zout, 0, sizeof(double) * 2 * (size_t)nc * (size_t)nM);
     for (long p = 0; p < nN; ++p) {
         long rem = p, q = 0, stride = 1;
         long idx[3] = {0, 0, 0};
@@ -244,7 +340,7 @@ static void pad_spectrum(int d, const long* N, const long* M, const double* zin,
             q += pos(kof(idx[a], N[a]), M[a]) * stride;
             stride *= M[a];
         }
-        for (int c = 0; c < d; ++c) {
+        for (int c = 0; c < nc; ++c) {
             zout[2 * ((long)c * nM + q)] = zin[2 * ((long)c * nN + p)];
             zout[2 * ((long)c * nM + q) + 1] = zin[2 * ((long)c * nN + p) + 1];
         }
@@ -252,7 +348,8 @@ static void pad_spectrum(int d, const long* N, const long* M, const double* zin,
 }
 
 /* truncation P_N of Fourier coefficients from Z_M to Z_N (Sec. 4.1) */
-static void trunc_spectrum(int d, const long* N, const long* M, const double* zin, double* zout) {
+static void trunc_spectrum(int d, int nc, const long* N, const long* M, const double* zin,
+                           double* zout) {
     long nN = prod(d, N), nM = prod(d, M);
     for (long p = 0; p < nN; ++p) {
         long rem = p, q = 0, stride = 1;
@@ -265,7 +362,7 @@ static void trunc_spectrum(int d, const long* N, const long* M, const double* zi
             q += pos(kof(idx[a], N[a]), M[a]) * stride;
             stride *= M[a];
         }
-        for (int c = 0; c < d; ++c) {
+        for (int c = 0; c < nc; ++c) {
             zout[2 * ((long)c * nN + p)] = zin[2 * ((long)c * nM + q)];
             zout[2 * ((long)c * nN + p) + 1] = zin[2 * ((long)c * nM + q) + 1];
         }
@@ -278,15 +375,15 @@ static void trunc_spectrum(int d, const long* N, const long* M, const double* zi
 
 int hor_apply_G(const hor_cell* c, const double* u, double* out) {
     if (!valid_cell(c) || !u || !out) return HOR_EINVAL;
-    int d = c->d;
+    int d = c->d, nc = ncomp(c);
     long np = prod(d, c->N);
-    double* z = to_complex(d, np, u);
+    double* z = to_complex(nc, np, u);
     if (!z) return HOR_ENOMEM;
     int s = 0;
-    for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, -1, z + 2 * (long)comp * np);
-    if (!s) project_fourier(d, c->N, c->Y, z, c->dual);
-    for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, +1, z + 2 * (long)comp * np);
-    if (!s) s = to_real(d, np, z, out);
+    for (int comp = 0; comp < nc && !s; ++comp) s = hor_dft_all(d, c->N, -1, z + 2 * (long)comp * np);
+    if (!s) project_fourier(d, c->N, c->Y, z, c->dual, c->kind == HOR_ELASTIC);
+    for (int comp = 0; comp < nc && !s; ++comp) s = hor_dft_all(d, c->N, +1, z + 2 * (long)comp * np);
+    if (!s) s = to_real(nc, np, z, out);
     free(z);
     return s;
 }
@@ -294,20 +391,20 @@ int hor_apply_G(const hor_cell* c, const double* u, double* out) {
 /* Interpolate a real field u [d][N] (grid values of a T_N polynomial) to the
  * Q grid: identity for GaNi, Fourier zero-padding for Ga.  out [d][Q]. */
 static int interp_to_Q(const hor_cell* c, const double* u, double* out) {
-    int d = c->d;
+    int d = c->d, nc = ncomp(c);
     long nN = prod(d, c->N), nQ = prod(d, c->Q);
     if (c->scheme == HOR_GANI) {
-        memcpy(out, u, sizeof(double) * (size_t)d * (size_t)nN);
+        memcpy(out, u, sizeof(double) * (size_t)nc * (size_t)nN);
         return HOR_OK;
     }
-    double* z = to_complex(d, nN, u);
-    double* zq = (double*)malloc(sizeof(double) * 2 * (size_t)d * (size_t)nQ);
+    double* z = to_complex(nc, nN, u);
+    double* zq = (double*)malloc(sizeof(double) * 2 * (size_t)nc * (size_t)nQ);
     if (!z || !zq) { free(z); free(zq); return HOR_ENOMEM; }
     int s = 0;
-    for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, -1, z + 2 * (long)comp * nN);
-    if (!s) pad_spectrum(d, c->N, c->Q, z, zq);
-    for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->Q, +1, zq + 2 * (long)comp * nQ);
-    if (!s) s = to_real(d, nQ, zq, out);
+    for (int comp = 0; comp < nc && !s; ++comp) s = hor_dft_all(d, c->N, -1, z + 2 * (long)comp * nN);
+    if (!s) pad_spectrum(d, nc, c->N, c->Q, z, zq);
+    for (int comp = 0; comp < nc && !s; ++comp) s = hor_dft_all(d, c->Q, +1, zq + 2 * (long)comp * nQ);
+    if (!s) s = to_real(nc, nQ, zq, out);
     free(z);
     free(zq);
     return s;
@@ -315,27 +412,27 @@ static int interp_to_Q(const hor_cell* c, const double* u, double* out) {
 
 int hor_apply_GA(const hor_cell* c, const double* u, double* out) {
     if (!valid_cell(c) || !u || !out) return HOR_EINVAL;
-    int d = c->d;
+    int d = c->d, nc = ncomp(c);
     long nN = prod(d, c->N), nQ = prod(d, c->Q);
-    double* uq = (double*)malloc(sizeof(double) * (size_t)d * (size_t)nQ);
-    double* jq = (double*)malloc(sizeof(double) * (size_t)d * (size_t)nQ);
-    double* zn = (double*)malloc(sizeof(double) * 2 * (size_t)d * (size_t)nN);
+    double* uq = (double*)malloc(sizeof(double) * (size_t)nc * (size_t)nQ);
+    double* jq = (double*)malloc(sizeof(double) * (size_t)nc * (size_t)nQ);
+    double* zn = (double*)malloc(sizeof(double) * 2 * (size_t)nc * (size_t)nN);
     if (!uq || !jq || !zn) { free(uq); free(jq); free(zn); return HOR_ENOMEM; }
     int s = interp_to_Q(c, u, uq);            /* u on the quadrature grid */
     double* zq = NULL;
     if (!s) {
         flux(c, nQ, uq, jq);                  /* A_Q u */
-        zq = to_complex(d, nQ, jq);
+        zq = to_complex(nc, nQ, jq);
         if (!zq) s = HOR_ENOMEM;
     }
-    for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->Q, -1, zq + 2 * (long)comp * nQ);
+    for (int comp = 0; comp < nc && !s; ++comp) s = hor_dft_all(d, c->Q, -1, zq + 2 * (long)comp * nQ);
     if (!s) {
-        if (c->scheme == HOR_GA) trunc_spectrum(d, c->N, c->Q, zq, zn);
-        else memcpy(zn, zq, sizeof(double) * 2 * (size_t)d * (size_t)nN);
-        project_fourier(d, c->N, c->Y, zn, c->dual);
+        if (c->scheme == HOR_GA) trunc_spectrum(d, nc, c->N, c->Q, zq, zn);
+        else memcpy(zn, zq, sizeof(double) * 2 * (size_t)nc * (size_t)nN);
+        project_fourier(d, c->N, c->Y, zn, c->dual, c->kind == HOR_ELASTIC);
     }
-    for (int comp = 0; comp < d && !s; ++comp) s = hor_dft_all(d, c->N, +1, zn + 2 * (long)comp * nN);
-    if (!s) s = to_real(d, nN, zn, out);
+    for (int comp = 0; comp < nc && !s; ++comp) s = hor_dft_all(d, c->N, +1, zn + 2 * (long)comp * nN);
+    if (!s) s = to_real(nc, nN, zn, out);
     free(uq); free(jq); free(zn); free(zq);
     return s;
 }
@@ -360,7 +457,7 @@ static int op_GA(const hor_cell* c, const void* ctx, const double* u, double* ou
 /* L-SD operator M e = e + Gamma_lambda (A - lambda I) e, Gamma_lambda = G / lambda */
 static int op_LSD(const hor_cell* c, const void* ctx, const double* u, double* out) {
     double lam = *(const double*)ctx;
-    long n = (long)c->d * prod(c->d, c->N);
+    long n = (long)ncomp(c) * prod(c->d, c->N);
     double* t = (double*)malloc(sizeof(double) * (size_t)n);
     double* g = (double*)malloc(sizeof(double) * (size_t)n);
     if (!t || !g) { free(t); free(g); return HOR_ENOMEM; }
@@ -379,7 +476,7 @@ static int cg_core(const hor_cell* c, op_fn M, const void* ctx, const double* b,
                    int max_iter, double ref2, double* x, int* iters, double* relres,
                    double* hist) {
     long np = prod(c->d, c->N);
-    long n = (long)c->d * np;
+    long n = (long)ncomp(c) * np;
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
     double* p = (double*)malloc(sizeof(double) * (size_t)n);
     double* q = (double*)malloc(sizeof(double) * (size_t)n);
@@ -438,9 +535,9 @@ static double* const_field(int d, long np, const double* E) {
 int hor_cg(const hor_cell* c, const double* E, double tol, int max_iter,
            int warm, double* x, int* iters, double* relres, double* hist) {
     if (!valid_cell(c) || !E || !x || !(tol > 0.0) || max_iter < 0) return HOR_EINVAL;
-    int d = c->d;
-    long np = prod(d, c->N), n = (long)d * np;
-    double* Ef = const_field(d, np, E);
+    int d = c->d, nc = ncomp(c);
+    long np = prod(d, c->N), n = (long)nc * np;
+    double* Ef = const_field(nc, np, E);
     double* b = (double*)malloc(sizeof(double) * (size_t)n);
     if (!Ef || !b) { free(Ef); free(b); return HOR_ENOMEM; }
     int s = hor_apply_GA(c, Ef, b);           /* b = -G A E */
@@ -463,11 +560,11 @@ int hor_cg(const hor_cell* c, const double* E, double tol, int max_iter,
 int hor_cg_lsd(const hor_cell* c, const double* E, double lambda, double tol,
                int max_iter, double* e, int* iters) {
     if (!valid_cell(c) || !E || !e || !(lambda > 0.0) || !(tol > 0.0)) return HOR_EINVAL;
-    int d = c->d;
+    int d = c->d, nc = ncomp(c);
     long np = prod(d, c->N);
-    double* Ef = const_field(d, np, E);
+    double* Ef = const_field(nc, np, E);
     if (!Ef) return HOR_ENOMEM;
-    memcpy(e, Ef, sizeof(double) * (size_t)d * (size_t)np);   /* e0 = E */
+    memcpy(e, Ef, sizeof(double) * (size_t)nc * (size_t)np);   /* e0 = E */
     int s = cg_core(c, op_LSD, &lambda, Ef, tol, max_iter, 0.0, e, iters, NULL, NULL);
     free(Ef);
     return s;
@@ -476,9 +573,9 @@ int hor_cg_lsd(const hor_cell* c, const double* E, double lambda, double tol,
 int hor_ms(const hor_cell* c, const double* E, double lambda, double tol,
            int max_iter, double* e, int* iters) {
     if (!valid_cell(c) || !E || !e || !(lambda > 0.0) || !(tol > 0.0)) return HOR_EINVAL;
-    int d = c->d;
-    long np = prod(d, c->N), n = (long)d * np;
-    double* Ef = const_field(d, np, E);
+    int d = c->d, nc = ncomp(c);
+    long np = prod(d, c->N), n = (long)nc * np;
+    double* Ef = const_field(nc, np, E);
     double* t = (double*)malloc(sizeof(double) * (size_t)n);
     double* g = (double*)malloc(sizeof(double) * (size_t)n);
     if (!Ef || !t || !g) { free(Ef); free(t); free(g); return HOR_ENOMEM; }
@@ -517,11 +614,11 @@ int hor_ms(const hor_cell* c, const double* E, double lambda, double tol,
 
 int hor_strain_on_Q(const hor_cell* c, const double* E, const double* x, double* out) {
     if (!valid_cell(c) || !E || !x || !out) return HOR_EINVAL;
-    int d = c->d;
+    int d = c->d, nc = ncomp(c);
     long nQ = prod(d, c->Q);
     int s = interp_to_Q(c, x, out);
     if (!s)
-        for (int a = 0; a < d; ++a)
+        for (int a = 0; a < nc; ++a)
             for (long p = 0; p < nQ; ++p) out[(long)a * nQ + p] += E[a];
     return s;
 }
@@ -529,27 +626,27 @@ int hor_strain_on_Q(const hor_cell* c, const double* E, const double* x, double*
 int hor_homogenized(const hor_cell* c, int L, const double* E, const double* x,
                     double* W, double* J) {
     if (!valid_cell(c) || L < 1 || !E || !x || !W) return HOR_EINVAL;
-    int d = c->d;
+    int d = c->d, nc = ncomp(c);
     long nN = prod(d, c->N), nQ = prod(d, c->Q);
-    double* e = (double*)malloc(sizeof(double) * (size_t)L * (size_t)d * (size_t)nQ);
-    double* j = (double*)malloc(sizeof(double) * (size_t)L * (size_t)d * (size_t)nQ);
+    double* e = (double*)malloc(sizeof(double) * (size_t)L * (size_t)nc * (size_t)nQ);
+    double* j = (double*)malloc(sizeof(double) * (size_t)L * (size_t)nc * (size_t)nQ);
     if (!e || !j) { free(e); free(j); return HOR_ENOMEM; }
     int s = 0;
     for (int l = 0; l < L && !s; ++l) {
-        s = hor_strain_on_Q(c, E + (long)l * d, x + (long)l * d * nN, e + (long)l * d * nQ);
-        if (!s) flux(c, nQ, e + (long)l * d * nQ, j + (long)l * d * nQ);
+        s = hor_strain_on_Q(c, E + (long)l * nc, x + (long)l * nc * nN, e + (long)l * nc * nQ);
+        if (!s) flux(c, nQ, e + (long)l * nc * nQ, j + (long)l * nc * nQ);
     }
     if (!s) {
         for (int l = 0; l < L; ++l)
             for (int m = 0; m < L; ++m)
-                W[l * L + m] = gdot((long)d * nQ, nQ, e + (long)l * d * nQ, j + (long)m * d * nQ);
+                W[l * L + m] = gdot((long)nc * nQ, nQ, e + (long)l * nc * nQ, j + (long)m * nc * nQ);
         if (J)
             for (int l = 0; l < L; ++l)
-                for (int a = 0; a < d; ++a) {
+                for (int a = 0; a < nc; ++a) {
                     double sum = 0.0;
-                    const double* jj = j + (long)l * d * nQ + (long)a * nQ;
+                    const double* jj = j + (long)l * nc * nQ + (long)a * nQ;
                     for (long p = 0; p < nQ; ++p) sum += jj[p];
-                    J[l * d + a] = sum / (double)nQ;
+                    J[l * nc + a] = sum / (double)nQ;
                 }
     }
     free(e); free(j);

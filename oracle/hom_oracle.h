@@ -37,7 +37,14 @@ extern "C" {
 enum { HOR_OK = 0, HOR_EINVAL = -1, HOR_ENOTREAL = -2, HOR_EBREAKDOWN = -5,
        HOR_ENOTCONV = -4, HOR_ENOMEM = -3 };
 
-enum { HOR_ISO = 0, HOR_DIAG = 1, HOR_FULLSYM = 2 };
+/* HOR_ELASTIC: linear elasticity (d = 2 plane strain, or 3), the extension
+ * beyond the scalar setting that Sec. 6 names.  Fields are then symmetric
+ * tensors in Mandel form, d(d+1)/2 components in Voigt order with the
+ * off-diagonal entries times sqrt 2; A holds the Lame fields [lambda, mu] on
+ * the Q grid (nA = 2), sigma = lambda tr(eps) I + 2 mu eps; the trial space is
+ * the compatible strains (symmetric gradients of periodic displacements) and
+ * E, x, W, J are taken over those components. */
+enum { HOR_ISO = 0, HOR_DIAG = 1, HOR_FULLSYM = 2, HOR_ELASTIC = 3 };
 enum { HOR_GANI = 0, HOR_GA = 1 };
 
 typedef struct {

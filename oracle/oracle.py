@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hom_oracle.c")
 _LIB = os.environ.get("HOM_ORACLE_LIB") or os.path.join(_HERE, "libhom_oracle.so")
 
-ISO, DIAG, FULLSYM = 0, 1, 2
+ISO, DIAG, FULLSYM, ELASTIC = 0, 1, 2, 3
 GANI, GA = 0, 1
 _ERR = {0: "ok", -1: "invalid argument", -2: "imaginary part not negligible",
         -3: "out of memory", -4: "not converged", -5: "CG breakdown"}
@@ -87,7 +87,12 @@ def _chk(code: int, what: str, allow=()):
 
 
 def n_coeff(kind: int, d: int) -> int:
-    return {ISO: 1, DIAG: d, FULLSYM: d * (d + 1) // 2}[kind]
+    return {ISO: 1, DIAG: d, FULLSYM: d * (d + 1) // 2, ELASTIC: 2}[kind]
+
+
+def n_comp(kind: int, d: int) -> int:
+    """Field components: d, or d(d+1)/2 Mandel components for elasticity."""
+    return d * (d + 1) // 2 if kind == ELASTIC else d
 
 
 class Cell:
@@ -105,6 +110,7 @@ class Cell:
         if A.shape != (n_coeff(kind, d),) + Q:
             raise ValueError(f"A has shape {A.shape}, expected {(n_coeff(kind, d),) + Q}")
         self.A, self.N, self.Q, self.d, self.kind, self.scheme = A, N, Q, d, kind, scheme
+        self.nc = n_comp(kind, d)
         self.Y = tuple(Y) if Y is not None else (0.5,) * d
         c = _Cell()
         c.d, c.scheme, c.kind = d, scheme, kind
@@ -119,8 +125,8 @@ class Cell:
     # -- operators ------------------------------------------------------
     def _field(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64)
-        if u.shape != (self.d,) + self.N:
-            raise ValueError(f"field shape {u.shape} != {(self.d,) + self.N}")
+        if u.shape != (self.nc,) + self.N:
+            raise ValueError(f"field shape {u.shape} != {(self.nc,) + self.N}")
         return u
 
     def apply_G(self, u):
@@ -139,8 +145,8 @@ class Cell:
     def cg(self, E, tol=1e-8, max_iter=10000, x0=None, history=False, allow_notconv=False):
         """CG on G A x = -G A E (x0 = 0 unless given).  Returns
         (x, iters, true relative residual[, history])."""
-        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.d)
-        x = np.zeros((self.d,) + self.N) if x0 is None else self._field(x0).copy()
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.nc)
+        x = np.zeros((self.nc,) + self.N) if x0 is None else self._field(x0).copy()
         it = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
         hist = np.zeros(max_iter + 1)
@@ -152,16 +158,16 @@ class Cell:
         return x, it.value, rr.value
 
     def cg_lsd(self, E, lam, tol=1e-12, max_iter=10000):
-        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.d)
-        e = np.empty((self.d,) + self.N)
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.nc)
+        e = np.empty((self.nc,) + self.N)
         it = ctypes.c_int(0)
         _chk(lib().hor_cg_lsd(ctypes.byref(self._c), _dp(E), lam, tol, max_iter, _dp(e),
                               ctypes.byref(it)), "cg_lsd")
         return e, it.value
 
     def ms(self, E, lam, tol=1e-12, max_iter=100000):
-        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.d)
-        e = np.empty((self.d,) + self.N)
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.nc)
+        e = np.empty((self.nc,) + self.N)
         it = ctypes.c_int(0)
         _chk(lib().hor_ms(ctypes.byref(self._c), _dp(E), lam, tol, max_iter, _dp(e),
                           ctypes.byref(it)), "ms")
@@ -170,26 +176,27 @@ class Cell:
     def homogenized(self, E, x):
         """W_lm = <e_l . A e_m>_Q and J_l = <A e_l>_Q for load cases E [L][d]
         and fluctuations x [L][d][N]."""
-        E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, self.d)
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, self.nc)
         L = E.shape[0]
-        x = np.ascontiguousarray(x, dtype=np.float64).reshape((L, self.d) + self.N)
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape((L, self.nc) + self.N)
         W = np.empty((L, L))
-        J = np.empty((L, self.d))
+        J = np.empty((L, self.nc))
         _chk(lib().hor_homogenized(ctypes.byref(self._c), L, _dp(E), _dp(x), _dp(W), _dp(J)),
              "homogenized")
         return W, J
 
     def strain_on_Q(self, E, x):
-        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.d)
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(self.nc)
         x = self._field(x)
-        out = np.empty((self.d,) + self.Q)
+        out = np.empty((self.nc,) + self.Q)
         _chk(lib().hor_strain_on_Q(ctypes.byref(self._c), _dp(E), _dp(x), _dp(out)),
              "strain_on_Q")
         return out
 
     def solve(self, E, tol=1e-8, max_iter=10000):
-        """Solve every load case of E [L][d]; returns (x [L][d][N], W, J, iters)."""
-        E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, self.d)
+        """Solve every load case of E [L][d] (elasticity: [L][d(d+1)/2] Mandel
+        strains); returns (x [L][nc][N], W, J, iters)."""
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, self.nc)
         xs, its = [], []
         for El in E:
             x, it, _ = self.cg(El, tol=tol, max_iter=max_iter)

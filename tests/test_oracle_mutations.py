@@ -22,16 +22,22 @@ MUTATIONS = [
      "const double scale = 1.0;"),
     ("DFT sign flipped", "cs[2 * t + 1] = (double)sign * sin(th);",
      "cs[2 * t + 1] = -(double)sign * sin(th);"),
-    ("zero mode kept", "if (k != 0) zero = 0;", "zero = 0;"),
-    ("xi without Y", "xi[a] = (double)k / Y[a];", "xi[a] = (double)k;"),
+    ("zero mode kept", "if (k != 0) zero = 0;\n            xi[a] = (double)k / Y[a];\n        }\n        if (zero) {\n            for (int a = 0;",
+     "zero = 0;\n            xi[a] = (double)k / Y[a];\n        }\n        if (zero) {\n            for (int a = 0;"),
+    ("xi without Y", "xi[a] = (double)k / Y[a];\n        }\n        if (zero) {\n            for (int a = 0;",
+     "xi[a] = (double)k;\n        }\n        if (zero) {\n            for (int a = 0;"),
+    ("elastic zero mode kept", "if (k != 0) zero = 0;\n            xi[a] = (double)k / Y[a];\n        }\n        if (zero) {\n            for (int q = 0;",
+     "zero = 0;\n            xi[a] = (double)k / Y[a];\n        }\n        if (zero) {\n            for (int q = 0;"),
+    ("elastic xi without Y", "xi[a] = (double)k / Y[a];\n        }\n        if (zero) {\n            for (int q = 0;",
+     "xi[a] = (double)k;\n        }\n        if (zero) {\n            for (int q = 0;"),
     ("projection on the real part only", "z[2 * ((long)a * np + p) + 1] = xi[a] * si / xx;",
      "z[2 * ((long)a * np + p) + 1] = xi[a] * sr / xx;"),
     ("signed index off by one", "static long kof(long i, long n) { return (i <= (n - 1) / 2) ? i : i - n; }",
      "static long kof(long i, long n) { return (i < (n - 1) / 2) ? i : i - n; }"),
     ("flux with a transposed Voigt entry", "s += A_entry(c, np, p, a, b) * e[(long)b * np + p];",
      "s += A_entry(c, np, p, a, a) * e[(long)b * np + p];"),
-    ("pad to the wrong position", "q += pos(kof(idx[a], N[a]), M[a]) * stride;\n            stride *= M[a];\n        }\n        for (int c = 0; c < d; ++c) {\n            zout[2 * ((long)c * nM + q)]",
-     "q += idx[a] * stride;\n            stride *= M[a];\n        }\n        for (int c = 0; c < d; ++c) {\n            zout[2 * ((long)c * nM + q)]"),
+    ("pad to the wrong position", "q += pos(kof(idx[a], N[a]), M[a]) * stride;\n            stride *= M[a];\n        }\n        for (int c = 0; c < nc; ++c) {\n            zout[2 * ((long)c * nM + q)]",
+     "q += idx[a] * stride;\n            stride *= M[a];\n        }\n        for (int c = 0; c < nc; ++c) {\n            zout[2 * ((long)c * nM + q)]"),
     ("RHS sign", "for (long i = 0; i < n; ++i) b[i] = -b[i];", "for (long i = 0; i < n; ++i) b[i] = b[i];"),
     ("beta from the old residual twice", "double beta = rho1 / rho;", "double beta = rho / rho1;"),
     ("alpha without (p, q)", "double alpha = rho / gam;", "double alpha = rho / gdot(n, np, p, p);"),
@@ -41,9 +47,16 @@ MUTATIONS = [
      "double rho0 = rho;"),
     ("strain without E", "for (long p = 0; p < nQ; ++p) out[(long)a * nQ + p] += E[a];",
      "for (long p = 0; p < nQ; ++p) out[(long)a * nQ + p] += 0.0;"),
-    ("W with the strain twice", "W[l * L + m] = gdot((long)d * nQ, nQ, e + (long)l * d * nQ, j + (long)m * d * nQ);",
-     "W[l * L + m] = gdot((long)d * nQ, nQ, e + (long)l * d * nQ, e + (long)m * d * nQ);"),
+    ("W with the strain twice", "W[l * L + m] = gdot((long)nc * nQ, nQ, e + (long)l * nc * nQ, j + (long)m * nc * nQ);",
+     "W[l * L + m] = gdot((long)nc * nQ, nQ, e + (long)l * nc * nQ, e + (long)m * nc * nQ);"),
     ("grid mean without 1/|N|", "return s / (double)np;   /* grid mean, Sec. 5.1 */", "return s;"),
+    ("elastic projection without the xi xi / (2 |xi|^2) term",
+     "ur[a] = (2.0 / xx) * (tr[a] - xi[a] * xtr / (2.0 * xx));", "ur[a] = (2.0 / xx) * tr[a];"),
+    ("Mandel shear written without sqrt 2", "double f = (a == b) ? 1.0 : r2;", "double f = 1.0;"),
+    ("Hooke law without the trace term", "+ ((q < d) ? lam * tr : 0.0);", "+ 0.0;"),
+    ("Hooke law with mu for 2 mu", "j[(long)q * np + p] = 2.0 * mu * e[", "j[(long)q * np + p] = mu * e["),
+    ("elastic trace over every component", "for (int a = 0; a < d; ++a) tr += e[(long)a * np + p];",
+     "for (int a = 0; a < d * (d + 1) / 2; ++a) tr += e[(long)a * np + p];"),
 ]
 
 

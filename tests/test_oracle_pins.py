@@ -596,3 +596,225 @@ def test_dual_two_sided_bounds_exact_square(oracle):
         assert np.linalg.eigvalsh(Wp - lower).min() > 0
         gaps.append(Wp[0, 0] - lower[0, 0])
     assert gaps[2] < gaps[1] < gaps[0]
+
+
+# ------------------- linear elasticity (the extension named in Sec. 6)
+# Mandel form: symmetric tensors as d(d+1)/2 vectors in Voigt order with the
+# off-diagonal entries times sqrt 2 (so the vector dot product is Z : Z').
+def mandel_pairs(d):
+    return {2: [(0, 0), (1, 1), (0, 1)], 3: [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]}[d]
+
+
+def to_mandel(Z, d):
+    """(d, d, ...) symmetric tensor -> (m, ...) Mandel vector."""
+    return np.stack([Z[a, b] * (1.0 if a == b else np.sqrt(2.0)) for a, b in mandel_pairs(d)])
+
+
+def from_mandel(z, d):
+    Z = np.zeros((d, d) + z.shape[1:], dtype=z.dtype)
+    for t, (a, b) in enumerate(mandel_pairs(d)):
+        v = z[t] if a == b else z[t] / np.sqrt(2.0)
+        Z[a, b] = v
+        Z[b, a] = v
+    return Z
+
+
+def lame_stiffness(lam, mu, d):
+    """Mandel matrix of lambda tr(eps) I + 2 mu eps (textbook Hooke law)."""
+    m = d * (d + 1) // 2
+    C = 2.0 * mu * np.eye(m)
+    C[:d, :d] += lam
+    return C
+
+
+def lame_field(Q, seed, contrast=20.0):
+    """Random Lame fields (lambda, mu) on grid Q: mu in [1, contrast],
+    lambda = mu times a factor in [0.2, 2] (positive definite everywhere)."""
+    u = hi.uniform(seed, 2 * int(np.prod(Q))).reshape((2,) + tuple(Q))
+    mu = 1.0 + (contrast - 1.0) * u[0]
+    lam = mu * (0.2 + 1.8 * u[1])
+    return np.stack([lam, mu])
+
+
+def sym_grad_mandel(U, Y=None):
+    """Mandel strain of the trigonometric displacement U [d][N] by numpy FFT
+    differentiation (d/dx_a <-> 2 pi i k_a / (2 Y_a))."""
+    d = U.shape[0]
+    N = U.shape[1:]
+    Y = (0.5,) * d if Y is None else Y
+    ks = np.meshgrid(*[hi.signed_index(n) for n in N], indexing="ij")
+    Uh = np.stack([np.fft.fftn(U[a]) for a in range(d)])
+    G = np.zeros((d, d) + tuple(N))
+    for a in range(d):
+        for b in range(d):
+            G[a, b] = np.fft.ifftn(1j * np.pi * ks[b] / Y[b] * Uh[a]).real
+    return to_mandel(0.5 * (G + G.transpose((1, 0) + tuple(range(2, 2 + d)))), d)
+
+
+@pytest.mark.parametrize("N,Y", [((9, 7), None), ((5, 7, 3), None), ((7, 5), (0.5, 0.8)),
+                                 ((5, 3, 5), (0.7, 0.5, 0.4))])
+def test_elastic_projection_properties(oracle, N, Y):
+    """G onto compatible strains: idempotent, self-adjoint in the grid inner
+    product, zero on constants, the identity on symmetric gradients of
+    trigonometric displacements (numpy FFT), and its output satisfies the
+    compatibility condition inc(Z) = xi x Z x xi = 0 at every frequency."""
+    d = len(N)
+    m = d * (d + 1) // 2
+    c = oracle.Cell(lame_field(N, 3), N, kind=oracle.ELASTIC, Y=Y)
+    u = rand_field((m,) + N, 51)
+    v = rand_field((m,) + N, 52)
+    Gu, Gv = c.apply_G(u), c.apply_G(v)
+    np.testing.assert_allclose(c.apply_G(Gu), Gu, atol=1e-13)
+    assert abs(np.mean(Gu * v) - np.mean(u * Gv)) < 1e-14
+    const = np.ones((m,) + N) * np.arange(1, m + 1).reshape((m,) + (1,) * d)
+    assert np.abs(c.apply_G(const)).max() < 1e-13
+    U = rand_field((d,) + N, 53)
+    for a in range(d):
+        U[a] = np.fft.ifftn(np.fft.fftn(U[a])).real
+    eps = sym_grad_mandel(U, Y)
+    np.testing.assert_allclose(c.apply_G(eps), eps, atol=1e-12 * np.abs(eps).max())
+    Zh = from_mandel(np.stack([np.fft.fftn(Gu[t]) for t in range(m)]), d)
+    Yv = (0.5,) * d if Y is None else Y
+    ks = [k / Yv[a] for a, k in enumerate(np.meshgrid(*[hi.signed_index(n) for n in N],
+                                                      indexing="ij"))]
+    if d == 2:
+        inc = ks[1] ** 2 * Zh[0, 0] + ks[0] ** 2 * Zh[1, 1] - 2 * ks[0] * ks[1] * Zh[0, 1]
+    else:
+        eps3 = np.zeros((3, 3, 3))
+        eps3[0, 1, 2] = eps3[1, 2, 0] = eps3[2, 0, 1] = 1.0
+        eps3[0, 2, 1] = eps3[2, 1, 0] = eps3[1, 0, 2] = -1.0
+        K = np.stack(ks).astype(float)
+        inc = np.einsum("ikl,jmn,k...,m...,ln...->ij...", eps3, eps3, K, K, Zh)
+    assert np.abs(inc).max() < 1e-11 * np.abs(Zh).max()
+
+
+@pytest.mark.parametrize("N", [(7, 5), (5, 3, 5)])
+def test_elastic_homogeneous_cell(oracle, N):
+    """Constant Lame moduli: the fluctuation vanishes and the energy matrix of
+    the unit Mandel strains is the stiffness itself."""
+    d = len(N)
+    m = d * (d + 1) // 2
+    A = np.stack([np.full(N, 1.7), np.full(N, 0.9)])
+    x, W, J, its = oracle.Cell(A, N, kind=oracle.ELASTIC).solve(np.eye(m), tol=1e-12)
+    np.testing.assert_allclose(W, lame_stiffness(1.7, 0.9, d), atol=1e-13)
+    assert np.abs(x).max() < 1e-13
+
+
+def elastic_laminate_W(lam, mu, d):
+    """Energy matrix of the unit Mandel strains for layers normal to x_1 with
+    grid values lam, mu (closed form of the layered medium: the strains along
+    the layers equal the applied ones, the tractions sigma_1b are constant)."""
+    m = d * (d + 1) // 2
+    W = np.zeros((m, m))
+    strains = []
+    for I in range(m):
+        E = from_mandel(np.eye(m)[I], d)
+        eps = np.repeat(E[:, :, None], len(lam), axis=2)
+        lam2 = lam + 2.0 * mu
+        other = sum(E[b, b] for b in range(1, d))
+        s11 = (E[0, 0] + other * np.mean(lam / lam2)) / np.mean(1.0 / lam2)
+        eps[0, 0] = (s11 - lam * other) / lam2
+        for b in range(1, d):
+            s1b = 2.0 * E[0, b] / np.mean(1.0 / mu)
+            eps[0, b] = eps[b, 0] = s1b / (2.0 * mu)
+        strains.append(to_mandel(eps, d))
+    for I in range(m):
+        for J in range(m):
+            W[I, J] = np.mean([strains[I][:, p] @ lame_stiffness(lam[p], mu[p], d) @ strains[J][:, p]
+                               for p in range(len(lam))])
+    return W
+
+
+@pytest.mark.parametrize("N", [(15, 7), (9, 5, 7)])
+def test_elastic_laminate_closed_form(oracle, N):
+    d = len(N)
+    m = d * (d + 1) // 2
+    u = hi.uniform(61, 2 * N[0]).reshape(2, N[0])
+    mu = 1.0 + 30.0 * u[0]
+    lam = mu * (0.2 + 1.8 * u[1])
+    A = np.stack([hi.laminate(N, lam), hi.laminate(N, mu)])
+    _, W, _, _ = oracle.Cell(A, N, kind=oracle.ELASTIC).solve(np.eye(m), tol=1e-14)
+    np.testing.assert_allclose(W, elastic_laminate_W(lam, mu, d), rtol=1e-11, atol=1e-11)
+
+
+def elastic_fourier_galerkin_dense(A, N, scheme, E):
+    """Dense Galerkin solve in displacement form, independent of the oracle:
+    unknowns u^(k) in C^d for k in Z_N \\ {0}, strain^(k) = B(k) u^(k) with
+    B(k) u = Mandel(sym(xi (x) u)) (not normalised), K_km = B(k)^T C^(k - m)
+    B(m) and b_k = -B(k)^T C^(k) E with C^ the numpy DFT of the Mandel
+    stiffness field on Q (k - m mod Q).  Returns W over the Q grid."""
+    N = tuple(N)
+    d = len(N)
+    m = d * (d + 1) // 2
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    Cx = np.zeros((m, m) + Q)
+    for idx in np.ndindex(*Q):
+        Cx[(slice(None), slice(None)) + idx] = lame_stiffness(A[0][idx], A[1][idx], d)
+    Ch = np.fft.fftn(Cx, axes=tuple(range(2, 2 + d))) / np.prod(Q)
+    ks = np.array(list(np.ndindex(*N)))
+    kk = np.stack([hi.signed_index(n)[ks[:, a]] for a, n in enumerate(N)], axis=1)
+    kk = kk[np.any(kk != 0, axis=1)]
+    xi = kk / 0.5
+    B = np.zeros((len(kk), m, d))
+    for p in range(d):
+        for t, (a, b) in enumerate(mandel_pairs(d)):
+            f = 1.0 if a == b else np.sqrt(2.0)
+            B[:, t, p] = f * 0.5 * (xi[:, a] * (b == p) + xi[:, b] * (a == p))
+
+    def Cmat(j):
+        idx = tuple(np.mod(j[..., a], Q[a]) for a in range(d))
+        return np.moveaxis(Ch[(slice(None), slice(None)) + idx], (0, 1), (-2, -1))
+
+    K = np.einsum("kta,kmts,msb->kamb", B, Cmat(kk[:, None, :] - kk[None, :, :]), B)
+    n = len(kk) * d
+    K = K.reshape(n, n)
+    fields = []
+    for El in np.atleast_2d(E):
+        rhs = -np.einsum("kta,kts,s->ka", B, Cmat(kk), El).reshape(n)
+        uh = np.linalg.solve(K, rhs).reshape(len(kk), d)
+        specQ = np.zeros((m,) + Q, dtype=complex)
+        for t in range(len(kk)):
+            pos = tuple(int(kk[t, a]) % Q[a] for a in range(d))
+            specQ[(slice(None),) + pos] = B[t] @ uh[t]
+        eQ = np.stack([np.fft.ifftn(specQ[s]).real * np.prod(Q) + El[s] for s in range(m)])
+        fields.append(eQ.reshape(m, -1))
+    Cf = Cx.reshape(m, m, -1)
+    L = len(fields)
+    W = np.zeros((L, L))
+    for l in range(L):
+        for k2 in range(L):
+            W[l, k2] = np.mean(np.einsum("sp,stp,tp->p", fields[l], Cf, fields[k2]))
+    return W
+
+
+@pytest.mark.parametrize("N", [(3, 5), (5, 5), (3, 3, 3)])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_elastic_dense_fourier_galerkin(oracle, N, scheme):
+    """The oracle's real-space CG for elasticity against the displacement-form
+    Galerkin system assembled densely and solved by LU (GaNi: C^(k - m) wraps
+    mod N; Ga on 2N - 1: no wrap)."""
+    d = len(N)
+    m = d * (d + 1) // 2
+    Q = tuple(2 * n - 1 for n in N) if scheme == 1 else N
+    A = lame_field(Q, 71 + scheme)
+    _, W, _, _ = oracle.Cell(A, N, kind=oracle.ELASTIC, scheme=scheme).solve(np.eye(m), tol=1e-14)
+    np.testing.assert_allclose(W, elastic_fourier_galerkin_dense(A, N, scheme, np.eye(m)),
+                               rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("N", [(9, 9), (5, 5, 5)])
+def test_elastic_voigt_reuss_bounds(oracle, N):
+    """Effective stiffness symmetric, between the Reuss and Voigt averages of
+    the Mandel stiffness in the Loewner order; the flux J of unit strains is
+    the energy matrix itself (the energy-flux identity at convergence)."""
+    d = len(N)
+    m = d * (d + 1) // 2
+    A = lame_field(N, 81)
+    _, W, J, _ = oracle.Cell(A, N, kind=oracle.ELASTIC).solve(np.eye(m), tol=1e-13)
+    Cs = np.stack([lame_stiffness(A[0][i], A[1][i], d) for i in np.ndindex(*N)])
+    voigt = Cs.mean(axis=0)
+    reuss = np.linalg.inv(np.linalg.inv(Cs).mean(axis=0))
+    np.testing.assert_allclose(W, W.T, atol=1e-12 * np.abs(W).max())
+    assert np.linalg.eigvalsh(voigt - W).min() > -1e-10
+    assert np.linalg.eigvalsh(W - reuss).min() > -1e-10
+    np.testing.assert_allclose(J, W, rtol=1e-9, atol=1e-9)
