@@ -59,6 +59,9 @@ def parse():
                          "re-tune now, or first registered variant")
     ap.add_argument("--tune-out", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--extra", action="store_true", help="also measure the other workloads")
+    ap.add_argument("--elastic", action="store_true",
+                    help="also linear elasticity: the 60 spheres of the sphere workload as stiff "
+                         "isotropic inclusions, 255^3, six Mandel load cases")
     ap.add_argument("--bounds", action="store_true",
                     help="also the two-sided bounds of exactly integrated primal and dual Ga "
                          "(2-D square 63..255, 3-D spheres 33..127)")
@@ -87,6 +90,8 @@ def make_workload(name, n=None):
     import hom_inputs as hi
     if name == "spheres":
         return hi.cfg3_spheres()
+    if name == "elastic":
+        return hi.elastic_spheres()
     if name == "lognormal":
         return hi.cfg4_lognormal()
     if name == "pixels":
@@ -154,12 +159,14 @@ def pass_model_bytes(w, L, real_bytes):
     spectrum of a real field counted as one real per grid point) and the flux
     pass also reads A once.  GaNi: 2 d |N| s per pass and load case; Ga (the
     pruned pad / truncate passes): the trial / quadrature sizes of each pass."""
-    d = len(w.N)
+    dim = len(w.N)
+    # field components: d, or the d(d+1)/2 Mandel components of elasticity
+    d = dim * (dim + 1) // 2 if w.kind == 3 else dim
     N = list(w.N)
     Q = [2 * n - 1 for n in N] if w.scheme == 1 else N
-    nA = 1 if w.kind == 0 else (d if w.kind == 1 else d * (d + 1) // 2)
+    nA = {0: 1, 1: dim, 2: dim * (dim + 1) // 2, 3: 2}[w.kind]
     s = real_bytes
-    if d == 2:
+    if dim == 2:
         ex = N[0] * N[1] + Q[0] * N[1]
         row = 2 * Q[0] * N[1]
         return {"expand0": d * L * s * ex, "row": d * L * s * row + nA * Q[0] * Q[1] * s,
@@ -562,6 +569,19 @@ def main():
         out["ms_vs_cg"] = ms_experiment(hom)
     if args.bounds:
         out["two_sided_bounds"] = bounds_experiment(hom)
+    if args.elastic:
+        we = make_workload("elastic")
+        me = measure(hom, we, hom.MIXED, 2, 1, ref=True, inner_tol=args.inner_tol)
+        me["config"] = config_of(we, args)
+        C = np.array(me["A_H"])
+        cs = np.stack([np.diag([2.0 * mu] * 6) + np.pad(np.full((3, 3), lam), ((0, 3), (0, 3)))
+                       for lam, mu in ((1.0, 1.0), (100.0, 100.0))])
+        wv = [1 - we.info["vf"], we.info["vf"]]
+        voigt = np.einsum("k,kij->ij", wv, cs)
+        reuss = np.linalg.inv(np.einsum("k,kij->ij", wv, np.linalg.inv(cs)))
+        me["stiffness_within_voigt_reuss"] = bool(np.linalg.eigvalsh(voigt - C).min() > 0 and
+                                                  np.linalg.eigvalsh(C - reuss).min() > 0)
+        out["elastic"] = me
     if args.serving:
         out["serving"] = serving(hom, args.serving, args.serving_rate, budget=64 << 30)
         if args.serving_fp64:

@@ -333,7 +333,7 @@ class Workload:
     d: int
     N: tuple
     scheme: int            # 0 GaNi, 1 Ga
-    kind: int              # 0 iso, 1 diag, 2 full symmetric
+    kind: int              # 0 iso, 1 diag, 2 full symmetric, 3 isotropic elasticity
     A: np.ndarray          # (nA, *Q) or Q for iso
     E: np.ndarray          # (L, d)
     tol: float
@@ -362,6 +362,18 @@ def cfg3_spheres(N=(255, 255, 255), count=60, r=0.06, seed=3):
     A = inclusions(N, count, r, 1e3, 1.0, seed)
     return Workload(f"spheres-{N[0]}^3", 3, tuple(N), 0, 0, A, np.eye(3), 1e-6,
                     {"vf": float((A > 1).mean()), "contrast": 1e3, "seed": seed})
+
+
+def elastic_spheres(N=(255, 255, 255), count=60, r=0.06, seed=3, contrast=100.0):
+    """3-D linear elasticity: the 60 spheres of the sphere workload as stiff
+    isotropic inclusions (Lame lambda = mu = contrast) in a matrix with
+    lambda = mu = 1 (Poisson ratio 1/4); A = [lambda, mu]; the six unit Mandel
+    strains as load cases."""
+    inside = inclusions(N, count, r, 2.0, 1.0, seed) > 1.0
+    lam = np.where(inside, contrast, 1.0)
+    A = np.stack([lam, lam.copy()])
+    return Workload(f"elastic-spheres-{N[0]}^3", 3, tuple(N), 0, 3, A, np.eye(6), 1e-6,
+                    {"vf": float(inside.mean()), "contrast": contrast, "seed": seed})
 
 
 def cfg4_lognormal(N=(127, 127, 127), seed=4):

@@ -24,6 +24,20 @@
  * quadrature grid: nA = 1 (HOM_A_ISO: a I), d (HOM_A_DIAG) or d(d+1)/2
  * (HOM_A_FULLSYM, Voigt order 11,22,33,23,13,12; in 2-D 11,22,12).
  *
+ * Linear elasticity (HOM_A_ELASTIC, d = 2 plane strain or 3; the extension
+ * beyond the scalar setting that Sec. 6 names): nA = 2 planes, the Lame
+ * fields lambda and mu, with sigma = lambda tr(eps) I + 2 mu eps.  Strains,
+ * load cases and mean stresses are then symmetric tensors as Mandel vectors of
+ * m = d(d+1)/2 components (Voigt order, off-diagonal entries times sqrt 2, so
+ * that dot products are tensor contractions): E is [L][m], strain [L][m][N
+ * grid], J [L][m], and W the energies of the load cases (the effective Mandel
+ * stiffness for E = I_m).  The trial space is the compatible strains (symmetric
+ * gradients of periodic trigonometric displacements); the CG iterate holds d
+ * displacement potentials per frequency on an orthonormal basis of them.
+ * Elastic cells run the generic first-axis and last-axis kernels; they take no
+ * dual or a_trig option, the server does not batch them, and a last-axis
+ * length with a prime factor above 31 is rejected (HOM_EINVAL).
+ *
  * Errors: every function returns a hom_status; nothing aborts or throws.
  * Ownership: the caller owns every buffer it passes; the library copies what
  * it keeps.  Threading: a cell is not re-entrant; distinct cells may be used
@@ -55,7 +69,7 @@ typedef enum {
   HOM_ESCRATCH = -8     /* hom_apply_noalloc: workspace above HOM_NOALLOC_SCRATCH_BYTES */
 } hom_status;
 
-typedef enum { HOM_A_ISO = 0, HOM_A_DIAG = 1, HOM_A_FULLSYM = 2 } hom_a_kind;
+typedef enum { HOM_A_ISO = 0, HOM_A_DIAG = 1, HOM_A_FULLSYM = 2, HOM_A_ELASTIC = 3 } hom_a_kind;
 typedef enum { HOM_GANI = 0, HOM_GA = 1 } hom_scheme;
 /* HOM_FP64: FFTs, fields and reductions in FP64.
  * HOM_MIXED: the CG recursion runs with FP32 FFTs and fields (FP64 dots and
@@ -134,12 +148,15 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
                            int A_on_device, const hom_options* opt, hom_cell** out);
 
 /* Solve L load cases.
- *  E        [L][d] host, macroscopic gradients (Sec. 1, the split e = E + e~)
+ *  E        [L][d] host, macroscopic gradients (Sec. 1, the split e = E + e~);
+ *           elastic cells: [L][m] Mandel strains
  *  tol      stopping test ||r_i|| / ||r_0|| <= tol (HOM_FP64) or the FP64
  *           residual ||b - Op x|| / ||b|| <= tol (HOM_MIXED); tol > 0
  *  strain   nullable device pointer, [L][d][N grid] FP64: total strain E + e~
+ *           (elastic cells: [L][m][N grid])
  *  W        nullable host pointer, [L][L] energies (A_H when E = I)
- *  J        nullable host pointer, [L][d] mean fluxes <A (E_l + e~_l)>
+ *  J        nullable host pointer, [L][d] mean fluxes <A (E_l + e~_l)> (elastic
+ *           cells: [L][m] mean stresses)
  *  strain0  nullable device pointer [L][d][N grid] FP64: warm start; its
  *           E_N component is used (re-projected by G, Sec. 5.3 Lemma)
  *  info     nullable

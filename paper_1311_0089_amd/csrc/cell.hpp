@@ -54,7 +54,9 @@ struct CellImpl {
   int Q[3] = {1, 1, 1};       // quadrature grid
   int scheme = HOM_GANI, kind = HOM_A_ISO, nA = 1;
   int dual = 0;               // dual (flux) problem on J_N
-  int npot = 1;               // potentials per frequency (2: 3-D dual)
+  int npot = 1;               // potentials per frequency (2: 3-D dual; d: elasticity)
+  int nf = 2;                 // field components: dd, or dd(dd+1)/2 (elasticity)
+  int elastic = 0;            // linear elasticity (kind HOM_A_ELASTIC)
   double Y[3] = {0.5, 0.5, 0.5};
   hom_options opt{};
   double rhoA = 1.0;

@@ -223,6 +223,48 @@ __device__ __forceinline__ T dual3_comp(const NormalGeo& g, int k0, int col, int
   return ((comp == j ? s : T(0)) - xc * xj) * inv_sqrt(s * m);
 }
 
+// Elasticity: the compatible strains of frequency k != 0 are the Mandel
+// vectors of sym(xi (x) u), u in C^d.  With K = (|xi|^2 I + xi xi^T) / 2
+// (|sym(xi (x) u)|^2 = u^T K u), the columns b_p = sym(xi (x) K^-1/2 e_p),
+// K^-1/2 = (sqrt 2 (I - n n^T) + n n^T) / |xi|, are an orthonormal basis;
+// in terms of n = xi / |xi| alone:
+//   b_p[aa] = sqrt 2 n_a [a = p] + (1 - sqrt 2) n_p n_a^2,
+//   b_p[ab] = n_a [b = p] + n_b [a = p] + (sqrt 2 - 2) n_p n_a n_b  (a != b),
+// Mandel order 11, 22, (33, 23, 13,) 12.  Every b_p is odd in k.  Component
+// comp of b_pot; 0 at k = 0.
+template <class T>
+__device__ __forceinline__ T elastic_comp(const NormalGeo& g, int k0, int col, int comp, int pot) {
+  T x[3] = {T(k0 * g.invY[0]), T(0), T(0)};
+  if (g.d == 3) {
+    x[1] = T(kof(col / g.H, g.N1) * g.invY[1]);
+    x[2] = T((col % g.H) * g.invY[2]);
+  } else {
+    x[1] = T(col * g.invY[1]);
+  }
+  const T s = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  if (!(s > T(0))) return T(0);
+  const T r = inv_sqrt(s);
+  const T n[3] = {x[0] * r, x[1] * r, x[2] * r};
+  // Mandel pair (a, b) of component comp
+  int a, b;
+  if (g.d == 2) {
+    a = (comp == 1) ? 1 : 0;
+    b = (comp == 0) ? 0 : 1;
+  } else {
+    a = (comp < 3) ? comp : (comp == 3) ? 1 : 0;
+    b = (comp < 3) ? comp : (comp == 5) ? 1 : 2;
+  }
+  const T sq2 = T(1.4142135623730951);
+  if (a == b) return (a == pot ? sq2 * n[a] : T(0)) + (T(1) - sq2) * n[pot] * n[a] * n[a];
+  return (b == pot ? n[a] : T(0)) + (a == pot ? n[b] : T(0)) + (sq2 - T(2)) * n[pot] * n[a] * n[b];
+}
+
+// basis component of a cell with several potentials per frequency
+template <class T>
+__device__ __forceinline__ T pot_comp(const NormalGeo& g, int k0, int col, int comp, int pot) {
+  return g.elastic ? elastic_comp<T>(g, k0, col, comp, pot) : dual3_comp<T>(g, k0, col, comp, pot);
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[NT / 64];
@@ -376,7 +418,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
-  for (int al0 = 0; al0 < a.g.d; al0 += CPN) {
+  for (int al0 = 0; al0 < a.g.nf; al0 += CPN) {
     constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     if (n_fft != n_in) {
       for (int f = threadIdx.x; f < n_fft * LW; f += NT) lds[f] = cpx<T>{T(0), T(0)};
@@ -387,16 +429,21 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
       int i, w;
       if (pos(it, i, w)) {
         const int row = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
-        if (multi && a.g.npot == 2) {
-          // 3-D dual (generic kernels only): X_a = t1_a c_1 + t2_a c_2
+        if (multi && a.g.npot > 1) {
+          // several potentials (3-D dual, elasticity; generic kernels only):
+          // X_a = sum_p b_p[a] c_p
           const int col = min(col0 + w, a.inner - 1);
-          const cpx<T> s1 = (w < ncols) ? a.c[ibase + a.g.pot_stride + (long)min(i, n_in - 1) * a.si +
-                                                (long)col * a.sc_]
-                                          : cpx<T>{T(0), T(0)};
           for (int c = 0; c < nc; ++c) {
-            const cpx<T> u = cscale(s[it], dual3_comp<T>(a.g, kof(i, n_in), col, al0 + c, 0));
-            const cpx<T> v = cscale(s1, dual3_comp<T>(a.g, kof(i, n_in), col, al0 + c, 1));
-            lds[row * LW + c * W + w] = cpx<T>{u.x + v.x, u.y + v.y};
+            cpx<T> u = cscale(s[it], pot_comp<T>(a.g, kof(i, n_in), col, al0 + c, 0));
+            for (int pt = 1; pt < a.g.npot; ++pt) {
+              const cpx<T> sp = (w < ncols) ? a.c[ibase + pt * a.g.pot_stride +
+                                                  (long)min(i, n_in - 1) * a.si + (long)col * a.sc_]
+                                            : cpx<T>{T(0), T(0)};
+              const cpx<T> v = cscale(sp, pot_comp<T>(a.g, kof(i, n_in), col, al0 + c, pt));
+              u.x += v.x;
+              u.y += v.y;
+            }
+            lds[row * LW + c * W + w] = u;
           }
           continue;
         }
@@ -510,8 +557,8 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
-  // two potentials per frequency (3-D dual, generic kernels only): each is
-  // projected in turn, the transforms of the components repeated
+  // several potentials per frequency (3-D dual, elasticity; generic kernels
+  // only): each is projected in turn, the transforms of the components repeated
   const int npot = (P::WC == 0) ? a.g.npot : 1;
   double part = 0.0;
   for (int pot = 0; pot < npot; ++pot) {
@@ -583,9 +630,9 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
           const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
           for (int c = 0; c < nc; ++c) {
             const cpx<T> v = lds[row * LW + c * W + w];
-            const T nvc = (npot == 2) ? dual3_comp<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1),
-                                                      al0 + c, pot)
-                                      : normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
+            const T nvc = (npot > 1) ? pot_comp<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1),
+                                                   al0 + c, pot)
+                                     : normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
             acc[it].x += nvc * v.x;
             acc[it].y += nvc * v.y;
           }
@@ -656,15 +703,16 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
 // ---------------------------------------------------------------------------
 // last (contiguous) axis: pairs of rows packed as one complex line
 // ---------------------------------------------------------------------------
-// stored components of A per point: 1 (isotropic), d (diagonal) or d(d+1)/2
-// (symmetric, order 00 11 [22 12 02] 01)
+// stored components of A per point: 1 (isotropic), d (diagonal), d(d+1)/2
+// (symmetric, order 00 11 [22 12 02] 01) or 2 (isotropic elasticity: lambda,
+// mu; d is then the Mandel component count 3 or 6)
 __device__ __forceinline__ int coef_count(int kind, int d) {
-  return kind == 0 ? 1 : kind == 1 ? d : d * (d + 1) / 2;
+  return kind == 0 ? 1 : kind == 1 ? d : kind == 3 ? 2 : d * (d + 1) / 2;
 }
 
 template <class T>
 __device__ __forceinline__ void load_coef(int kind, int d, const T* A, long Acs, long off, T* c) {
-  const int na = coef_count(kind, d), namax = (d == 3) ? 6 : (d == 2) ? 3 : 1;
+  const int na = coef_count(kind, d), namax = (d >= 3) ? 6 : (d == 2) ? 3 : 1;
 #pragma unroll
   for (int q = 0; q < 6; ++q)
     if (q < namax && q < na) c[q] = A[q * Acs + off];
@@ -677,6 +725,13 @@ __device__ __forceinline__ void flux_coef(int kind, int d, const T* c, const T* 
     for (int q = 0; q < d; ++q) j[q] = c[0] * e[q];
   } else if (kind == 1) {
     for (int q = 0; q < d; ++q) j[q] = c[q] * e[q];
+  } else if (kind == 3) {
+    // sigma = lambda tr(eps) I + 2 mu eps on Mandel vectors of d = 3 (plane
+    // strain) or 6 components, the normal components first
+    const int dim = (d == 6) ? 3 : 2;
+    T tr = T(0);
+    for (int q = 0; q < dim; ++q) tr += e[q];
+    for (int q = 0; q < d; ++q) j[q] = T(2) * c[1] * e[q] + (q < dim ? c[0] * tr : T(0));
   } else if (d == 1) {
     j[0] = c[0] * e[0];
   } else if (d == 2) {
@@ -804,7 +859,9 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
           const int lp = f / n, x = f % n;
           const int r0 = 2 * (pair0 + lp);
           if (r0 >= a.rows) return;
-          T e0[3], e1[3], j0[3], j1[3];
+          // the generic kernel serves elasticity too: up to 6 components
+          constexpr int DM = (P::DD > 0) ? 3 : 6;
+          T e0[DM], e1[DM], j0[DM], j1[DM];
           if (MODE == ROW_CONST) {
             const double* E = a.E + (long)item * d;
             for (int q = 0; q < d; ++q) e0[q] = e1[q] = T(E[q]);

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_sym_h0(SymArgs<T> a) {
     const int i0 = (int)(pi / a.N1), i1 = (int)(pi % a.N1);
     const int m0 = i0 ? a.N0 - i0 : 0, m1 = i1 ? a.N1 - i1 : 0;
     if ((long)m0 * a.N1 + m1 < pi) continue;   // the pair's first element takes it
-    const T sg = (a.npot == 2 && pot == 1) ? T(1) : T(-1);
+    const T sg = (pot == a.even_pot) ? T(1) : T(-1);
     const long base = (long)item * a.stride + pot * a.pot_stride;
     const long e = base + i0 * a.s0 + i1 * a.s1, em = base + m0 * a.s0 + m1 * a.s1;
 #pragma unroll
@@ -503,7 +503,7 @@ constexpr int kRangeBlocks = 1024;
 
 __global__ __launch_bounds__(kThreads) void k_a_range(const double* A, int d, int kind, long npts,
                                                       double* out) {
-  const int nA = (kind == 0) ? 1 : (kind == 1) ? d : d * (d + 1) / 2;
+  const int nA = coef_values(kind, d);
   double lo = INFINITY, hi = 0.0;
   int flags = 0;
   for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
@@ -576,9 +576,10 @@ __global__ __launch_bounds__(kThreads) void k_quad(const double* e, long es, lon
                                                    double* partials) {
   // D components and at most 3 x 3 load-case pairs: every loop has a
   // compile-time bound, so the accumulators stay in registers
-  double acc[18];   // W slots l * 3 + m, then J slots 9 + m * 3 + q
+  constexpr int NS = 9 + 3 * D;   // W slots l * 3 + m, then J slots 9 + m * D + q
+  double acc[NS];
 #pragma unroll
-  for (int t = 0; t < 18; ++t) acc[t] = 0.0;
+  for (int t = 0; t < NS; ++t) acc[t] = 0.0;
   for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
        p += (long)gridDim.x * blockDim.x) {
     double c[6];
@@ -591,12 +592,12 @@ __global__ __launch_bounds__(kThreads) void k_quad(const double* e, long es, lon
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (m >= nm) break;
-      double em[D], jm[3];
+      double em[D], jm[D];
 #pragma unroll
       for (int q = 0; q < D; ++q) em[q] = e[(m0 + m) * es + q * ecs + p];
       flux_coef<double>(kind, D, c, em, jm);
 #pragma unroll
-      for (int q = 0; q < D; ++q) acc[9 + m * 3 + q] += jm[q];
+      for (int q = 0; q < D; ++q) acc[9 + m * D + q] += jm[q];
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
         double sum = 0.0;
@@ -607,19 +608,19 @@ __global__ __launch_bounds__(kThreads) void k_quad(const double* e, long es, lon
     }
   }
   // per wave, then across the waves in order (one barrier)
-  __shared__ double red[kThreads / 64][18];
+  __shared__ double red[kThreads / 64][NS];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < 18; ++t) {
+  for (int t = 0; t < NS; ++t) {
     double v = acc[t];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     if (lane == 0) red[wid][t] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 18) {
+  if (threadIdx.x < NS) {
     double v = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
-    partials[(long)blockIdx.x * 18 + threadIdx.x] = v;
+    partials[(long)blockIdx.x * kQuadSlots + threadIdx.x] = v;
   }
 }
 
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_quad_final(const double* partials,
   // workgroup t: out[t], t < 9 a W slot (3x3), t >= 9 a J sum, divided by npts
   const int t = blockIdx.x;
   double v = 0.0;
-  for (int b = threadIdx.x; b < blocks; b += blockDim.x) v += partials[(long)b * 18 + t];
+  for (int b = threadIdx.x; b < blocks; b += blockDim.x) v += partials[(long)b * kQuadSlots + t];
   v = block_sum<kThreads>(v);
   if (threadIdx.x == 0) out[t] = v / (double)npts;
 }
@@ -834,6 +835,8 @@ hipError_t launch_quad(const double* e, long e_stride, long e_cstride, const dou
                      A_cstride, kind, npts, l0, nl, m0, nm, partials); break;
     case 3: launch_k(k_quad<3>, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
                      A_cstride, kind, npts, l0, nl, m0, nm, partials); break;
+    case 6: launch_k(k_quad<6>, dim3(blocks), dim3(kThreads), 0, s, e, e_stride, e_cstride, A,
+                     A_cstride, kind, npts, l0, nl, m0, nm, partials); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -842,8 +845,7 @@ hipError_t launch_quad_final(const double* partials, int blocks, int nl, int nm,
                              double* out, hipStream_t s) {
   (void)nl;
   (void)nm;
-  (void)d;
-  launch_k(k_quad_final, dim3(18), dim3(kThreads), 0, s, partials, blocks, npts, out);
+  launch_k(k_quad_final, dim3(9 + 3 * d), dim3(kThreads), 0, s, partials, blocks, npts, out);
   return hipGetLastError();
 }
 hipError_t launch_convert(const double* in, float* out, long n, hipStream_t s) {

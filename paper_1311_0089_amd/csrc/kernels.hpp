@@ -81,8 +81,10 @@ struct NormalGeo {
   int N1;        // trial size of axis 1 (3-D only)
   int H;         // half-spectrum bins of the last axis
   int dual;      // dual problem on J_N (2-D: the rotated normal t = (-n_1, n_0))
-  int npot;      // potentials per frequency: 1, or 2 for the 3-D dual problem
+  int npot;      // potentials per frequency: 1; 2 (3-D dual); d (elasticity)
   long pot_stride;   // elements between the potentials of an item
+  int nf;        // field components: d, or d(d+1)/2 Mandel components (elasticity)
+  int elastic;   // linear elasticity: compatible strains, potentials = displacements
   double invY[3];
 };
 
@@ -272,6 +274,7 @@ struct SymArgs {
   long stride;          // item stride
   long pot_stride;      // between the potentials of an item
   int npot;             // potentials per frequency
+  int even_pot;         // the potential whose basis vector is even in k (-1: none)
   int N0, N1;           // extents of the plane (2-D cells: N1 = 1)
   long s0, s1;          // element strides of the plane's two axes
   const ItemScal* sc;   // selection (null: every item; else item_live_project)
@@ -288,9 +291,21 @@ hipError_t launch_norm_parts(const cpx<T>* v, long stride, long count, int n0, i
 // Eigenvalue range [lo, hi] of the coefficient at one point (v holds its
 // nA values: kind 0 a I, kind 1 diagonal, kind 2 symmetric in Voigt order);
 // false if a value is not finite or the matrix is not positive definite.
+__host__ __device__ inline int coef_values(int kind, int d) {
+  return kind == 0 ? 1 : kind == 1 ? d : kind == 3 ? 2 : d * (d + 1) / 2;
+}
+
 __host__ __device__ inline bool point_range(int d, int kind, const double* v, double* lo, double* hi) {
-  for (int t = 0; t < (kind == 0 ? 1 : kind == 1 ? d : d * (d + 1) / 2); ++t)
+  for (int t = 0; t < coef_values(kind, d); ++t)
     if (!isfinite(v[t])) return false;
+  if (kind == 3) {
+    // isotropic elasticity (lambda, mu) in d dimensions: the Mandel stiffness
+    // has the eigenvalues 2 mu and d lambda + 2 mu
+    const double a = 2.0 * v[1], b = d * v[0] + 2.0 * v[1];
+    *lo = fmin(a, b);
+    *hi = fmax(a, b);
+    return *lo > 0;
+  }
   if (kind == 0) {
     *lo = *hi = v[0];
     return v[0] > 0;
@@ -348,7 +363,8 @@ __host__ __device__ inline bool point_range(int d, int kind, const double* v, do
 // scratch: device buffer of kQuadScratch doubles; host: pinned host buffer
 // of at least 3 * 1024 doubles.
 constexpr int kQuadBlocks = 2048;   // workgroups of the energy quadrature
-constexpr long kQuadScratch = (long)kQuadBlocks * 18 + 64;
+constexpr int kQuadSlots = 27;      // per workgroup: 3 x 3 W slots and 3 x (up to 6) J sums
+constexpr long kQuadScratch = (long)kQuadBlocks * kQuadSlots + 64;
 hipError_t a_field_range(const double* A, int d, int kind, long npts, double* scratch,
                          double* host, hipStream_t s, double* lo, double* hi, int* flags);
 

@@ -330,10 +330,10 @@ hipError_t hom_server::retire(SizeClass* k, int s) {
       const int nm = std::min(3, L - m0);
       err = launch_quad(k->ebuf, (long)dd * e->nQ, e->nQ, A, e->nQ, e->kind, dd, e->nQ, l0, nl,
                         m0, nm, e->quad, blocks, e->stream);
-      double* outp = e->quad + (size_t)kQuadBlocks * 18;
+      double* outp = e->quad + (size_t)kQuadBlocks * kQuadSlots;
       if (err == hipSuccess)
         err = launch_quad_final(e->quad, blocks, nl, nm, dd, e->nQ, outp, e->stream);
-      double h[18];
+      double h[kQuadSlots];
       if (err == hipSuccess)
         err = hipMemcpyAsync(h, outp, sizeof(h), hipMemcpyDeviceToHost, e->stream);
       if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
@@ -342,7 +342,7 @@ hipError_t hom_server::retire(SizeClass* k, int s) {
         for (int m = 0; m < nm; ++m) hW[(size_t)(l0 + l) * L + m0 + m] = h[l * 3 + m];
       if (l0 == 0)
         for (int m = 0; m < nm; ++m)
-          for (int a = 0; a < dd; ++a) hJ[(size_t)(m0 + m) * dd + a] = h[9 + m * 3 + a];
+          for (int a = 0; a < dd; ++a) hJ[(size_t)(m0 + m) * dd + a] = h[9 + m * dd + a];
     }
   }
   if (err != hipSuccess) return err;
@@ -518,7 +518,8 @@ hom_status hom_server_submit(hom_server* s, hom_cell* c, int L, const double* E,
   if (!s || !c || !E || !ticket || L < 1 || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
   CellImpl* cell = c->impl;
   if (L > cell->dd) return HOM_EINVAL;  // a slot holds at most d load cases
-  if (cell->dual) return HOM_EINVAL;    // size classes batch primal cells only
+  // size classes batch primal scalar cells only
+  if (cell->dual || cell->elastic) return HOM_EINVAL;
   for (int i = 0; i < L * cell->d; ++i)
     if (!std::isfinite(E[i])) return HOM_EINVAL;
   if (cell->device != s->device) return HOM_EINVAL;

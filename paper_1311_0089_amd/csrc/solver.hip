@@ -198,7 +198,9 @@ hipError_t cell_setup(CellImpl* c) {
   }
   // the 3-D dual problem has two potentials per frequency, stored one after
   // the other: every CG vector kernel sees them as one spectrum of 2S elements
-  c->npot = (c->dual && dd == 3) ? 2 : 1;
+  c->elastic = (c->kind == HOM_A_ELASTIC);
+  c->npot = c->elastic ? dd : (c->dual && dd == 3) ? 2 : 1;
+  c->nf = c->elastic ? dd * (dd + 1) / 2 : dd;
   c->S *= c->npot;
   // plans for every length used
   const DevPlan* p = nullptr;
@@ -214,11 +216,11 @@ hipError_t ensure_work(CellImpl* c, int items, bool need32) {
   hipError_t e = hipSuccess;
   bool realloc = false;
   if (c->w64.items < items) {
-    if ((e = c->w64.alloc(items, c->S, c->Xe, c->dd, P)) != hipSuccess) return e;
+    if ((e = c->w64.alloc(items, c->S, c->Xe, c->nf, P)) != hipSuccess) return e;
     realloc = true;
   }
   if (need32 && c->w32.items < items) {
-    if ((e = c->w32.alloc(items, c->S, c->Xe, c->dd, P)) != hipSuccess) return e;
+    if ((e = c->w32.alloc(items, c->S, c->Xe, c->nf, P)) != hipSuccess) return e;
     realloc = true;
   }
   if (realloc) {
@@ -239,6 +241,8 @@ static NormalGeo normal_geo(const CellImpl* c) {
   g.dual = c->dual;
   g.npot = c->npot;
   g.pot_stride = c->S / c->npot;
+  g.nf = c->nf;
+  g.elastic = c->elastic;
   for (int a = 0; a < 3; ++a) g.invY[a] = 1.0 / c->Y[a];
   return g;
 }
@@ -275,7 +279,7 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.c_stride = c->S;
   a.si = scalar_si(c);
   a.sc_ = scalar_sc(c);
-  a.X_stride = (long)c->dd * c->Xe;
+  a.X_stride = (long)c->nf * c->Xe;
   a.X_cstride = c->Xe;
   a.n_in = c->N[0];
   a.n_fft = G0;
@@ -306,14 +310,14 @@ static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int 
   ColPlainArgs<T> a{};
   a.in = in;
   a.out = out;
-  a.in_stride = a.out_stride = (long)c->dd * c->Xe;
+  a.in_stride = a.out_stride = (long)c->nf * c->Xe;
   a.in_cstride = a.out_cstride = c->Xe;
   a.outer = G0;
   a.n_fft = G1;
   a.n_in = (sign > 0) ? c->N[1] : G1;
   a.n_out = (sign > 0) ? G1 : c->N[1];
   a.inner = c->H;
-  a.d = c->dd;
+  a.d = c->nf;
   a.scale = (sign > 0) ? T(1) : T(1.0 / (double)G1);
   a.plan = p1->p;
   a.tw = tw_of<T>(p1);
@@ -342,20 +346,20 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   RowArgs<T> a{};
   a.in = in;
   a.out = out;
-  a.in_stride = a.out_stride = (long)c->dd * c->Xe;
+  a.in_stride = a.out_stride = (long)c->nf * c->Xe;
   a.in_cstride = a.out_cstride = c->Xe;
   const long rows = (c->dd == 3) ? (long)G0 * G1 : G0;
   a.ureal = ureal;
   a.oreal = oreal;
   a.real_cstride = rows * Glast;
-  a.real_stride = (long)c->dd * a.real_cstride;
+  a.real_stride = (long)c->nf * a.real_cstride;
   a.A = (sizeof(T) == 8) ? (const T*)(const void*)c->A64 : (const T*)(const void*)c->A32;
   a.A_stride = c->A_block;
   a.A_group = c->A_group;
   a.A_cstride = c->nQ;
   a.kind = c->kind;
   a.E = dE;
-  a.d = c->dd;
+  a.d = c->nf;
   a.rows = (int)rows;
   a.n = Glast;
   a.H = c->H;
@@ -366,7 +370,8 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
                  : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
   const StaticKernel* sk =
-      (kind >= 0) ? find_static(kind, sizeof(cpx<T>), Glast, Nlast, c->dd, pl->p) : nullptr;
+      (kind >= 0 && !c->elastic) ? find_static(kind, sizeof(cpx<T>), Glast, Nlast, c->dd, pl->p)
+                                 : nullptr;
   if (sk) {
     a.RP = sk->W;
     return launch_row<T>(a, items, mode, sk->lds, c->stream, sk);
@@ -379,7 +384,7 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   if (sizeof(T) == 8 && pl->p.blue && mode != ROW_FWD) return hipErrorNotSupported;
   size_t lds = 0;
   int RP = 0;
-  if ((e = row_shape(pl->p, c->dd, rows, sizeof(cpx<T>), &RP, &lds)) != hipSuccess) return e;
+  if ((e = row_shape(pl->p, c->nf, rows, sizeof(cpx<T>), &RP, &lds)) != hipSuccess) return e;
   a.RP = RP;
   return launch_row<T>(a, items, mode, lds, c->stream);
 }
@@ -395,7 +400,7 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   (void)w;
   ColProjectArgs<T> a{};
   a.X = X;
-  a.X_stride = (long)c->dd * c->Xe;
+  a.X_stride = (long)c->nf * c->Xe;
   a.X_cstride = c->Xe;
   a.q = out;
   a.s_stride = c->S;
@@ -412,7 +417,7 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.n_out = c->N[0];
   a.inner = (int)inner0(c);
   a.epi = epi;
-  a.d = c->dd;
+  a.d = c->nf;
   if (cg) {
     a.rr_part = cg->rr;
     a.rr_n = cg->rr_n;
@@ -497,6 +502,7 @@ hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemSc
   sa.v[2] = w.p;
   sa.stride = c->S;
   sa.npot = c->npot;
+  sa.even_pot = (c->dual && c->dd == 3) ? 1 : -1;   // t_2 of the 3-D dual
   sa.pot_stride = c->S / c->npot;
   sa.N0 = c->N[0];
   sa.N1 = (c->dd == 3) ? c->N[1] : 1;
@@ -540,12 +546,12 @@ hipError_t pipe_project_real(CellImpl* c, Work<double>& w, int items, const doub
     ColPlainArgs<double> a{};
     a.in = w.X2;
     a.out = w.X1;
-    a.in_stride = a.out_stride = (long)c->dd * c->Xe;
+    a.in_stride = a.out_stride = (long)c->nf * c->Xe;
     a.in_cstride = a.out_cstride = c->Xe;
     a.outer = N0;
     a.n_in = a.n_fft = a.n_out = N1;
     a.inner = c->H;
-    a.d = c->dd;
+    a.d = c->nf;
     a.scale = 1.0 / (double)N1;
     a.plan = p1->p;
     a.tw = p1->tw64;
@@ -828,17 +834,22 @@ static hipError_t cg_run(CellImpl* c, int items, int max_iter, std::vector<ItemS
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// components of a load case, a strain field or a mean flux as the caller
+// sees them: d, or the d(d+1)/2 Mandel components of an elastic cell
+static int user_comps(const CellImpl* c) { return c->elastic ? c->nf : c->d; }
+
 // the load cases on the device, in the cell's persistent buffer
 static hipError_t upload_E(CellImpl* c, int L, const double* E, double** dE) {
-  // [L][dd] with zero padding for d = 1
-  std::vector<double> h((size_t)L * c->dd, 0.0);
+  // [L][nf] with zero padding for d = 1 (E holds L x user_comps(c) values)
+  const int nu = user_comps(c);
+  std::vector<double> h((size_t)L * c->nf, 0.0);
   for (int l = 0; l < L; ++l)
-    for (int a = 0; a < c->d; ++a) h[(size_t)l * c->dd + a] = E[(size_t)l * c->d + a];
+    for (int a = 0; a < nu; ++a) h[(size_t)l * c->nf + a] = E[(size_t)l * nu + a];
   if (c->dE_items < L) {
     if (c->dE) (void)hipFree(c->dE);
     c->dE = nullptr;
     c->dE_items = 0;
-    hipError_t e = hipMalloc(&c->dE, sizeof(double) * 3 * std::max(L, 8));
+    hipError_t e = hipMalloc(&c->dE, sizeof(double) * 6 * std::max(L, 8));
     if (e != hipSuccess) return e;
     c->dE_items = std::max(L, 8);
   }
@@ -868,7 +879,7 @@ static hipError_t ensure_ebuf(CellImpl* c, int items) {
   if (c->ebuf) (void)hipFree(c->ebuf);
   c->ebuf = nullptr;
   c->ebuf_items = 0;
-  hipError_t e = hipMalloc(&c->ebuf, sizeof(double) * (size_t)items * c->dd * c->nQ);
+  hipError_t e = hipMalloc(&c->ebuf, sizeof(double) * (size_t)items * c->nf * c->nQ);
   if (e == hipSuccess) c->ebuf_items = items;
   return e;
 }
@@ -891,19 +902,19 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
     if ((e = hipMalloc(&c->quad, sizeof(double) * kQuadScratch)) != hipSuccess) return e;
   }
   const int blocks = (int)std::min<long>(kQuadBlocks, (c->nQ + kThreads - 1) / kThreads);
-  std::vector<double> hW((size_t)L * L, 0.0), hJ((size_t)L * c->dd, 0.0);
+  std::vector<double> hW((size_t)L * L, 0.0), hJ((size_t)L * c->nf, 0.0);
   for (int l0 = 0; l0 < L; l0 += 3) {
     const int nl = std::min(3, L - l0);
     for (int m0 = 0; m0 < L; m0 += 3) {
       const int nm = std::min(3, L - m0);
-      if ((e = launch_quad(eQ, (long)c->dd * c->nQ, c->nQ, c->A64, c->nQ, c->kind, c->dd, c->nQ,
+      if ((e = launch_quad(eQ, (long)c->nf * c->nQ, c->nQ, c->A64, c->nQ, c->kind, c->nf, c->nQ,
                            l0, nl, m0, nm, c->quad, blocks, c->stream)) != hipSuccess)
         return e;
-      double* outp = c->quad + (size_t)kQuadBlocks * 18;
-      if ((e = launch_quad_final(c->quad, blocks, nl, nm, c->dd, c->nQ, outp, c->stream)) !=
+      double* outp = c->quad + (size_t)kQuadBlocks * kQuadSlots;
+      if ((e = launch_quad_final(c->quad, blocks, nl, nm, c->nf, c->nQ, outp, c->stream)) !=
           hipSuccess)
         return e;
-      double h[18];
+      double h[kQuadSlots];
       void* hp = nullptr;
       if ((e = pinned(c, sizeof(h), &hp)) != hipSuccess) return e;
       if ((e = hipMemcpyAsync(hp, outp, sizeof(h), hipMemcpyDeviceToHost, c->stream)) !=
@@ -915,13 +926,14 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
         for (int m = 0; m < nm; ++m) hW[(size_t)(l0 + l) * L + m0 + m] = h[l * 3 + m];
       if (l0 == 0)
         for (int m = 0; m < nm; ++m)
-          for (int a = 0; a < c->dd; ++a) hJ[(size_t)(m0 + m) * c->dd + a] = h[9 + m * 3 + a];
+          for (int a = 0; a < c->nf; ++a) hJ[(size_t)(m0 + m) * c->nf + a] = h[9 + m * c->nf + a];
     }
   }
   if (W) std::memcpy(W, hW.data(), sizeof(double) * hW.size());
   if (J)
     for (int l = 0; l < L; ++l)
-      for (int a = 0; a < c->d; ++a) J[(size_t)l * c->d + a] = hJ[(size_t)l * c->dd + a];
+      for (int a = 0; a < user_comps(c); ++a)
+        J[(size_t)l * user_comps(c) + a] = hJ[(size_t)l * c->nf + a];
   if (strain_user && eQ != strain_user) {
     if (gani && c->d == c->dd) {
       // unreachable: handled above
@@ -933,7 +945,7 @@ static hipError_t homogenize(CellImpl* c, int L, const double* dE, double* strai
         if ((e = pipe_synth(c, c->w64, L, x, dE, false, c->ebuf)) != hipSuccess) return e;
       }
       for (int l = 0; l < L; ++l) {
-        const double* src = c->ebuf + (size_t)l * c->dd * (gani ? c->nQ : c->nN);
+        const double* src = c->ebuf + (size_t)l * c->nf * (gani ? c->nQ : c->nN);
         if ((e = hipMemcpyAsync(strain_user + (size_t)l * c->nN, src, sizeof(double) * c->nN,
                                 hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
           return e;
@@ -1066,6 +1078,7 @@ static bool fp64_rows_served(const CellImpl* c) {
     const DevPlan* pl = nullptr;
     if (get_dev_plan(lens[i], &pl) != hipSuccess) return false;
     if (!pl->p.blue) continue;
+    if (c->elastic) return false;   // elastic cells run the generic rows only
     for (int k : {KK_ROW, KK_ROW_CONST, KK_ROW_SYNTH}) {
       if (i == 1 && k != KK_ROW_SYNTH) continue;
       if (!find_static(k, (int)sizeof(cpx<double>), lens[i], Nl, c->dd, pl->p)) return false;
@@ -1087,7 +1100,7 @@ static void wait_user_stream(CellImpl* c) {
 hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const double* A,
                            int A_on_device, const hom_options* opt, hom_cell** out) {
   if (!out || !N || !A || d < 1 || d > 3) return HOM_EINVAL;
-  if (kind < HOM_A_ISO || kind > HOM_A_FULLSYM) return HOM_EINVAL;
+  if (kind < HOM_A_ISO || kind > HOM_A_ELASTIC) return HOM_EINVAL;
   *out = nullptr;
   hom_options o;
   if (opt)
@@ -1100,6 +1113,9 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   if (!(o.inner_tol > 0 && o.inner_tol < 1)) return HOM_EINVAL;
   if (o.a_trig != 0 && (o.a_trig != 1 || o.scheme != HOM_GA)) return HOM_EINVAL;
   if (o.dual != 0 && (o.dual != 1 || d < 2)) return HOM_EINVAL;
+  // linear elasticity: d = 2 (plane strain) or 3, primal problem, sampled
+  // Lame fields
+  if (kind == HOM_A_ELASTIC && (d < 2 || o.dual || o.a_trig)) return HOM_EINVAL;
   for (int a = 0; a < d; ++a) {
     if (N[a] < 1 || (N[a] % 2) == 0 || N[a] > (1 << 20)) return HOM_EINVAL;
     if (!(o.Y[a] > 0) || !std::isfinite(o.Y[a])) return HOM_EINVAL;
@@ -1110,7 +1126,8 @@ hom_status hom_create_cell(int d, const int32_t* N, hom_a_kind kind, const doubl
   key.dd = d < 2 ? 2 : d;
   key.scheme = o.scheme;
   key.dual = o.dual;
-  const int nA_user = (kind == HOM_A_ISO) ? 1 : (kind == HOM_A_DIAG) ? d : d * (d + 1) / 2;
+  const int nA_user = (kind == HOM_A_ISO) ? 1 : (kind == HOM_A_DIAG) ? d
+                    : (kind == HOM_A_ELASTIC) ? 2 : d * (d + 1) / 2;
   // d = 1 runs as a 2-D cell with a single grid point along the second axis;
   // its one coefficient acts as an isotropic one (e_2 vanishes identically)
   key.kind = (d == 1) ? HOM_A_ISO : kind;
@@ -1226,7 +1243,7 @@ hom_status hom_solve(hom_cell* hc, int L, const double* E, double tol, double* s
                      double* J, const double* strain0, hom_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   if (!hc || L < 1 || !E || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
-  for (int i = 0; i < L * hc->impl->d; ++i)
+  for (int i = 0; i < L * user_comps(hc->impl); ++i)
     if (!std::isfinite(E[i])) return HOM_EINVAL;
   CellImpl* c = hc->impl;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -1398,7 +1415,7 @@ hom_status hom_solve_ms(hom_cell* hc, int L, const double* E, double tol, double
                         double* W, double* J, hom_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   if (!hc || L < 1 || !E || !(tol > 0) || !std::isfinite(tol)) return HOM_EINVAL;
-  for (int i = 0; i < L * hc->impl->d; ++i)
+  for (int i = 0; i < L * user_comps(hc->impl); ++i)
     if (!std::isfinite(E[i])) return HOM_EINVAL;
   CellImpl* c = hc->impl;
   // lambda = (c_A + C_A) / 2 needs a positive lower eigenvalue bound
@@ -1460,7 +1477,7 @@ hom_status hom_apply(hom_cell* hc, hom_prec prec, int L, const double* u, double
   wait_user_stream(c);
   Work<double>& w = c->w64;
   double* dE = nullptr;
-  std::vector<double> zero((size_t)L * c->d, 0.0);
+  std::vector<double> zero((size_t)L * user_comps(c), 0.0);
   do {
     if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
     if ((e = pipe_project_real(c, w, L, u, w.x)) != hipSuccess) break;
@@ -1493,7 +1510,7 @@ hom_status hom_project(hom_cell* hc, int L, const double* u, double* out) {
   if (e != hipSuccess) return dev_status(e);
   wait_user_stream(c);
   double* dE = nullptr;
-  std::vector<double> zero((size_t)L * c->d, 0.0);
+  std::vector<double> zero((size_t)L * user_comps(c), 0.0);
   do {
     if ((e = upload_E(c, L, zero.data(), &dE)) != hipSuccess) break;
     if ((e = pipe_project_real(c, c->w64, L, u, c->w64.x)) != hipSuccess) break;
@@ -1540,8 +1557,8 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // and output (HOM_MIXED), zero load cases for the synthesis
 static size_t noalloc_bytes(const CellImpl* c, int L, bool mixed) {
   const size_t sv = sizeof(cpx<double>) * (size_t)c->S * L;
-  const size_t xv = sizeof(cpx<double>) * (size_t)c->Xe * c->dd * L;
-  size_t b = 2 * align256(sv) + 2 * align256(xv) + align256(sizeof(double) * 3 * (size_t)L);
+  const size_t xv = sizeof(cpx<double>) * (size_t)c->Xe * c->nf * L;
+  size_t b = 2 * align256(sv) + 2 * align256(xv) + align256(sizeof(double) * 6 * (size_t)L);
   if (mixed) b += 2 * align256(sizeof(cpx<float>) * (size_t)c->S * L);
   return b;
 }
@@ -1567,7 +1584,7 @@ extern "C" hom_status hom_apply_noalloc(hom_cell* hc, hom_prec prec, int L, cons
     return q;
   };
   const size_t sv = sizeof(cpx<double>) * (size_t)c->S * L;
-  const size_t xv = sizeof(cpx<double>) * (size_t)c->Xe * c->dd * L;
+  const size_t xv = sizeof(cpx<double>) * (size_t)c->Xe * c->nf * L;
   Work<double> w;
   w.items = L;
   w.x = reinterpret_cast<cpx<double>*>(take(sv));
@@ -1575,7 +1592,7 @@ extern "C" hom_status hom_apply_noalloc(hom_cell* hc, hom_prec prec, int L, cons
   w.X1 = reinterpret_cast<cpx<double>*>(take(xv));
   w.X2 = reinterpret_cast<cpx<double>*>(take(xv));
   w.r = w.p = w.b = w.x;   // not read by these passes (no CG epilogue)
-  double* dE = reinterpret_cast<double*>(take(sizeof(double) * 3 * (size_t)L));
+  double* dE = reinterpret_cast<double*>(take(sizeof(double) * 6 * (size_t)L));
   Work<float> w32;
   if (mixed) {
     w32.items = L;
@@ -1594,7 +1611,7 @@ extern "C" hom_status hom_apply_noalloc(hom_cell* hc, hom_prec prec, int L, cons
   do {
     // the synthesis adds the load case, which is zero here; the array keeps
     // the last call's contents, so it is cleared on every call
-    if ((e = launch_zero(dE, 3 * (long)L, c->stream)) != hipSuccess) break;
+    if ((e = launch_zero(dE, 6 * (long)L, c->stream)) != hipSuccess) break;
     if ((e = pipe_project_real(c, w, L, u, w.x)) != hipSuccess) break;
     if (!mixed) {
       if ((e = pipe_apply<double>(c, w, L, w.x, EPI_STORE, w.q, nullptr, nullptr, nullptr,
@@ -1623,8 +1640,8 @@ template <class T>
 static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double* bytes) {
   Work<T>& w = work_of<T>(c);
   hipError_t e;
-  std::vector<double> hE((size_t)L * c->dd, 0.0);
-  for (int l = 0; l < L; ++l) hE[(size_t)l * c->dd + (l % c->dd)] = 1.0;
+  std::vector<double> hE((size_t)L * c->nf, 0.0);
+  for (int l = 0; l < L; ++l) hE[(size_t)l * c->nf + (l % c->nf)] = 1.0;
   double* dE = nullptr;
   if ((e = hipMalloc(&dE, sizeof(double) * hE.size())) != hipSuccess) return e;
   if ((e = hipMemcpy(dE, hE.data(), sizeof(double) * hE.size(), hipMemcpyHostToDevice)) !=
@@ -1725,13 +1742,13 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   // reads r, p, x and writes p, x; the expansion reads p and writes the d
   // fields; the update reads r, q, writes r
   bytes[8] = L * 5.0 * S * esz;
-  bytes[0] = L * (S * esz + (double)c->dd * Q0 * inner * esz);
+  bytes[0] = L * (S * esz + (double)c->nf * Q0 * inner * esz);
   if (c->dd == 3) {
-    bytes[1] = L * (double)c->dd * Q0 * c->H * esz * (c->N[1] + Q1);
+    bytes[1] = L * (double)c->nf * Q0 * c->H * esz * (c->N[1] + Q1);
     bytes[3] = bytes[1];
   }
-  bytes[2] = L * 2.0 * c->dd * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
-  bytes[4] = L * ((double)c->dd * Q0 * inner * esz + 2.0 * S * esz);
+  bytes[2] = L * 2.0 * c->nf * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
+  bytes[4] = L * ((double)c->nf * Q0 * inner * esz + 2.0 * S * esz);
   bytes[5] = L * 3.0 * S * esz;
   for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
   bytes[7] += bytes[8];
@@ -1781,6 +1798,9 @@ static std::vector<PassKey> pass_keys(const CellImpl* c) {
   const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
   const int Glast = (dd == 3) ? Q2 : Q1;
   std::vector<PassKey> v;
+  // elastic cells run the generic kernels of every pass but the axis-1 ones
+  // (shared with the scalar cells of the shape): nothing of theirs to tune
+  if (c->elastic) return v;
   // a cell with two potentials per frequency runs the generic expand and
   // project kernels: their variants are not its to time or force
   const bool col = (c->npot == 1);
@@ -1806,8 +1826,8 @@ template <class T>
 static hipError_t autotune_impl(CellImpl* c, int L, int reps, double* best_us) {
   Work<T>& w = work_of<T>(c);
   hipError_t e;
-  std::vector<double> hE((size_t)L * c->dd, 0.0);
-  for (int l = 0; l < L; ++l) hE[(size_t)l * c->dd + (l % c->dd)] = 1.0;
+  std::vector<double> hE((size_t)L * c->nf, 0.0);
+  for (int l = 0; l < L; ++l) hE[(size_t)l * c->nf + (l % c->nf)] = 1.0;
   double* dE = nullptr;
   if ((e = hipMalloc(&dE, sizeof(double) * hE.size())) != hipSuccess) return e;
   e = hipMemcpy(dE, hE.data(), sizeof(double) * hE.size(), hipMemcpyHostToDevice);

@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(_HERE, "libhom.so")
 
 GANI, GA = 0, 1
 FP64, MIXED = 0, 1
-ISO, DIAG, FULLSYM = 0, 1, 2
+ISO, DIAG, FULLSYM, ELASTIC = 0, 1, 2, 3
 
 EXPORTED_SYMBOLS = [
     "hom_options_default", "hom_create_cell", "hom_solve", "hom_solve_ms", "hom_apply",
@@ -145,7 +145,8 @@ class Cell:
     """A periodic cell on the current GPU.
 
     A: coefficient field [nA][Q grid] (numpy float64 on the host, or a torch
-    float64 CUDA tensor); N: odd trial sizes; kind: ISO/DIAG/FULLSYM;
+    float64 CUDA tensor); N: odd trial sizes; kind: ISO/DIAG/FULLSYM, or
+    ELASTIC (A = [lambda, mu], fields as Mandel vectors of d(d+1)/2 components);
     scheme: GANI (A on N) or GA (A on 2N-1); prec: FP64 or MIXED."""
 
     def __init__(self, A, N, kind=ISO, scheme=GANI, prec=FP64, Y=None, max_iter=10000,
@@ -153,6 +154,8 @@ class Cell:
         import torch
         self.N = tuple(int(n) for n in N)
         self.d = len(self.N)
+        # field components: d, or the d(d+1)/2 Mandel components of elasticity
+        self.nc = self.d * (self.d + 1) // 2 if kind == ELASTIC else self.d
         self.Q = tuple(2 * n - 1 for n in self.N) if scheme == GA else self.N
         self.kind, self.scheme, self.prec = kind, scheme, prec
         self._h = ctypes.c_void_p(None)
@@ -193,12 +196,12 @@ class Cell:
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         L = E.shape[0]
         W = np.zeros((L, L))
-        J = np.zeros((L, self.d))
+        J = np.zeros((L, self.nc))
         info = Info()
         strain = None
         sp = ctypes.c_void_p(None)
         if want_strain:
-            strain = torch.empty((L, self.d) + self.N, dtype=torch.float64, device="cuda")
+            strain = torch.empty((L, self.nc) + self.N, dtype=torch.float64, device="cuda")
             sp = ctypes.c_void_p(strain.data_ptr())
         s0 = ctypes.c_void_p(None)
         if strain0 is not None:
@@ -219,12 +222,12 @@ class Cell:
         E = np.ascontiguousarray(np.atleast_2d(np.asarray(E, dtype=np.float64)))
         L = E.shape[0]
         W = np.zeros((L, L))
-        J = np.zeros((L, self.d))
+        J = np.zeros((L, self.nc))
         info = Info()
         strain = None
         sp = ctypes.c_void_p(None)
         if want_strain:
-            strain = torch.empty((L, self.d) + self.N, dtype=torch.float64, device="cuda")
+            strain = torch.empty((L, self.nc) + self.N, dtype=torch.float64, device="cuda")
             sp = ctypes.c_void_p(strain.data_ptr())
         code = lib().hom_solve_ms(self._h, L, _dptr(E), float(tol), sp, _dptr(W), _dptr(J),
                                   ctypes.byref(info))
