@@ -859,8 +859,8 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
           const int lp = f / n, x = f % n;
           const int r0 = 2 * (pair0 + lp);
           if (r0 >= a.rows) return;
-          // the generic kernel serves elasticity too: up to 6 components
-          constexpr int DM = (P::DD > 0) ? 3 : 6;
+          // up to 6 components (elasticity): the compile-time count, else 6
+          constexpr int DM = (P::DD > 3) ? P::DD : (P::DD > 0) ? 3 : 6;
           T e0[DM], e1[DM], j0[DM], j1[DM];
           if (MODE == ROW_CONST) {
             const double* E = a.E + (long)item * d;

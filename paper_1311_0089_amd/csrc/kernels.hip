@@ -202,6 +202,112 @@ __global__ __launch_bounds__(kThreads) void k_sym_h0(SymArgs<T> a) {
 }
 
 template <class T>
+__global__ __launch_bounds__(kThreads) void k_basis_expand(BasisArgs<T> a) {
+  const int item = blockIdx.y;
+  if (a.sc && !item_live(a.sc[item])) return;
+  const long n = (long)a.N0 * a.inner;
+  const int npot = a.g.npot, nf = a.g.nf;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / a.inner), col = (int)(e % a.inner);
+    const int k0 = kof(i, a.N0);
+    const long src = (long)item * a.c_stride + (long)i * a.si + (long)col * a.sc_;
+    cpx<T> cp[3];
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt)
+      cp[pt] = (pt < npot) ? a.c[src + pt * a.g.pot_stride] : cpx<T>{T(0), T(0)};
+    cpx<T>* X = a.Xo + (long)item * a.X_stride + e;
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) {
+      if (comp >= nf) break;
+      cpx<T> u{T(0), T(0)};
+#pragma unroll
+      for (int pt = 0; pt < 3; ++pt) {
+        if (pt >= npot) break;
+        const T bv = pot_comp<T>(a.g, k0, col, comp, pt);
+        u.x += bv * cp[pt].x;
+        u.y += bv * cp[pt].y;
+      }
+      X[(long)comp * a.X_cstride] = u;
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_basis_project(BasisArgs<T> a) {
+  const int item = blockIdx.y;
+  if (a.sc && !item_live_project(a.sc[item])) {
+    // as the projection pass: an item whose update broke down stops here
+    const ItemScal& q0 = a.sc[item];
+    if (q0.active && q0.broke && a.rr_part && blockIdx.x == 0 && threadIdx.x == 0)
+      a.sc[item].halt = 1;
+    return;
+  }
+  const long n = (long)a.N0 * a.inner;
+  const int npot = a.g.npot, nf = a.g.nf;
+  double part = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / a.inner), col = (int)(e % a.inner);
+    const int k0 = kof(i, a.N0);
+    const int h = (a.g.d == 3) ? col % a.g.H : col;   // 2-D: the column is h
+    const double wt = (h == 0) ? 1.0 : 2.0;
+    const cpx<T>* X = a.Xi + (long)item * a.X_stride + e;
+    cpx<T> xv[6];
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp)
+      xv[comp] = (comp < nf) ? X[(long)comp * a.X_cstride] : cpx<T>{T(0), T(0)};
+#pragma unroll
+    for (int pt = 0; pt < 3; ++pt) {
+      if (pt >= npot) break;
+      cpx<T> qv{T(0), T(0)};
+#pragma unroll
+      for (int comp = 0; comp < 6; ++comp) {
+        if (comp >= nf) break;
+        const T bv = pot_comp<T>(a.g, k0, col, comp, pt);
+        qv.x += bv * xv[comp].x;
+        qv.y += bv * xv[comp].y;
+      }
+      const long idx = (long)item * a.c_stride + pt * a.g.pot_stride + (long)i * a.si +
+                       (long)col * a.sc_;
+      if (a.epi == EPI_STORE) {
+        a.q[idx] = qv;
+        if (a.p) {
+          const cpx<T> pv = a.p[idx];
+          part += wt * ((double)pv.x * (double)qv.x + (double)pv.y * (double)qv.y);
+        }
+      } else if (a.epi == EPI_RHS) {
+        qv = cpx<T>{-qv.x, -qv.y};
+        a.q[idx] = qv;
+        if (a.r) a.r[idx] = qv;
+        if (a.pp) a.pp[idx] = qv;
+        if (a.x) a.x[idx] = cpx<T>{T(0), T(0)};
+        part += wt * ((double)qv.x * (double)qv.x + (double)qv.y * (double)qv.y);
+      } else {  // EPI_RESID: r = b - q
+        const cpx<T> bv = a.b[idx];
+        const cpx<T> rv = cpx<T>{bv.x - qv.x, bv.y - qv.y};
+        a.r[idx] = rv;
+        part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
+      }
+    }
+  }
+  if (a.partials) {
+    part = block_sum<kThreads>(part);
+    if (threadIdx.x == 0) a.partials[(long)item * a.P + blockIdx.x] = part;
+  }
+  if (a.rr_part && blockIdx.x == 0) {
+    // bookkeeping of the update before this iteration's expansion, as the
+    // projection pass does it
+    const bool fresh = a.sc[item].fresh != 0;
+    const double s = fresh ? 0.0 : sum_partials_wave(a.rr_part + (long)item * a.P, a.rr_n);
+    if (threadIdx.x == 0) {
+      if (fresh) a.sc[item].fresh = 0;
+      else cg_book(a.sc[item], s);
+    }
+  }
+}
+
+template <class T>
 __global__ __launch_bounds__(kThreads) void k_norm_parts(const cpx<T>* v, long stride, long count,
                                                           int n0, int H, double* part, int P,
                                                           const ItemScal* sc) {
@@ -654,19 +760,23 @@ __global__ void k_widen(const float* in, double* out, long n) {
 // ---------------------------------------------------------------------------
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
-// events armed for the next launch of this thread: the dispatch records them
-// itself, so the interval is the kernel's own, with no marker packet added
+// events armed for the next launches of this thread: the first dispatch
+// records the start, the last one the stop, so the interval is the kernels'
+// own, with no marker packet added
 static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
-void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
+static thread_local int t_ev_left = 0;
+void arm_launch_events(hipEvent_t start, hipEvent_t stop, int launches) {
   t_ev_start = start;
   t_ev_stop = stop;
+  t_ev_left = (start || stop) ? launches : 0;
 }
 
 template <class F, class... Args>
 static void launch_k(F fn, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
-  if (t_ev_start) {
-    hipEvent_t a = t_ev_start, z = t_ev_stop;
-    t_ev_start = t_ev_stop = nullptr;
+  if (t_ev_left > 0) {
+    hipEvent_t a = t_ev_start, z = (t_ev_left == 1) ? t_ev_stop : nullptr;
+    t_ev_start = nullptr;
+    if (--t_ev_left == 0) t_ev_stop = nullptr;
     hipExtLaunchKernelGGL(fn, grid, block, (std::uint32_t)lds, s, a, z, 0u, args...);
   } else {
     hipLaunchKernelGGL(fn, grid, block, lds, s, args...);
@@ -866,6 +976,19 @@ hipError_t launch_sym_h0(const SymArgs<T>& a, int items, hipStream_t s) {
 }
 
 template <class T>
+hipError_t launch_basis_expand(const BasisArgs<T>& a, int items, int blocks, hipStream_t s) {
+  launch_k((k_basis_expand<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_basis_project(const BasisArgs<T>& a, int items, int blocks, hipStream_t s) {
+  if (blocks < 1 || blocks > a.P) return hipErrorInvalidValue;
+  launch_k((k_basis_project<T>), dim3(blocks, items), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_norm_parts(const cpx<T>* v, long stride, long count, int n0, int H,
                              double* part, int P, int blocks, int items, const ItemScal* sc,
                              hipStream_t s) {
@@ -949,6 +1072,10 @@ template hipError_t launch_row<float>(const RowArgs<float>&, int, int, size_t, h
 template hipError_t launch_row<double>(const RowArgs<double>&, int, int, size_t, hipStream_t, const StaticKernel*);
 template hipError_t launch_cg_direction<float>(const CgDirArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_cg_direction<double>(const CgDirArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_basis_expand<float>(const BasisArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_basis_expand<double>(const BasisArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_basis_project<float>(const BasisArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_basis_project<double>(const BasisArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_sym_h0<float>(const SymArgs<float>&, int, hipStream_t);
 template hipError_t launch_sym_h0<double>(const SymArgs<double>&, int, hipStream_t);
 template hipError_t launch_norm_parts<float>(const cpx<float>*, long, long, int, int, double*, int,

@@ -281,6 +281,41 @@ struct SymArgs {
 };
 template <class T>
 hipError_t launch_sym_h0(const SymArgs<T>& a, int items, hipStream_t s);
+
+// Cells with several potentials per frequency (3-D dual, elasticity) split
+// each first-axis pass into a per-frequency basis map on the trial rows and a
+// plain column transform (the compile-time kernels of the shape):
+//   expand:  X_a(k) = sum_p b_p[a](k) c_p(k), then F_0^-1 with padding;
+//   project: F_0 with truncation, then q_p(k) = sum_a b_p[a](k) X^_a(k) and
+//            the epilogue of the projection pass (store with (p, q), right-hand
+//            side, residual; the bookkeeping of the last update in workgroup 0).
+// X holds component spectra on the trial rows: [item][nf][N0][inner] with the
+// component stride X_cstride; the potentials use the scalar layout (si, sc_).
+template <class T>
+struct BasisArgs {
+  const cpx<T>* c;     // expand: potentials
+  cpx<T>* Xo;          // expand: component spectra written
+  const cpx<T>* Xi;    // project: transformed component spectra read
+  long c_stride, X_stride, X_cstride;
+  int N0, inner, si, sc_;
+  // project epilogue (as ColProjectArgs)
+  cpx<T>* q;
+  const cpx<T>* p;
+  cpx<T>* r;
+  cpx<T>* pp;
+  cpx<T>* x;
+  const cpx<T>* b;
+  double* partials;
+  int P, epi;
+  const double* rr_part;
+  int rr_n;
+  NormalGeo g;
+  ItemScal* sc;
+};
+template <class T>
+hipError_t launch_basis_expand(const BasisArgs<T>& a, int items, int blocks, hipStream_t s);
+template <class T>
+hipError_t launch_basis_project(const BasisArgs<T>& a, int items, int blocks, hipStream_t s);
 // part[item][b] for b < blocks: the Hermitian-weighted (v, v) of a share of
 // the item's count elements (weight 1 where h = (e / n0) % H is 0, else 2)
 template <class T>
@@ -368,9 +403,10 @@ constexpr long kQuadScratch = (long)kQuadBlocks * kQuadSlots + 64;
 hipError_t a_field_range(const double* A, int d, int kind, long npts, double* scratch,
                          double* host, hipStream_t s, double* lo, double* hi, int* flags);
 
-// Arm HIP events for the next kernel launched by this thread through the
-// launchers below: hipExtLaunchKernel records them from the dispatch itself.
-void arm_launch_events(hipEvent_t start, hipEvent_t stop);
+// Arm HIP events for the next `launches` kernels launched by this thread
+// through the launchers below: hipExtLaunchKernel records the start event from
+// the first dispatch and the stop event from the last one.
+void arm_launch_events(hipEvent_t start, hipEvent_t stop, int launches = 1);
 
 // CG start: rho = (r_0, r_0) from partials; the stopping test is relative to
 // (b, b) from ref (nullable: to rho itself, the cold start where r_0 = b); an

@@ -104,6 +104,8 @@ RegProjPre<T, P253, 127, 16, 256> p253pre;
 RegCol<T, P255, 255, 16, 512> c255t512;
 // last-axis pass with the load cases of a row tile on consecutive workgroups
 RegRow<T, P255, 255, 3, 4, 256, false, true> r255_3i;
+// six Mandel components (3-D elasticity)
+RegRow<T, P255, 255, 6, 2, 256> r255_6;
 RegRow<T, P253, 127, 3, 4, 256, false, true> r253_3i;
 RegRow<T, P1023, 1023, 2, 1, 320, true, true> r1023_2i;
 }  // namespace

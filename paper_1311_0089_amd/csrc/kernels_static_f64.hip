@@ -30,6 +30,8 @@ RegRow<T, P1023, 1023, 2, 1, 128> r1023_2n;
 RegRow<T, P1023, 1023, 3, 1, 256> r1023_3;
 RegRow<T, P255, 255, 2, 4, 256> r255_2;
 RegRow<T, P255, 255, 3, 4, 256> r255_3;
+// six Mandel components (3-D elasticity)
+RegRow<T, P255, 255, 6, 2, 256> r255_6;
 RegRow<T, P127, 127, 2, 4, 256> r127_2;
 RegRow<T, P127, 127, 3, 4, 256> r127_3;
 RegRow<T, P63, 63, 2, 8, 256> r63_2;

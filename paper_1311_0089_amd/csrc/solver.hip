@@ -267,6 +267,51 @@ static int scalar_sc(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 
 // elements per column as the CG vector kernels see them (1: row-major)
 int scalar_n0(const CellImpl* c) { return scalar_colmajor(c) ? c->N[0] : 1; }
 
+// workgroups of the basis maps of a cell with several potentials per
+// frequency (also the number of partial sums its projection writes)
+static int basis_blocks(const CellImpl* c) {
+  const long n = (long)c->N[0] * inner0(c);
+  return (int)std::max(1L, std::min<long>(512, (n + 4L * kThreads - 1) / (4L * kThreads)));
+}
+
+// plain first-axis pass of the component spectra: inverse with padding
+// N0 -> G0 (sign > 0) or forward with truncation G0 -> N0, the compile-time
+// column kernels of the length where there are some
+template <class T>
+static hipError_t plain_axis0(CellImpl* c, int items, int sign, int G0, const cpx<T>* in,
+                              cpx<T>* out, ItemScal* sc) {
+  const DevPlan* p0;
+  hipError_t e = get_dev_plan(G0, &p0);
+  if (e != hipSuccess) return e;
+  ColPlainArgs<T> a{};
+  a.in = in;
+  a.out = out;
+  a.in_stride = a.out_stride = (long)c->nf * c->Xe;
+  a.in_cstride = a.out_cstride = c->Xe;
+  a.outer = 1;
+  a.n_fft = G0;
+  a.n_in = (sign > 0) ? c->N[0] : G0;
+  a.n_out = (sign > 0) ? G0 : c->N[0];
+  a.inner = (int)inner0(c);
+  a.d = c->nf;
+  a.scale = (sign > 0) ? T(1) : T(1.0 / (double)G0);
+  a.plan = p0->p;
+  a.tw = tw_of<T>(p0);
+  a.sc = sc;
+  const StaticKernel* sk = find_static(sign > 0 ? KK_PLAIN_INV : KK_PLAIN_FWD, sizeof(cpx<T>),
+                                       G0, c->N[0], 0, p0->p);
+  if (sk) {
+    a.W = sk->W;
+    return launch_col_plain<T>(a, items, sign, sk->lds, c->stream, sk);
+  }
+  ColShape sh;
+  if ((e = col_shape(p0->p, std::max(a.n_in, a.n_out), a.inner, sizeof(cpx<T>), &sh)) !=
+      hipSuccess)
+    return e;
+  a.W = sh.W;
+  return launch_col_plain<T>(a, items, sign, sh.lds, c->stream);
+}
+
 template <class T>
 static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int G0,
                                ItemScal* sc) {
@@ -288,6 +333,26 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
+  if (c->npot > 1) {
+    // several potentials: basis map on the trial rows (into X2), then the
+    // plain inverse pass with padding into X1
+    BasisArgs<T> b{};
+    b.c = in;
+    b.Xo = w.X2;
+    b.c_stride = c->S;
+    b.X_stride = a.X_stride;
+    b.X_cstride = c->Xe;
+    b.N0 = c->N[0];
+    b.inner = a.inner;
+    b.si = a.si;
+    b.sc_ = a.sc_;
+    b.g = a.g;
+    b.sc = sc;
+    const long n = (long)c->N[0] * a.inner;
+    const int blocks = (int)std::max(1L, std::min<long>(2048, (n + kThreads - 1) / kThreads));
+    if ((e = launch_basis_expand<T>(b, items, blocks, c->stream)) != hipSuccess) return e;
+    return plain_axis0<T>(c, items, +1, G0, w.X2, w.X1, sc);
+  }
   const StaticKernel* sk = col_static(c, KK_EXPAND, sizeof(cpx<T>), G0, p0->p);
   if (sk) {
     a.W = sk->W;
@@ -370,8 +435,7 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
                  : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
   const StaticKernel* sk =
-      (kind >= 0 && !c->elastic) ? find_static(kind, sizeof(cpx<T>), Glast, Nlast, c->dd, pl->p)
-                                 : nullptr;
+      (kind >= 0) ? find_static(kind, sizeof(cpx<T>), Glast, Nlast, c->nf, pl->p) : nullptr;
   if (sk) {
     a.RP = sk->W;
     return launch_row<T>(a, items, mode, sk->lds, c->stream, sk);
@@ -427,6 +491,37 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   a.plan = p0->p;
   a.tw = tw_of<T>(p0);
   a.sc = sc;
+  if (c->npot > 1) {
+    // several potentials: plain forward pass with truncation into the other
+    // component buffer, then the basis map with the projection's epilogue
+    cpx<T>* tmp = (X == w.X1) ? w.X2 : w.X1;
+    if ((e = plain_axis0<T>(c, items, -1, G0, X, tmp, sc)) != hipSuccess) return e;
+    BasisArgs<T> ba{};
+    ba.Xi = tmp;
+    ba.c_stride = c->S;
+    ba.X_stride = a.X_stride;
+    ba.X_cstride = c->Xe;
+    ba.N0 = c->N[0];
+    ba.inner = a.inner;
+    ba.si = a.si;
+    ba.sc_ = a.sc_;
+    ba.q = out;
+    ba.p = pdot;
+    ba.r = r;
+    ba.pp = pp;
+    ba.x = x;
+    ba.b = b;
+    ba.partials = partials;
+    ba.P = a.P;
+    ba.epi = epi;
+    ba.rr_part = a.rr_part;
+    ba.rr_n = a.rr_n;
+    ba.g = a.g;
+    ba.sc = sc;
+    const int blocks = basis_blocks(c);
+    if (tiles) *tiles = blocks;
+    return launch_basis_project<T>(ba, items, blocks, c->stream);
+  }
   const StaticKernel* sk = col_static(c, KK_PROJECT, sizeof(cpx<T>), G0, p0->p);
   if (sk) {
     a.W = sk->W;
@@ -445,6 +540,7 @@ int project_tiles(CellImpl* c) {
   const DevPlan* p0;
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
   const int inner = (int)inner0(c);
+  if (c->npot > 1) return basis_blocks(c);
   const StaticKernel* sk = col_static(c, KK_PROJECT, sizeof(cpx<T>), c->Q[0], p0->p);
   if (sk) return (inner + sk->W - 1) / sk->W;
   ColShape sh;
@@ -1078,10 +1174,9 @@ static bool fp64_rows_served(const CellImpl* c) {
     const DevPlan* pl = nullptr;
     if (get_dev_plan(lens[i], &pl) != hipSuccess) return false;
     if (!pl->p.blue) continue;
-    if (c->elastic) return false;   // elastic cells run the generic rows only
     for (int k : {KK_ROW, KK_ROW_CONST, KK_ROW_SYNTH}) {
       if (i == 1 && k != KK_ROW_SYNTH) continue;
-      if (!find_static(k, (int)sizeof(cpx<double>), lens[i], Nl, c->dd, pl->p)) return false;
+      if (!find_static(k, (int)sizeof(cpx<double>), lens[i], Nl, c->nf, pl->p)) return false;
     }
   }
   return true;
@@ -1685,8 +1780,9 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     const CgFuse cg{w.part2, ub, it > 0 ? 1 : 0};
     hipEvent_t* E = ev.data() + (size_t)it * NK * 2;
     int* Ln = launched.data() + (size_t)it * NK;
+    // the first-axis stages of a cell with several potentials are two kernels
     auto arm = [&](int k) {
-      arm_launch_events(E[2 * k], E[2 * k + 1]);
+      arm_launch_events(E[2 * k], E[2 * k + 1], (c->npot > 1 && (k == 0 || k == 4)) ? 2 : 1);
       Ln[k] = 1;
     };
     arm(7);

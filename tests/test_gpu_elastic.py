@@ -30,7 +30,8 @@ def hom():
 
 @gpu
 @pytest.mark.parametrize("N,scheme", [((15, 13), 0), ((9, 11), 1), ((33, 31), 0), ((9, 7, 5), 0),
-                                      ((7, 5, 9), 1), ((15, 13, 11), 0)])
+                                      ((7, 5, 9), 1), ((15, 13, 11), 0), ((15, 255), 0),
+                                      ((9, 7, 255), 0), ((255, 5, 7), 0)])
 def test_elastic_matches_oracle(hom, oracle, N, scheme):
     import torch
     d = len(N)
