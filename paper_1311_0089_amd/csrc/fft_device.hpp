@@ -241,6 +241,15 @@ struct FftPlan {
   int chirp_off;            // offset of the n chirp values exp(-i pi j^2 / n)
   int dfwd_off;             // offset of D_- = FFT_m(conj chirp) / m   (forward)
   int dinv_off;             // offset of D_+ = FFT_m(chirp) / m        (inverse)
+  // Rader's algorithm for a prime n whose n - 1 factors into the Stockham
+  // radices (used by the compile-time kernels that choose it; the generic
+  // kernels keep Bluestein): tables after the Bluestein ones
+  int rader;                // 1 if present
+  int r_nst;                // stages of the (n-1)-point Stockham transform
+  int r_rad[kMaxStages];    // its radices
+  int r_off;                // its twiddles
+  int r_bf, r_bi;           // B_-/+ = FFT_{n-1}(b) / (n-1), b_m = exp(-/+ 2 pi i g^m / n)
+  int r_gidx, r_sidx;       // g^-p mod n and g^q mod n (as the real parts)
 };
 
 // Maximum complex values a thread holds during one stage.

@@ -266,13 +266,97 @@ struct SStockham<T, S, LEN, W, WF, LS, ES, NT, MF, Rad<Rs...>> {
   }
 };
 
-// full n-point DFT of sign S on W lines (layout: element (w, i) at w*LS + i*ES);
-// MF: first stage on the matrix cores where use_mstage allows it
-template <class T, int S, class SP, int W, bool WF, int LS, int ES, int NT, bool MF = false>
-__device__ __forceinline__ void sfft(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+// Rader's algorithm for a prime n on W lines of n + 1 rows (the plan's tables
+// after the Bluestein ones, see FftPlan): a_p = x_{g^-p} in rows 0..n-2 and x_0
+// in row n; the (n-1)-point forward transform; X_0 = x_0 + A_0 into row n-1;
+// A times B of sign S; the inverse transform gives the cyclic convolution c,
+// and X_{g^q} = x_0 + c_q, X_0 go back to the rows of their indices.
+template <class T, int S, class SP, int W, bool WF, int LS, int ES, int NT>
+__device__ __forceinline__ void rader_fft(cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                          const FftPlan& P) {
   using R_ = typename SP::radices;
-  if constexpr (!SP::blue) {
+  constexpr int n = SP::n, L = n - 1;
+  constexpr int NG = (L * W + NT - 1) / NT;
+  const cpx<T>* gi = tw + P.r_gidx;
+  const cpx<T>* si = tw + P.r_sidx;
+  const cpx<T>* Bv = tw + (S < 0 ? P.r_bf : P.r_bi);
+  auto at = [](int u, int& w, int& p) __attribute__((always_inline)) {
+    const int f = threadIdx.x + u * NT;
+    if (WF) {
+      w = f % W;
+      p = f / W;
+    } else {
+      p = f % L;
+      w = f / L;
+    }
+    return f < L * W;
+  };
+  cpx<T> v[NG];
+  // gather a_p = x_{g^-p}; x_0 of line threadIdx.x (< W) to row n
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    int w, p;
+    if (at(u, w, p)) v[u] = buf[w * LS + (int)gi[p].x * ES];
+  }
+  cpx<T> x0{};
+  if ((int)threadIdx.x < W) x0 = buf[threadIdx.x * LS];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    int w, p;
+    if (at(u, w, p)) buf[w * LS + p * ES] = v[u];
+  }
+  if ((int)threadIdx.x < W) buf[threadIdx.x * LS + n * ES] = x0;
+  __syncthreads();
+  SStockham<T, -1, L, W, WF, LS, ES, NT, false, R_>::run(buf, tw + P.r_off);
+  if ((int)threadIdx.x < W) {
+    cpx<T>* line = buf + threadIdx.x * LS;
+    const cpx<T> a0 = line[0], xz = line[n * ES];
+    line[L * ES] = cpx<T>{xz.x + a0.x, xz.y + a0.y};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    int w, p;
+    if (at(u, w, p)) {
+      cpx<T>* e = buf + w * LS + p * ES;
+      *e = cmul(*e, Bv[p]);
+    }
+  }
+  __syncthreads();
+  SStockham<T, +1, L, W, WF, LS, ES, NT, false, R_>::run(buf, tw + P.r_off);
+  // scatter X_{g^q} = x_0 + c_q and X_0
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    int w, p;
+    if (at(u, w, p)) {
+      const cpx<T> c = buf[w * LS + p * ES], xz = buf[w * LS + n * ES];
+      v[u] = cpx<T>{xz.x + c.x, xz.y + c.y};
+    }
+  }
+  if ((int)threadIdx.x < W) x0 = buf[threadIdx.x * LS + L * ES];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    int w, p;
+    if (at(u, w, p)) buf[w * LS + (int)si[p].x * ES] = v[u];
+  }
+  if ((int)threadIdx.x < W) buf[threadIdx.x * LS] = x0;
+  __syncthreads();
+}
+
+// full n-point DFT of sign S on W lines (layout: element (w, i) at w*LS + i*ES);
+// MF: first stage on the matrix cores where use_mstage allows it.  SP::blue:
+// 0 Stockham, 1 Bluestein (tables at compile-time offsets), 2 Rader (tables
+// located by the plan P)
+template <class T, int S, class SP, int W, bool WF, int LS, int ES, int NT, bool MF = false>
+__device__ __forceinline__ void sfft(cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                     const FftPlan& P) {
+  using R_ = typename SP::radices;
+  if constexpr (SP::blue == 0) {
     SStockham<T, S, SP::len, W, WF, LS, ES, NT, MF, R_>::run(buf, tw);
+  } else if constexpr (SP::blue == 2) {
+    rader_fft<T, S, SP, W, WF, LS, ES, NT>(buf, tw, P);
   } else {
     constexpr int n = SP::n, m = SP::len;
     constexpr int chirp_off = TwSizeOf<R_>::v;

@@ -79,13 +79,13 @@ struct ColStat {
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
   __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
-  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan&, int, const cpx<T>* tw) {
-    sfft<T, S, SP, W_, true, 1, W_, NT_, MF_>(lds, tw);
+  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan& P, int, const cpx<T>* tw) {
+    sfft<T, S, SP, W_, true, 1, W_, NT_, MF_>(lds, tw, P);
   }
   template <class T, int S>
-  __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan&, int,
+  __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan& P, int,
                                                   const cpx<T>* tw) {
-    sfft<T, S, SP, W_, true, 1, RL, NT_, MF_>(lds, tw);
+    sfft<T, S, SP, W_, true, 1, RL, NT_, MF_>(lds, tw, P);
   }
 };
 
@@ -107,9 +107,9 @@ struct ColStatCP {
   __device__ static constexpr int ntrial(int) { return NTRIAL; }
   __device__ static constexpr int rowlen(int) { return RL; }
   template <class T, int S>
-  __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan&, int,
+  __device__ __forceinline__ static void fft_rows(cpx<T>* lds, const FftPlan& P, int,
                                                   const cpx<T>* tw) {
-    sfft<T, S, SP, D_ * W_, true, 1, RL, NT_, MF_>(lds, tw);
+    sfft<T, S, SP, D_ * W_, true, 1, RL, NT_, MF_>(lds, tw, P);
   }
 };
 
@@ -148,9 +148,9 @@ struct RowStat {
   __device__ static constexpr int H(int) { return (NTRIAL + 1) / 2; }
   __device__ static constexpr int ls(int) { return SP::len; }
   template <class T, int S>
-  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan&, int, int,
+  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan& P, int, int,
                                              const cpx<T>* tw) {
-    sfft<T, S, SP, D_ * RP_, false, SP::len, 1, NT_, MF_>(lds, tw);
+    sfft<T, S, SP, D_ * RP_, false, SP::len, 1, NT_, MF_>(lds, tw, P);
   }
 };
 

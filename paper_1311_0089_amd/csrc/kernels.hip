@@ -51,6 +51,15 @@ std::vector<const StaticKernel*> static_variants(int kind, int esz, int n, int n
     // static LDS of the block reductions)
     if (k.lds > g_static_max_lds) continue;
     // the compile-time plan must describe the same tables the host uploaded
+    // (a Rader kernel: the plan's Rader section, lines of n + 1 rows)
+    if (k.blue == 2) {
+      if (!p.rader || k.len != p.n + 1 || k.nst != p.r_nst) continue;
+      bool same = true;
+      for (int i = 0; i < p.r_nst; ++i) same = same && (k.rad[i] == p.r_rad[i]);
+      if (!same) continue;
+      out.push_back(&k);
+      continue;
+    }
     if (k.len != p.len || k.blue != p.blue || k.nst != p.nst) continue;
     bool same = true;
     for (int i = 0; i < p.nst; ++i) same = same && (k.rad[i] == p.rad[i]);

@@ -4,6 +4,16 @@
 namespace hom {
 namespace {
 using T = float;
+// Rader variants of the prime lengths 127 and 61, registered first (the
+// default where no tuned choice exists; the chirp-z variants below stay and
+// the tuner picks per pass)
+RegCol<T, P127R, 127, 16, 256> c127r;
+RegCol<T, P127R, 127, 8, 256> c127rn;
+RegRow<T, P127R, 127, 2, 8, 256> r127r_2;
+RegRow<T, P127R, 127, 3, 8, 256> r127r_3;
+RegCol<T, P61R, 31, 16, 256> c61r;
+RegRow<T, P61R, 31, 2, 8, 256> r61r_2;
+RegRow<T, P61R, 31, 3, 8, 256> r61r_3;
 // columns: plan, trial length, W, workgroup size
 RegCol<T, P1023, 1023, 4, 256> c1023;
 RegCol<T, P1023, 1023, 8, 512> c1023w;

@@ -4,6 +4,15 @@
 namespace hom {
 namespace {
 using T = double;
+// Rader variants of the prime lengths 127 and 61, registered first (the
+// default where no tuned choice exists; the chirp-z variants below stay and
+// the tuner picks per pass)
+RegCol<T, P127R, 127, 8, 256> c127r;
+RegRow<T, P127R, 127, 2, 4, 256> r127r_2;
+RegRow<T, P127R, 127, 3, 4, 256> r127r_3;
+RegCol<T, P61R, 31, 16, 256> c61r;
+RegRow<T, P61R, 31, 2, 8, 256> r61r_2;
+RegRow<T, P61R, 31, 3, 8, 256> r61r_3;
 RegCol<T, P1023, 1023, 2, 256> c1023;
 RegCol<T, P1023, 1023, 4, 512> c1023w;
 RegCol<T, P1023, 1023, 1, 128> c1023n1;

@@ -61,6 +61,71 @@ static void stockham_tables(int len, const std::vector<int>& rad, FftPlan& p,
   (void)len;
 }
 
+static bool is_prime(int n) {
+  if (n < 2) return false;
+  for (int q = 2; (long)q * q <= n; ++q)
+    if (n % q == 0) return false;
+  return true;
+}
+
+// smallest generator of the multiplicative group mod a prime n
+static int primitive_root(int n) {
+  std::vector<int> f;
+  int m = n - 1;
+  for (int q = 2; q * q <= m; ++q)
+    if (m % q == 0) {
+      f.push_back(q);
+      while (m % q == 0) m /= q;
+    }
+  if (m > 1) f.push_back(m);
+  for (int g = 2; g < n; ++g) {
+    bool ok = true;
+    for (int q : f) {
+      long r = 1, b = g;
+      for (int e = (n - 1) / q; e > 0; e >>= 1, b = b * b % n)
+        if (e & 1) r = r * b % n;
+      if (r == 1) ok = false;
+    }
+    if (ok) return g;
+  }
+  return 0;
+}
+
+// Rader (1968): for prime n and a generator g, X_{g^q} = x_0 + sum_p
+// x_{g^-p} w^{g^(q-p)}, a cyclic convolution of length L = n - 1 of
+// a_p = x_{g^-p} with b_m = w^{g^m}, evaluated as IFFT_L(FFT_L(a) B) with
+// B = FFT_L(b) / L; X_0 = x_0 + FFT_L(a)_0.
+static void add_rader(int n, HostPlan& h) {
+  if (!is_prime(n) || n < 5) return;
+  const int L = n - 1;
+  const std::vector<int> f = factorize(L);
+  if (f.empty() || (int)f.size() > kMaxStages) return;
+  const int g = primitive_root(n);
+  if (!g) return;
+  FftPlan t{};
+  h.p.r_off = (int)h.table.size();
+  stockham_tables(L, f, t, h.table);
+  h.p.r_nst = t.nst;
+  for (int s = 0; s < t.nst; ++s) h.p.r_rad[s] = t.rad[s];
+  std::vector<long> gp(L);
+  gp[0] = 1;
+  for (int m = 1; m < L; ++m) gp[m] = gp[m - 1] * g % n;
+  for (int sgn = 0; sgn < 2; ++sgn) {
+    // sgn 0: forward transform, w = exp(-2 pi i / n); 1: inverse, w = exp(+2 pi i / n)
+    (sgn == 0 ? h.p.r_bf : h.p.r_bi) = (int)h.table.size();
+    for (long k = 0; k < L; ++k) {
+      std::complex<long double> s = {0.0L, 0.0L};
+      for (long m = 0; m < L; ++m) s += root(sgn == 0 ? gp[m] : -gp[m], n) * root(m * k, L);
+      h.table.push_back(s / (long double)L);
+    }
+  }
+  h.p.r_gidx = (int)h.table.size();
+  for (long p = 0; p < L; ++p) h.table.push_back({(long double)gp[(L - p) % L], 0.0L});
+  h.p.r_sidx = (int)h.table.size();
+  for (long q = 0; q < L; ++q) h.table.push_back({(long double)gp[q], 0.0L});
+  h.p.rader = 1;
+}
+
 HostPlan build_plan(int n) {
   HostPlan h{};
   h.p.n = n;
@@ -100,6 +165,7 @@ HostPlan build_plan(int n) {
       h.table.push_back(s / (long double)m);
     }
   }
+  add_rader(n, h);
   return h;
 }
 

@@ -147,5 +147,9 @@ using P125 = SPlan<125, 125, 0, Rad<5, 5, 5>>;
 using P61 = SPlan<61, 128, 1, Rad<8, 8, 2>>;
 using P29 = SPlan<29, 29, 0, Rad<29>>;
 using P509 = SPlan<509, 1024, 1, Rad<8, 8, 8, 2>>;
+// Rader plans of the primes above 31 whose n - 1 factors into the radices:
+// lines of n + 1 rows, the radices of the (n-1)-point transform
+using P127R = SPlan<127, 128, 2, Rad<9, 7, 2>>;
+using P61R = SPlan<61, 62, 2, Rad<15, 4>>;
 
 }  // namespace hom

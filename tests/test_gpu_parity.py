@@ -151,7 +151,10 @@ def _chirp_length(n):
 # different widths, all components per transform, different row-pair counts
 VARIANT_CASES = [((1023, 15), 0, 0), ((15, 1023), 1, 0), ((255, 15), 0, 0),
                  ((255, 15, 15), 0, 0), ((127, 15, 15), 2, 1), ((127, 15, 15), 0, 0),
-                 ((63, 15, 15), 1, 0), ((15, 15, 255), 0, 0), ((15, 15, 127), 0, 1)]
+                 ((63, 15, 15), 1, 0), ((15, 15, 255), 0, 0), ((15, 15, 127), 0, 1),
+                 # chirp-z and Rader variants of the prime lengths 127 and 61
+                 ((127, 15), 2, 0), ((15, 127), 0, 0), ((15, 15, 127), 1, 0),
+                 ((31, 15), 0, 1), ((15, 31), 2, 1), ((15, 15, 31), 0, 1)]
 
 
 @gpu
