@@ -521,6 +521,103 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_plain(ColPlainArgs<T> a) 
 }
 
 // ---------------------------------------------------------------------------
+// plain column pass of a two-stage plan (n = R1 R2) with the first stage's
+// operands loaded from global memory straight into registers and the second
+// stage's results stored straight to global memory: one LDS exchange and one
+// barrier per tile instead of the four round trips of the LDS-staged pass.
+// Lanes take consecutive columns of the tile, so both the loads and the
+// stores of a wave cover whole row segments.
+// ---------------------------------------------------------------------------
+template <class R_>
+struct TwoRadices;
+template <int A, int B>
+struct TwoRadices<Rad<A, B>> {
+  static constexpr int r1 = A, r2 = B;
+};
+
+template <class T, class SP, int NTRIAL, int W, int NT, int S>
+__global__ __launch_bounds__(NT) void k_col_reg2(ColPlainArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int R1 = TwoRadices<typename SP::radices>::r1, R2 = TwoRadices<typename SP::radices>::r2;
+  constexpr int n = SP::n;
+  static_assert(R1 * R2 == n && !SP::blue, "two-stage Stockham plan");
+  // inverse: trial rows in, padded to n; forward: n rows in, truncated to trial
+  constexpr int n_in = (S > 0) ? NTRIAL : n, n_out = (S > 0) ? n : NTRIAL;
+  constexpr int hk = (NTRIAL - 1) / 2;   // |k| of the trial frequencies
+  const int item = blockIdx.z / a.d, comp = blockIdx.z % a.d;
+  if (a.sc && !item_live(a.sc[item])) return;
+  const int o = blockIdx.y;
+  const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+  const int ncols = min(W, a.inner - col0);
+  const cpx<T>* in = a.in + (long)item * a.in_stride + (long)comp * a.in_cstride +
+                     (long)o * n_in * a.inner + col0;
+  cpx<T>* out = a.out + (long)item * a.out_stride + (long)comp * a.out_cstride +
+                (long)o * n_out * a.inner + col0;
+  // stage 1 (no twiddles): butterfly (w, j), j < R2, operands at rows j + r R2
+  constexpr int T1 = R2 * W, M1 = (T1 + NT - 1) / NT;
+  cpx<T> v[M1][R1];
+#pragma unroll
+  for (int it = 0; it < M1; ++it) {
+    const int f = min((int)threadIdx.x + it * NT, T1 - 1);
+    const int w = min(f % W, ncols - 1), j = f / W;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int t = j + r * R2;
+      if constexpr (n_in == n) {
+        v[it][r] = in[(long)t * a.inner + w];
+      } else {
+        const int k = kof(t, n);
+        const bool trial = (k >= -hk && k <= hk);
+        const cpx<T> x = in[(long)(trial ? posk(k, NTRIAL) : 0) * a.inner + w];
+        v[it][r] = trial ? x : cpx<T>{T(0), T(0)};
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < M1; ++it) {
+    const int f = (int)threadIdx.x + it * NT;
+    if (f < T1) {
+      const int w = f % W, j = f / W;
+      Dft<T, R1, S>::run(v[it]);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) lds[(j * R1 + r) * W + w] = v[it][r];
+    }
+  }
+  __syncthreads();
+  // stage 2 (Ns = R1): butterfly (w, k), k < R1, operands at rows k + r R1,
+  // twiddles of the plan's second stage, results at rows k + r R1
+  constexpr int T2 = R1 * W, M2 = (T2 + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < M2; ++it) {
+    const int f = (int)threadIdx.x + it * NT;
+    if (f >= T2) continue;
+    const int w = f % W, k = f / W;
+    cpx<T> u[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) u[r] = lds[(k + r * R1) * W + w];
+#pragma unroll
+    for (int r = 1; r < R2; ++r) {
+      cpx<T> tw = a.tw[k * (R2 - 1) + r - 1];
+      if (S > 0) tw.y = -tw.y;
+      u[r] = cmul(u[r], tw);
+    }
+    Dft<T, R2, S>::run(u);
+    if (w >= ncols) continue;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int t = k + r * R1;
+      if constexpr (n_out == n) {
+        out[(long)t * a.inner + w] = cscale(u[r], a.scale);
+      } else {
+        const int kk = kof(t, n);
+        if (kk >= -hk && kk <= hk) out[(long)posk(kk, NTRIAL) * a.inner + w] = cscale(u[r], a.scale);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // axis 0 forward + truncation + projection q = n . F_0[X], CG epilogues
 // ---------------------------------------------------------------------------
 template <class T, class P, int PMAX>

@@ -118,5 +118,12 @@ RegRow<T, P255, 255, 3, 4, 256, false, true> r255_3i;
 RegRow<T, P255, 255, 6, 2, 256> r255_6;
 RegRow<T, P253, 127, 3, 4, 256, false, true> r253_3i;
 RegRow<T, P1023, 1023, 2, 1, 320, true, true> r1023_2i;
+// plain passes with the register pipeline (two-stage plans)
+RegColReg2<T, P255, 255, 16, 256> g255;
+RegColReg2<T, P255, 255, 8, 128> g255n;
+RegColReg2<T, P255, 255, 16, 512> g255t;
+RegColReg2<T, P253, 127, 16, 512> g253t;
+RegColReg2<T, P253, 127, 16, 256> g253;
+RegColReg2<T, P63, 63, 16, 128> g63;
 }  // namespace
 }  // namespace hom

@@ -59,5 +59,9 @@ RegRow<T, P29, 15, 2, 8, 256> r29_2;
 RegRow<T, P29, 15, 3, 8, 256> r29_3;
 RegRow<T, P509, 255, 2, 2, 512> r509_2;
 RegRow<T, P509, 255, 3, 1, 256> r509_3;
+// plain passes with the register pipeline (two-stage plans)
+RegColReg2<T, P255, 255, 8, 256> g255;
+RegColReg2<T, P253, 127, 8, 256> g253;
+RegColReg2<T, P63, 63, 8, 128> g63;
 }  // namespace
 }  // namespace hom

@@ -135,6 +135,35 @@ struct RegRow {
   }
 };
 
+// plain column passes of a two-stage plan with the register pipeline
+// (k_col_reg2): one LDS exchange per tile
+template <class T, class SP, int NTRIAL, int W, int NT>
+struct RegColReg2 {
+  static constexpr size_t lds = (size_t)SP::n * W * sizeof(cpx<T>);
+  static_assert(lds <= 66 * 1024, "column tile exceeds the LDS budget");
+  RegColReg2() {
+    add(KK_PLAIN_INV, (const void*)&k_col_reg2<T, SP, NTRIAL, W, NT, +1>);
+    add(KK_PLAIN_FWD, (const void*)&k_col_reg2<T, SP, NTRIAL, W, NT, -1>);
+  }
+  static void add(int kind, const void* fn) { add_kind(kind, 0, lds, fn); }
+  static void add_kind(int kind, int d, size_t lds_bytes, const void* fn) {
+    StaticKernel k{};
+    k.kind = kind;
+    k.esz = (int)sizeof(cpx<T>);
+    k.n = SP::n;
+    k.ntrial = NTRIAL;
+    k.d = d;
+    k.fn = fn;
+    k.W = W;
+    k.NT = NT;
+    k.lds = lds_bytes;
+    k.len = SP::len;
+    k.blue = SP::blue;
+    RegCol<T, SP, NTRIAL, 1, 256>::fill(k, typename SP::radices{});
+    register_static(k);
+  }
+};
+
 // plans
 using P1023 = SPlan<1023, 1023, 0, Rad<31, 11, 3>>;
 using P255 = SPlan<255, 255, 0, Rad<17, 15>>;

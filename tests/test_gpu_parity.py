@@ -154,7 +154,10 @@ VARIANT_CASES = [((1023, 15), 0, 0), ((15, 1023), 1, 0), ((255, 15), 0, 0),
                  ((63, 15, 15), 1, 0), ((15, 15, 255), 0, 0), ((15, 15, 127), 0, 1),
                  # chirp-z and Rader variants of the prime lengths 127 and 61
                  ((127, 15), 2, 0), ((15, 127), 0, 0), ((15, 15, 127), 1, 0),
-                 ((31, 15), 0, 1), ((15, 31), 2, 1), ((15, 15, 31), 0, 1)]
+                 ((31, 15), 0, 1), ((15, 31), 2, 1), ((15, 15, 31), 0, 1),
+                 # middle axes of 255, 253 (trial 127) and 63: the register-pipeline
+                 # plain passes beside the LDS-staged ones
+                 ((15, 255, 15), 0, 0), ((9, 127, 7), 1, 1), ((15, 63, 15), 2, 0)]
 
 
 @gpu
