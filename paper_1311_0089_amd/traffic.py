@@ -25,15 +25,15 @@ KERNEL_SOURCES = ["fft_device.hpp", "fft_static.hpp", "kernel_bodies.hpp", "kern
                   "kernels_static_f64.hip"]
 RECORD_TAG = "traffic-record:"
 
-# slot -> (kernel name prefix, element type) of the FP32 CG iteration
+# slot -> (kernel name prefixes, suffix or None) of the FP32 CG iteration
 SLOTS = {
-    "expand0": ("hom::k_col_expand<float", None),
-    "inv1": ("hom::k_col_plain<float", ", 1>"),
-    "row": ("hom::k_row<float", ", 0>"),
-    "fwd1": ("hom::k_col_plain<float", ", -1>"),
-    "project0": ("hom::k_col_project<float", None),
-    "update": ("hom::k_cg_update<float>", None),
-    "direction": ("hom::k_cg_direction<float>", None),
+    "expand0": (("hom::k_col_expand<float",), None),
+    "inv1": (("hom::k_col_plain<float", "hom::k_col_reg2<float"), ", 1>"),
+    "row": (("hom::k_row<float",), ", 0>"),
+    "fwd1": (("hom::k_col_plain<float", "hom::k_col_reg2<float"), ", -1>"),
+    "project0": (("hom::k_col_project<float",), None),
+    "update": (("hom::k_cg_update<float>",), None),
+    "direction": (("hom::k_cg_direction<float>",), None),
 }
 
 
@@ -48,8 +48,8 @@ def fingerprint() -> str:
 def _slot_of(name: str):
     head = name[5:] if name.startswith("void ") else name
     head = head.split("(")[0].rstrip()
-    for slot, (prefix, suffix) in SLOTS.items():
-        if head.startswith(prefix) and (suffix is None or head.endswith(suffix)):
+    for slot, (prefixes, suffix) in SLOTS.items():
+        if head.startswith(prefixes) and (suffix is None or head.endswith(suffix)):
             return slot
     return None
 
