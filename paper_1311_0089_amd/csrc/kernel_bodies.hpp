@@ -265,6 +265,17 @@ __device__ __forceinline__ T pot_comp(const NormalGeo& g, int k0, int col, int c
   return g.elastic ? elastic_comp<T>(g, k0, col, comp, pot) : dual3_comp<T>(g, k0, col, comp, pot);
 }
 
+// 1 / |xi| (0 at k = 0): in 3-D, xi_1 and xi_2 are constant along a first-axis
+// line, so n_1 F[X_1] + n_2 F[X_2] = F[xi_1 X_1 + xi_2 X_2] / |xi| and the
+// expansion's X_1, X_2 are xi_1, xi_2 times one transform of c / |xi|: the
+// first-axis passes of 3-D cells run two transforms per tile instead of three
+template <class T>
+__device__ __forceinline__ T inv_xi(const NormalGeo& g, int k0, const ColXi<T>& cx) {
+  const T xi0 = T(k0) * T(g.invY[0]);
+  const T s = xi0 * xi0 + cx.c;
+  return s > T(0) ? inv_sqrt(s) : T(0);
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[NT / 64];
@@ -411,14 +422,19 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
   // with row-major positions and NT a multiple of the tile width every
   // position of a thread lies in the same column: its part of xi is evaluated once
   constexpr bool col_fixed = (P::SL == 2) && P::WC > 0 && (NT % P::WC) == 0;
-  // two potentials per frequency (3-D dual) only in the generic kernels
-  constexpr bool multi = (P::WC == 0);
   ColXi<T> cx0{};
   if (col_fixed) cx0 = col_xi<T>(a.g, min(col0 + (int)threadIdx.x % W, a.inner - 1));
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
-  for (int al0 = 0; al0 < a.g.nf; al0 += CPN) {
+  // 3-D, one component per transform: transform 0 gives X_0, transform 1 the
+  // common part of X_1 and X_2 (see inv_xi)
+  // (known at compile time where the scalar layout is: row-major = 3-D)
+  constexpr int FOLD = (CPN != 1 || P::SL == 1) ? 0 : (P::SL == 2) ? 1 : -1;
+  const bool fold = (FOLD == 1) || (FOLD == -1 && a.g.d == 3);
+  const int ntr = fold ? 2 : a.g.nf;
+#pragma unroll 1
+  for (int al0 = 0; al0 < ntr; al0 += CPN) {
     constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
     if (n_fft != n_in) {
       for (int f = threadIdx.x; f < n_fft * LW; f += NT) lds[f] = cpx<T>{T(0), T(0)};
@@ -429,42 +445,44 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_expand(ColExpandArgs<T> a
       int i, w;
       if (pos(it, i, w)) {
         const int row = (n_fft == n_in) ? i : posk(kof(i, n_in), n_fft);
-        if (multi && a.g.npot > 1) {
-          // several potentials (3-D dual, elasticity; generic kernels only):
-          // X_a = sum_p b_p[a] c_p
-          const int col = min(col0 + w, a.inner - 1);
-          for (int c = 0; c < nc; ++c) {
-            cpx<T> u = cscale(s[it], pot_comp<T>(a.g, kof(i, n_in), col, al0 + c, 0));
-            for (int pt = 1; pt < a.g.npot; ++pt) {
-              const cpx<T> sp = (w < ncols) ? a.c[ibase + pt * a.g.pot_stride +
-                                                  (long)min(i, n_in - 1) * a.si + (long)col * a.sc_]
-                                            : cpx<T>{T(0), T(0)};
-              const cpx<T> v = cscale(sp, pot_comp<T>(a.g, kof(i, n_in), col, al0 + c, pt));
-              u.x += v.x;
-              u.y += v.y;
-            }
-            lds[row * LW + c * W + w] = u;
-          }
-          continue;
-        }
         const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
-        for (int c = 0; c < nc; ++c)
-          lds[row * LW + c * W + w] = cscale(s[it], normal_comp<T>(a.g, kof(i, n_in), cx, al0 + c));
+        if (fold) {
+          const T iv = inv_xi<T>(a.g, kof(i, n_in), cx);
+          lds[row * LW + w] = cscale(s[it], al0 == 0 ? T(kof(i, n_in)) * T(a.g.invY[0]) * iv : iv);
+        } else {
+          for (int c = 0; c < nc; ++c)
+            lds[row * LW + c * W + w] = cscale(s[it], normal_comp<T>(a.g, kof(i, n_in), cx, al0 + c));
+        }
       }
     }
     __syncthreads();
     P::template fft_rows<T, +1>(lds, a.plan, W, a.tw);
     cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride;
-    in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
-        n_fft * W * nc,
-        [=](int f) __attribute__((always_inline)) {
-          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
-          return lds[i * LW + c * W + w];
-        },
-        [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
-          const int w = f % W, t = f / W, c = t % nc, i = t / nc;
-          if (w < ncols) X[(long)c * a.X_cstride + (long)i * a.inner + col0 + w] = v;
-        });
+    if (fold && al0 == 1) {
+      // xi_1 Z into X_1 and xi_2 Z into X_2
+      in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
+          n_fft * W,
+          [=](int f) __attribute__((always_inline)) { return lds[(f / W) * LW + f % W]; },
+          [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+            const int w = f % W, i = f / W;
+            if (w >= ncols) return;
+            const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, col0 + w);
+            const long e = (long)i * a.inner + col0 + w;
+            X[e] = cscale(v, cx.x1);
+            X[e + a.X_cstride] = cscale(v, cx.x2);
+          });
+    } else {
+      in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
+          n_fft * W * nc,
+          [=](int f) __attribute__((always_inline)) {
+            const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+            return lds[i * LW + c * W + w];
+          },
+          [=](int f, const cpx<T>& v) __attribute__((always_inline)) {
+            const int w = f % W, t = f / W, c = t % nc, i = t / nc;
+            if (w < ncols) X[(long)c * a.X_cstride + (long)i * a.inner + col0 + w] = v;
+          });
+    }
     __syncthreads();
   }
 }
@@ -654,11 +672,13 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
   // components in groups of P::CP per transform; LDS tile [row][comp][column]
   constexpr int CPN = P::CP;
   const int LW = P::rowlen(CPN * W);
-  // several potentials per frequency (3-D dual, elasticity; generic kernels
-  // only): each is projected in turn, the transforms of the components repeated
-  const int npot = (P::WC == 0) ? a.g.npot : 1;
+  // 3-D, one component per transform: two transforms, X_0 and xi_1 X_1 +
+  // xi_2 X_2, the sum divided by |xi| at the end (see inv_xi).  Cells with
+  // several potentials per frequency do not come here (basis map + plain pass)
+  constexpr int FOLD = (CPN != 1 || P::SL == 1) ? 0 : (P::SL == 2) ? 1 : -1;
+  const bool fold = (FOLD == 1) || (FOLD == -1 && a.g.d == 3);
   double part = 0.0;
-  for (int pot = 0; pot < npot; ++pot) {
+  {
     cpx<T> acc[PMAX];
 #pragma unroll
     for (int it = 0; it < PMAX; ++it) acc[it] = cpx<T>{T(0), T(0)};
@@ -677,14 +697,21 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
           pre[c][u] = X0[(long)c * a.X_cstride + (long)i * a.inner + min(w, ncols - 1)];
         }
       }
+      // two transforms: X_0, and xi_1 X_1 + xi_2 X_2 (see inv_xi)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 2; ++c) {
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
           const int f = (int)threadIdx.x + u * NT;
           if (f < P::NF * P::WC) {
             const int i = f / P::WC, w = f % P::WC;
-            lds[i * LW + w] = (w < ncols) ? pre[c][u] : cpx<T>{T(0), T(0)};
+            cpx<T> v = pre[0][u];
+            if (c == 1) {
+              const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
+              v = cpx<T>{cx.x1 * pre[1][u].x + cx.x2 * pre[2][u].x,
+                         cx.x1 * pre[1][u].y + cx.x2 * pre[2][u].y};
+            }
+            lds[i * LW + w] = (w < ncols) ? v : cpx<T>{T(0), T(0)};
           }
         }
         __syncthreads();
@@ -694,19 +721,36 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
           int i, w;
           if (pos(it, i, w)) {
             const int row = (n_out == n_fft) ? i : posk(kof(i, n_out), n_fft);
-            const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
             const cpx<T> v = lds[row * LW + w];
-            const T nvc = normal_comp<T>(a.g, kof(i, n_out), cx, c);
-            acc[it].x += nvc * v.x;
-            acc[it].y += nvc * v.y;
+            const T f0 = (c == 0) ? T(kof(i, n_out)) * T(a.g.invY[0]) : T(1);
+            acc[it].x += f0 * v.x;
+            acc[it].y += f0 * v.y;
           }
         }
         __syncthreads();
       }
     }
-    for (int al0 = 0; al0 < (P::PRE ? 0 : a.d); al0 += CPN) {
+#pragma unroll 1
+    for (int al0 = 0; al0 < (P::PRE ? 0 : fold ? 2 : a.d); al0 += CPN) {
       constexpr int nc = CPN;   // CP > 1 kernels serve only cells with CP components
       const cpx<T>* X = a.X + (long)item * a.X_stride + (long)al0 * a.X_cstride + col0;
+      if (fold && al0 == 1) {
+        // xi_1 X_1 + xi_2 X_2, combined as it is loaded
+        in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
+            n_fft * W,
+            [=](int f) __attribute__((always_inline)) {
+              const int w = f % W, i = f / W;
+              const long e = (long)i * a.inner + min(w, ncols - 1);
+              return cpx2<T>{X[e], X[e + a.X_cstride]};
+            },
+            [=](int f, const cpx2<T>& v) __attribute__((always_inline)) {
+              const int w = f % W, i = f / W;
+              const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
+              lds[i * LW + w] = (w < ncols) ? cpx<T>{cx.x1 * v.a.x + cx.x2 * v.b.x,
+                                                     cx.x1 * v.a.y + cx.x2 * v.b.y}
+                                            : cpx<T>{T(0), T(0)};
+            });
+      } else
       in_rounds<NT, rounds_ch(P::NF * P::WC * P::CP, NT)>(
           n_fft * W * nc,
           [=](int f) __attribute__((always_inline)) {
@@ -727,9 +771,8 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
           const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, min(col0 + w, a.inner - 1));
           for (int c = 0; c < nc; ++c) {
             const cpx<T> v = lds[row * LW + c * W + w];
-            const T nvc = (npot > 1) ? pot_comp<T>(a.g, kof(i, n_out), min(col0 + w, a.inner - 1),
-                                                   al0 + c, pot)
-                                     : normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
+            const T nvc = fold ? (al0 == 0 ? T(kof(i, n_out)) * T(a.g.invY[0]) : T(1))
+                               : normal_comp<T>(a.g, kof(i, n_out), cx, al0 + c);
             acc[it].x += nvc * v.x;
             acc[it].y += nvc * v.y;
           }
@@ -737,7 +780,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
       }
       __syncthreads();
     }
-    const long sb = (long)item * a.s_stride + pot * a.g.pot_stride;
+    const long sb = (long)item * a.s_stride;
     // the epilogue's loads (p for (p, q), b for the residual) all go out first
     const cpx<T>* ld = (a.epi == EPI_STORE) ? a.p : (a.epi == EPI_RESID) ? a.b : nullptr;
     cpx<T> lv[PMAX];
@@ -759,6 +802,10 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
         const int h = col_fixed ? 1 : (a.g.d == 3) ? col % a.g.H : col;   // 2-D: column = h
         const double wt = col_fixed ? wt0 : (h == 0 ? 1.0 : 2.0);
         cpx<T> qv = cscale(acc[it], a.scale);
+        if (fold) {
+          const ColXi<T> cx = col_fixed ? cx0 : col_xi<T>(a.g, col);
+          qv = cscale(qv, inv_xi<T>(a.g, kof(i, n_out), cx));
+        }
         if (a.epi == EPI_STORE) {
           a.q[idx] = qv;
           if (a.p) {
