@@ -636,6 +636,248 @@ __global__ __launch_bounds__(NT) void k_col_reg2(ColPlainArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// first-axis passes of 3-D cells (one potential, row-major scalars: element
+// (i, column) at i si + column) with the
+// register pipeline of k_col_reg2: per tile two transforms (see inv_xi), each
+// with its first-stage operands taken from registers and its second-stage
+// results kept in registers, one LDS exchange per transform.  The thread of
+// first-stage butterfly (w, j) and of second-stage butterfly (w, k) works on
+// tile column w = threadIdx.x mod W throughout (NT a multiple of W), so its
+// part of xi is evaluated once.
+// ---------------------------------------------------------------------------
+template <class T, class SP, int NTRIAL, int W, int NT>
+__global__ __launch_bounds__(NT) void k_col_expand_r2(ColExpandArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int R1 = TwoRadices<typename SP::radices>::r1, R2 = TwoRadices<typename SP::radices>::r2;
+  constexpr int n = SP::n;
+  static_assert(R1 * R2 == n && !SP::blue, "two-stage Stockham plan");
+  static_assert(NT % W == 0, "a thread keeps one tile column");
+  constexpr int hk = (NTRIAL - 1) / 2;   // |k| of the trial frequencies
+  const int item = blockIdx.y;
+  if (a.sc && !item_live(a.sc[item])) return;
+  const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+  const int ncols = min(W, a.inner - col0);
+  const int w = (int)threadIdx.x % W;
+  const int wl = min(w, ncols - 1);   // loads of columns past the edge read the last one
+  const cpx<T>* c = a.c + (long)item * a.c_stride + col0 + wl;
+  cpx<T>* X = a.X + (long)item * a.X_stride + col0 + w;
+  const ColXi<T> cx = col_xi<T>(a.g, col0 + wl);
+  const T y0 = T(a.g.invY[0]);
+  // c / |xi| at the first-stage operand rows t = j + r R2 of every butterfly
+  // of this thread (0 outside the trial frequencies)
+  constexpr int T1 = R2 * W, M1 = (T1 + NT - 1) / NT;
+  cpx<T> pv[M1][R1];
+#pragma unroll
+  for (int it = 0; it < M1; ++it) {
+    const int j = min((int)threadIdx.x + it * NT, T1 - 1) / W;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int k = kof(j + r * R2, n);
+      const bool trial = (k >= -hk && k <= hk);
+      const cpx<T> x = c[(long)(trial ? posk(k, NTRIAL) : 0) * a.si];
+      pv[it][r] = trial ? cscale(x, inv_xi<T>(a.g, k, cx)) : cpx<T>{T(0), T(0)};
+    }
+  }
+  constexpr int T2 = R1 * W, M2 = (T2 + NT - 1) / NT;
+  // transform 0: xi_0 c / |xi| (X_0); transform 1: c / |xi| (X_1, X_2 = xi_1,
+  // xi_2 times it).  Unrolled: as a loop, the compiler keeps the twiddles and
+  // addresses it hoists out of it live across both transforms (~190 VGPRs
+  // against ~125)
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr) {
+#pragma unroll
+    for (int it = 0; it < M1; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      if (f < T1) {
+        const int j = f / W;
+        cpx<T> u[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+          u[r] = (tr == 0) ? cscale(pv[it][r], T(kof(j + r * R2, n)) * y0) : pv[it][r];
+        Dft<T, R1, +1>::run(u);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) lds[(j * R1 + r) * W + w] = u[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < M2; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      if (f >= T2) continue;
+      const int k = f / W;
+      cpx<T> u[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) u[r] = lds[(k + r * R1) * W + w];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) {
+        cpx<T> t = a.tw[k * (R2 - 1) + r - 1];
+        t.y = -t.y;
+        u[r] = cmul(u[r], t);
+      }
+      Dft<T, R2, +1>::run(u);
+      if (w >= ncols) continue;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const long e = (long)(k + r * R1) * a.inner;
+        if (tr == 0) {
+          X[e] = u[r];
+        } else {
+          X[a.X_cstride + e] = cscale(u[r], cx.x1);
+          X[2 * a.X_cstride + e] = cscale(u[r], cx.x2);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, class SP, int NTRIAL, int W, int NT>
+__global__ __launch_bounds__(NT) void k_col_project_r2(ColProjectArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int R1 = TwoRadices<typename SP::radices>::r1, R2 = TwoRadices<typename SP::radices>::r2;
+  constexpr int n = SP::n;
+  static_assert(R1 * R2 == n && !SP::blue, "two-stage Stockham plan");
+  static_assert(NT % W == 0, "a thread keeps one tile column");
+  constexpr int hk = (NTRIAL - 1) / 2;
+  const int item = blockIdx.y;
+  if (a.sc && !item_live_project(a.sc[item])) {
+    // an item whose update broke down stops here: the first workgroup raises
+    // halt for the update of this iteration (no workgroup here reads it)
+    const ItemScal& q0 = a.sc[item];
+    if (q0.active && q0.broke && a.rr_part && blockIdx.x == 0 && threadIdx.x == 0)
+      a.sc[item].halt = 1;
+    return;
+  }
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int col0 = tile * W;
+  const int ncols = min(W, a.inner - col0);
+  const int w = (int)threadIdx.x % W;
+  const int wl = min(w, ncols - 1);
+  const cpx<T>* X = a.X + (long)item * a.X_stride + col0 + wl;
+  const ColXi<T> cx = col_xi<T>(a.g, col0 + wl);
+  const T y0 = T(a.g.invY[0]);
+  constexpr int T1 = R2 * W, M1 = (T1 + NT - 1) / NT;
+  constexpr int T2 = R1 * W, M2 = (T2 + NT - 1) / NT;
+  // xi_0 F[X_0] + F[xi_1 X_1 + xi_2 X_2] at the second-stage result rows
+  cpx<T> acc[M2][R2];
+#pragma unroll
+  for (int it = 0; it < M2; ++it)
+#pragma unroll
+    for (int r = 0; r < R2; ++r) acc[it][r] = cpx<T>{T(0), T(0)};
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr) {
+#pragma unroll
+    for (int it = 0; it < M1; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      const int j = min(f, T1 - 1) / W;
+      cpx<T> u[R1];
+      if (tr == 0) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) u[r] = X[(long)(j + r * R2) * a.inner];
+      } else {
+        cpx<T> u2[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          u[r] = X[a.X_cstride + (long)(j + r * R2) * a.inner];
+          u2[r] = X[2 * a.X_cstride + (long)(j + r * R2) * a.inner];
+        }
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+          u[r] = cpx<T>{cx.x1 * u[r].x + cx.x2 * u2[r].x, cx.x1 * u[r].y + cx.x2 * u2[r].y};
+      }
+      if (f < T1) {
+        Dft<T, R1, -1>::run(u);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) lds[(j * R1 + r) * W + w] = u[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < M2; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      if (f >= T2) continue;
+      const int k = f / W;
+      cpx<T> u[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) u[r] = lds[(k + r * R1) * W + w];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) u[r] = cmul(u[r], a.tw[k * (R2 - 1) + r - 1]);
+      Dft<T, R2, -1>::run(u);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const T f0 = (tr == 0) ? T(kof(k + r * R1, n)) * y0 : T(1);
+        acc[it][r].x += f0 * u[r].x;
+        acc[it][r].y += f0 * u[r].y;
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue at the trial rows among this thread's result rows t = k + r R1;
+  // its loads (p for (p, q), b for the residual) all go out first
+  const long sb = (long)item * a.s_stride + col0 + wl;
+  const cpx<T>* ld = (a.epi == EPI_STORE) ? a.p : (a.epi == EPI_RESID) ? a.b : nullptr;
+  cpx<T> lv[M2][R2];
+#pragma unroll
+  for (int it = 0; it < M2; ++it) {
+    const int k = min((int)threadIdx.x + it * NT, T2 - 1) / W;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int kk = kof(k + r * R1, n);
+      const bool trial = (kk >= -hk && kk <= hk);
+      lv[it][r] = cpx<T>{T(0), T(0)};
+      if (ld) lv[it][r] = ld[sb + (long)(trial ? posk(kk, NTRIAL) : 0) * a.si];
+    }
+  }
+  // Hermitian weight of the column: 1 on the h = 0 plane, else 2
+  const double wt = (((col0 + w) % a.g.H) == 0) ? 1.0 : 2.0;
+  double part = 0.0;
+#pragma unroll
+  for (int it = 0; it < M2; ++it) {
+    const int f = (int)threadIdx.x + it * NT;
+    const int k = min(f, T2 - 1) / W;
+    const bool live = (f < T2) && (w < ncols);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int kk = kof(k + r * R1, n);
+      if (!live || kk < -hk || kk > hk) continue;
+      const long idx = sb + (long)posk(kk, NTRIAL) * a.si;
+      const cpx<T> qv = cscale(cscale(acc[it][r], a.scale), inv_xi<T>(a.g, kk, cx));
+      if (a.epi == EPI_STORE) {
+        a.q[idx] = qv;
+        if (a.p) part += wt * ((double)lv[it][r].x * (double)qv.x + (double)lv[it][r].y * (double)qv.y);
+      } else if (a.epi == EPI_RHS) {
+        const cpx<T> mq = cpx<T>{-qv.x, -qv.y};
+        a.q[idx] = mq;
+        if (a.r) a.r[idx] = mq;
+        if (a.pp) a.pp[idx] = mq;
+        if (a.x) a.x[idx] = cpx<T>{T(0), T(0)};
+        part += wt * ((double)mq.x * (double)mq.x + (double)mq.y * (double)mq.y);
+      } else {  // EPI_RESID: r = b - q
+        const cpx<T> rv = cpx<T>{lv[it][r].x - qv.x, lv[it][r].y - qv.y};
+        a.r[idx] = rv;
+        part += wt * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
+      }
+    }
+  }
+  if (a.partials) {
+    part = block_sum<NT>(part);
+    if (threadIdx.x == 0) a.partials[(long)item * a.P + tile] = part;
+  }
+  if (a.rr_part && blockIdx.x == 0) {
+    // bookkeeping of the update before this iteration's expansion (that
+    // expansion has finished reading rho; no other workgroup here reads it)
+    const bool fresh = a.sc[item].fresh != 0;
+    const double s = fresh ? 0.0 : sum_partials_wave(a.rr_part + (long)item * a.P, a.rr_n);
+    if (threadIdx.x == 0) {
+      if (fresh) a.sc[item].fresh = 0;
+      else cg_book(a.sc[item], s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // axis 0 forward + truncation + projection q = n . F_0[X], CG epilogues
 // ---------------------------------------------------------------------------
 template <class T, class P, int PMAX>

@@ -125,5 +125,10 @@ RegColReg2<T, P255, 255, 16, 512> g255t;
 RegColReg2<T, P253, 127, 16, 512> g253t;
 RegColReg2<T, P253, 127, 16, 256> g253;
 RegColReg2<T, P63, 63, 16, 128> g63;
+// 3-D first-axis expansion and projection with the register pipeline
+// (256 threads: four workgroups per CU; 320 and 512 threads, one
+// butterfly per thread in both stages, ran slower)
+RegColR2<T, P255, 255, 16, 256> e255;
+RegColR2<T, P253, 127, 16, 256> e253;
 }  // namespace
 }  // namespace hom

@@ -164,6 +164,20 @@ struct RegColReg2 {
   }
 };
 
+// first-axis expansion and projection of 3-D cells with the register
+// pipeline (k_col_expand_r2 / k_col_project_r2), two-stage plans
+template <class T, class SP, int NTRIAL, int W, int NT>
+struct RegColR2 {
+  static constexpr size_t lds = (size_t)SP::n * W * sizeof(cpx<T>);
+  static_assert(lds <= 66 * 1024, "column tile exceeds the LDS budget");
+  RegColR2() {
+    RegColReg2<T, SP, NTRIAL, W, NT>::add_kind(KK_EXPAND, 3, lds,
+                                               (const void*)&k_col_expand_r2<T, SP, NTRIAL, W, NT>);
+    RegColReg2<T, SP, NTRIAL, W, NT>::add_kind(KK_PROJECT, 3, lds,
+                                               (const void*)&k_col_project_r2<T, SP, NTRIAL, W, NT>);
+  }
+};
+
 // plans
 using P1023 = SPlan<1023, 1023, 0, Rad<31, 11, 3>>;
 using P255 = SPlan<255, 255, 0, Rad<17, 15>>;
