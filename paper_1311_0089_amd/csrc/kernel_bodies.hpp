@@ -645,7 +645,10 @@ __global__ __launch_bounds__(NT) void k_col_reg2(ColPlainArgs<T> a) {
 // tile column w = threadIdx.x mod W throughout (NT a multiple of W), so its
 // part of xi is evaluated once.
 // ---------------------------------------------------------------------------
-template <class T, class SP, int NTRIAL, int W, int NT>
+// PAIR: the expansion leaves Z in place of X_1 and nothing in X_2, and the
+// projection reads xi_1 X_1 + xi_2 X_2, already combined, in place of X_1: the
+// middle-axis passes of such cells apply xi_1 and xi_2 (k_col_mid2)
+template <class T, class SP, int NTRIAL, int W, int NT, bool PAIR = false>
 __global__ __launch_bounds__(NT) void k_col_expand_r2(ColExpandArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -722,6 +725,8 @@ __global__ __launch_bounds__(NT) void k_col_expand_r2(ColExpandArgs<T> a) {
         const long e = (long)(k + r * R1) * a.inner;
         if (tr == 0) {
           X[e] = u[r];
+        } else if (PAIR) {
+          X[a.X_cstride + e] = u[r];
         } else {
           X[a.X_cstride + e] = cscale(u[r], cx.x1);
           X[2 * a.X_cstride + e] = cscale(u[r], cx.x2);
@@ -732,7 +737,7 @@ __global__ __launch_bounds__(NT) void k_col_expand_r2(ColExpandArgs<T> a) {
   }
 }
 
-template <class T, class SP, int NTRIAL, int W, int NT>
+template <class T, class SP, int NTRIAL, int W, int NT, bool PAIR = false>
 __global__ __launch_bounds__(NT) void k_col_project_r2(ColProjectArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -773,9 +778,9 @@ __global__ __launch_bounds__(NT) void k_col_project_r2(ColProjectArgs<T> a) {
       const int f = (int)threadIdx.x + it * NT;
       const int j = min(f, T1 - 1) / W;
       cpx<T> u[R1];
-      if (tr == 0) {
+      if (tr == 0 || PAIR) {
 #pragma unroll
-        for (int r = 0; r < R1; ++r) u[r] = X[(long)(j + r * R2) * a.inner];
+        for (int r = 0; r < R1; ++r) u[r] = X[tr * a.X_cstride + (long)(j + r * R2) * a.inner];
       } else {
         cpx<T> u2[R1];
 #pragma unroll
@@ -873,6 +878,140 @@ __global__ __launch_bounds__(NT) void k_col_project_r2(ColProjectArgs<T> a) {
     if (threadIdx.x == 0) {
       if (fresh) a.sc[item].fresh = 0;
       else cg_book(a.sc[item], s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// middle-axis (3-D axis 1) passes between PAIR first-axis passes, register
+// pipeline as in k_col_reg2.  Inverse: part 0 transforms X_0; part 1 reads Z
+// once and gives X_1 = F^-1[xi_1 Z] and X_2 = xi_2 F^-1[Z] (xi_1 varies along
+// this axis, xi_2 = h / Y_2 is constant on a tile column).  Forward: part 0
+// transforms X_0; part 1 gives xi_1 F[X_1] + xi_2 F[X_2] into the X_1 slot.
+// The grid's z index is item * 2 + part.
+// ---------------------------------------------------------------------------
+template <class T, class SP, int NTRIAL, int W, int NT, int S>
+__global__ __launch_bounds__(NT) void k_col_mid2(ColPlainArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int R1 = TwoRadices<typename SP::radices>::r1, R2 = TwoRadices<typename SP::radices>::r2;
+  constexpr int n = SP::n;
+  static_assert(R1 * R2 == n && !SP::blue, "two-stage Stockham plan");
+  static_assert(NT % W == 0, "a thread keeps one tile column");
+  constexpr int n_in = (S > 0) ? NTRIAL : n, n_out = (S > 0) ? n : NTRIAL;
+  constexpr int hk = (NTRIAL - 1) / 2;
+  const int item = blockIdx.z >> 1, part = blockIdx.z & 1;
+  if (a.sc && !item_live(a.sc[item])) return;
+  const int o = blockIdx.y;
+  const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+  const int ncols = min(W, a.inner - col0);
+  const int w = (int)threadIdx.x % W;
+  const int wl = min(w, ncols - 1);
+  const cpx<T>* in = a.in + (long)item * a.in_stride + (long)o * n_in * a.inner + col0 + wl;
+  cpx<T>* out = a.out + (long)item * a.out_stride + (long)o * n_out * a.inner + col0 + w;
+  const T x1s = T(a.xi1_step), xi2 = T((col0 + wl) * a.xi2_step);
+  const int ntr = part ? 2 : 1;
+  constexpr int T1 = R2 * W, M1 = (T1 + NT - 1) / NT;
+  constexpr int T2 = R1 * W, M2 = (T2 + NT - 1) / NT;
+  // inverse: the trial rows of X_0 or Z at this thread's first-stage operand rows
+  cpx<T> pv[M1][R1];
+  if (S > 0) {
+    const cpx<T>* src = in + (part ? a.in_cstride : 0);
+#pragma unroll
+    for (int it = 0; it < M1; ++it) {
+      const int j = min((int)threadIdx.x + it * NT, T1 - 1) / W;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int k = kof(j + r * R2, n);
+        const bool trial = (k >= -hk && k <= hk);
+        const cpx<T> x = src[(long)(trial ? posk(k, NTRIAL) : 0) * a.inner];
+        pv[it][r] = trial ? x : cpx<T>{T(0), T(0)};
+      }
+    }
+  }
+  // forward, part 1: xi_1 F[X_1] + xi_2 F[X_2] at the second-stage result rows
+  cpx<T> acc[M2][R2];
+#pragma unroll
+  for (int it = 0; it < M2; ++it)
+#pragma unroll
+    for (int r = 0; r < R2; ++r) acc[it][r] = cpx<T>{T(0), T(0)};
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr) {
+    if (tr >= ntr) break;
+#pragma unroll
+    for (int it = 0; it < M1; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      const int j = min(f, T1 - 1) / W;
+      cpx<T> u[R1];
+      if (S > 0) {
+        // part 1, transform 0: xi_1 Z
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+          u[r] = (part && tr == 0) ? cscale(pv[it][r], T(kof(j + r * R2, n)) * x1s) : pv[it][r];
+      } else {
+        const cpx<T>* src = in + (long)(part + tr) * a.in_cstride;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) u[r] = src[(long)(j + r * R2) * a.inner];
+      }
+      if (f < T1) {
+        Dft<T, R1, S>::run(u);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) lds[(j * R1 + r) * W + w] = u[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < M2; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      if (f >= T2) continue;
+      const int k = f / W;
+      cpx<T> u[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) u[r] = lds[(k + r * R1) * W + w];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) {
+        cpx<T> t = a.tw[k * (R2 - 1) + r - 1];
+        if (S > 0) t.y = -t.y;
+        u[r] = cmul(u[r], t);
+      }
+      Dft<T, R2, S>::run(u);
+      if (S > 0) {
+        if (w >= ncols) continue;
+        // X_0 (part 0), X_1 (part 1, transform 0), X_2 = xi_2 F^-1[Z] (transform 1)
+        cpx<T>* dst = out + (long)(part + tr) * a.out_cstride;
+        const T sc = (part && tr == 1) ? xi2 : T(1);
+#pragma unroll
+        for (int r = 0; r < R2; ++r) dst[(long)(k + r * R1) * a.inner] = cscale(u[r], sc);
+      } else if (part == 0) {
+        if (w >= ncols) continue;
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          const int kk = kof(k + r * R1, n);
+          if (kk >= -hk && kk <= hk) out[(long)posk(kk, NTRIAL) * a.inner] = cscale(u[r], a.scale);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          const T fr = (tr == 0) ? T(kof(k + r * R1, n)) * x1s : xi2;
+          acc[it][r].x += fr * u[r].x;
+          acc[it][r].y += fr * u[r].y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (S < 0 && part) {
+#pragma unroll
+    for (int it = 0; it < M2; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      if (f >= T2 || w >= ncols) continue;
+      const int k = f / W;
+      cpx<T>* dst = out + a.out_cstride;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int kk = kof(k + r * R1, n);
+        if (kk >= -hk && kk <= hk) dst[(long)posk(kk, NTRIAL) * a.inner] = cscale(acc[it][r], a.scale);
+      }
     }
   }
 }

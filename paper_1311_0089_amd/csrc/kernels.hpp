@@ -112,6 +112,8 @@ struct ColPlainArgs {
   long in_stride, in_cstride, out_stride, out_cstride;
   int outer, n_in, n_fft, n_out, inner, W, d;
   T scale;           // 1/n on forward passes
+  // k_col_mid2 only: xi_1 = k_1 xi1_step along the pass, xi_2 = h xi2_step
+  double xi1_step, xi2_step;
   FftPlan plan;
   const cpx<T>* tw;
   ItemScal* sc;
@@ -204,7 +206,9 @@ struct CgDirArgs {
 
 // compile-time specialised pass kernels, registered by kernels_static*.hip
 enum { KK_EXPAND = 0, KK_PROJECT = 1, KK_PLAIN_INV = 2, KK_PLAIN_FWD = 3, KK_ROW = 4,
-       KK_ROW_CONST = 5, KK_ROW_SYNTH = 6 };
+       KK_ROW_CONST = 5, KK_ROW_SYNTH = 6,
+       // 3-D cells with two spectra between the first- and middle-axis passes
+       KK_EXPAND2 = 7, KK_PROJECT2 = 8, KK_MID2_INV = 9, KK_MID2_FWD = 10 };
 struct StaticKernel {
   int kind, esz, n, ntrial, d;  // d: component count (row kernels), else 0
   const void* fn;

@@ -130,5 +130,10 @@ RegColReg2<T, P63, 63, 16, 128> g63;
 // butterfly per thread in both stages, ran slower)
 RegColR2<T, P255, 255, 16, 256> e255;
 RegColR2<T, P253, 127, 16, 256> e253;
+RegMid2<T, P255, 255, 16, 256> m255;
+RegMid2<T, P253, 127, 16, 256> m253;
+RegMid2<T, P63, 63, 16, 128> m63;
+RegMid2<T, P255, 255, 16, 512> m255t;
+RegMid2<T, P253, 127, 16, 512> m253t;
 }  // namespace
 }  // namespace hom

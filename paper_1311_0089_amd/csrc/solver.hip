@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cell.hpp"
@@ -257,6 +258,24 @@ static const StaticKernel* col_static(const CellImpl* c, int kind, int esz, int 
 
 static long inner0(const CellImpl* c) { return (c->dd == 3) ? (long)c->N[1] * c->H : c->H; }
 
+// 3-D cells of one potential whose FP32 first- and middle-axis passes hand two
+// spectra to each other instead of three (X_0 and Z = F_0^-1[c / |xi|] on the
+// way in, X_0 and xi_1 X_1 + xi_2 X_2 on the way out; the middle-axis passes
+// apply xi_1 and xi_2): when each of the four passes has such a kernel for
+// the shape.  Every pass decides it the same way, so they agree.
+template <class T>
+static bool pair_mode(const CellImpl* c) {
+  if (!std::is_same<T, float>::value || c->dd != 3 || c->npot != 1) return false;
+  const DevPlan *p0, *p1;
+  if (get_dev_plan(c->Q[0], &p0) != hipSuccess || get_dev_plan(c->Q[1], &p1) != hipSuccess)
+    return false;
+  const int esz = (int)sizeof(cpx<T>);
+  return find_static(KK_EXPAND2, esz, c->Q[0], c->N[0], 3, p0->p) &&
+         find_static(KK_PROJECT2, esz, c->Q[0], c->N[0], 3, p0->p) &&
+         find_static(KK_MID2_INV, esz, c->Q[1], c->N[1], 0, p1->p) &&
+         find_static(KK_MID2_FWD, esz, c->Q[1], c->N[1], 0, p1->p);
+}
+
 // Layout of the scalar spectra (c, r, p, q, b, x) of an item: 2-D cells keep
 // them column-major (axis 0 contiguous), so the first-axis passes, whose
 // tiles are few columns wide there, load and store whole cache lines; 3-D
@@ -353,7 +372,8 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
     if ((e = launch_basis_expand<T>(b, items, blocks, c->stream)) != hipSuccess) return e;
     return plain_axis0<T>(c, items, +1, G0, w.X2, w.X1, sc);
   }
-  const StaticKernel* sk = col_static(c, KK_EXPAND, sizeof(cpx<T>), G0, p0->p);
+  const StaticKernel* sk = col_static(c, pair_mode<T>(c) ? KK_EXPAND2 : KK_EXPAND, sizeof(cpx<T>),
+                                      G0, p0->p);
   if (sk) {
     a.W = sk->W;
     return launch_col_expand<T>(a, items, sk->lds, c->stream, sk);
@@ -387,6 +407,18 @@ static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int 
   a.plan = p1->p;
   a.tw = tw_of<T>(p1);
   a.sc = sc;
+  if (pair_mode<T>(c)) {
+    // two parts per item: X_0, and the xi_1 / xi_2 pair (k_col_mid2)
+    const StaticKernel* sk = find_static(sign > 0 ? KK_MID2_INV : KK_MID2_FWD, sizeof(cpx<T>),
+                                         G1, c->N[1], 0, p1->p);
+    if (!sk) return hipErrorInvalidValue;
+    const NormalGeo g = normal_geo(c);
+    a.d = 2;
+    a.xi1_step = g.invY[1];
+    a.xi2_step = g.invY[2];
+    a.W = sk->W;
+    return launch_col_plain<T>(a, items, sign, sk->lds, c->stream, sk);
+  }
   const StaticKernel* sk = find_static(sign > 0 ? KK_PLAIN_INV : KK_PLAIN_FWD, sizeof(cpx<T>),
                                        G1, c->N[1], 0, p1->p);
   if (sk) {
@@ -522,7 +554,8 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
     if (tiles) *tiles = blocks;
     return launch_basis_project<T>(ba, items, blocks, c->stream);
   }
-  const StaticKernel* sk = col_static(c, KK_PROJECT, sizeof(cpx<T>), G0, p0->p);
+  const StaticKernel* sk = col_static(c, pair_mode<T>(c) ? KK_PROJECT2 : KK_PROJECT,
+                                      sizeof(cpx<T>), G0, p0->p);
   if (sk) {
     a.W = sk->W;
     if (tiles) *tiles = (a.inner + sk->W - 1) / sk->W;
@@ -541,7 +574,8 @@ int project_tiles(CellImpl* c) {
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return 0;
   const int inner = (int)inner0(c);
   if (c->npot > 1) return basis_blocks(c);
-  const StaticKernel* sk = col_static(c, KK_PROJECT, sizeof(cpx<T>), c->Q[0], p0->p);
+  const StaticKernel* sk = col_static(c, pair_mode<T>(c) ? KK_PROJECT2 : KK_PROJECT,
+                                      sizeof(cpx<T>), c->Q[0], p0->p);
   if (sk) return (inner + sk->W - 1) / sk->W;
   ColShape sh;
   if (col_shape(p0->p, c->N[0], inner, sizeof(cpx<T>), &sh) != hipSuccess) return 0;
@@ -1837,14 +1871,17 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   // algorithmic bytes of the steady state inside a graph: the direction step
   // reads r, p, x and writes p, x; the expansion reads p and writes the d
   // fields; the update reads r, q, writes r
+  // (cells that hand two spectra between the first- and middle-axis passes:
+  // two fields there instead of d)
+  const double nx = pair_mode<T>(c) ? 2.0 : (double)c->nf;
   bytes[8] = L * 5.0 * S * esz;
-  bytes[0] = L * (S * esz + (double)c->nf * Q0 * inner * esz);
+  bytes[0] = L * (S * esz + nx * Q0 * inner * esz);
   if (c->dd == 3) {
-    bytes[1] = L * (double)c->nf * Q0 * c->H * esz * (c->N[1] + Q1);
+    bytes[1] = L * (double)Q0 * c->H * esz * (nx * c->N[1] + (double)c->nf * Q1);
     bytes[3] = bytes[1];
   }
   bytes[2] = L * 2.0 * c->nf * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
-  bytes[4] = L * ((double)c->nf * Q0 * inner * esz + 2.0 * S * esz);
+  bytes[4] = L * (nx * Q0 * inner * esz + 2.0 * S * esz);
   bytes[5] = L * 3.0 * S * esz;
   for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
   bytes[7] += bytes[8];
@@ -1900,11 +1937,16 @@ static std::vector<PassKey> pass_keys(const CellImpl* c) {
   // a cell with two potentials per frequency runs the generic expand and
   // project kernels: their variants are not its to time or force
   const bool col = (c->npot == 1);
-  if (col) v.push_back({0, TuneKey{KK_EXPAND, esz, Q0, c->N[0], dd}, Q0});
-  if (dd == 3) v.push_back({1, TuneKey{KK_PLAIN_INV, esz, Q1, c->N[1], 0}, Q1});
+  // cells whose first- and middle-axis passes hand over two spectra tune
+  // the kernels of that form
+  const bool pair = pair_mode<T>(c);
+  if (col) v.push_back({0, TuneKey{pair ? KK_EXPAND2 : KK_EXPAND, esz, Q0, c->N[0], dd}, Q0});
+  if (dd == 3)
+    v.push_back({1, TuneKey{pair ? KK_MID2_INV : KK_PLAIN_INV, esz, Q1, c->N[1], 0}, Q1});
   v.push_back({2, TuneKey{KK_ROW, esz, Glast, c->N[dd - 1], dd}, Glast});
-  if (dd == 3) v.push_back({3, TuneKey{KK_PLAIN_FWD, esz, Q1, c->N[1], 0}, Q1});
-  if (col) v.push_back({4, TuneKey{KK_PROJECT, esz, Q0, c->N[0], dd}, Q0});
+  if (dd == 3)
+    v.push_back({3, TuneKey{pair ? KK_MID2_FWD : KK_PLAIN_FWD, esz, Q1, c->N[1], 0}, Q1});
+  if (col) v.push_back({4, TuneKey{pair ? KK_PROJECT2 : KK_PROJECT, esz, Q0, c->N[0], dd}, Q0});
   return v;
 }
 

@@ -171,10 +171,24 @@ struct RegColR2 {
   static constexpr size_t lds = (size_t)SP::n * W * sizeof(cpx<T>);
   static_assert(lds <= 66 * 1024, "column tile exceeds the LDS budget");
   RegColR2() {
-    RegColReg2<T, SP, NTRIAL, W, NT>::add_kind(KK_EXPAND, 3, lds,
-                                               (const void*)&k_col_expand_r2<T, SP, NTRIAL, W, NT>);
-    RegColReg2<T, SP, NTRIAL, W, NT>::add_kind(KK_PROJECT, 3, lds,
-                                               (const void*)&k_col_project_r2<T, SP, NTRIAL, W, NT>);
+    using R = RegColReg2<T, SP, NTRIAL, W, NT>;
+    R::add_kind(KK_EXPAND, 3, lds, (const void*)&k_col_expand_r2<T, SP, NTRIAL, W, NT>);
+    R::add_kind(KK_PROJECT, 3, lds, (const void*)&k_col_project_r2<T, SP, NTRIAL, W, NT>);
+    // the same with two spectra towards the middle-axis passes (k_col_mid2)
+    R::add_kind(KK_EXPAND2, 3, lds, (const void*)&k_col_expand_r2<T, SP, NTRIAL, W, NT, true>);
+    R::add_kind(KK_PROJECT2, 3, lds, (const void*)&k_col_project_r2<T, SP, NTRIAL, W, NT, true>);
+  }
+};
+
+// middle-axis passes between the two-spectra first-axis passes
+template <class T, class SP, int NTRIAL, int W, int NT>
+struct RegMid2 {
+  static constexpr size_t lds = (size_t)SP::n * W * sizeof(cpx<T>);
+  static_assert(lds <= 66 * 1024, "column tile exceeds the LDS budget");
+  RegMid2() {
+    using R = RegColReg2<T, SP, NTRIAL, W, NT>;
+    R::add_kind(KK_MID2_INV, 0, lds, (const void*)&k_col_mid2<T, SP, NTRIAL, W, NT, +1>);
+    R::add_kind(KK_MID2_FWD, 0, lds, (const void*)&k_col_mid2<T, SP, NTRIAL, W, NT, -1>);
   }
 };
 

@@ -28,9 +28,9 @@ RECORD_TAG = "traffic-record:"
 # slot -> (kernel name prefixes, suffix or None) of the FP32 CG iteration
 SLOTS = {
     "expand0": (("hom::k_col_expand<float", "hom::k_col_expand_r2<float"), None),
-    "inv1": (("hom::k_col_plain<float", "hom::k_col_reg2<float"), ", 1>"),
+    "inv1": (("hom::k_col_plain<float", "hom::k_col_reg2<float", "hom::k_col_mid2<float"), ", 1>"),
     "row": (("hom::k_row<float",), ", 0>"),
-    "fwd1": (("hom::k_col_plain<float", "hom::k_col_reg2<float"), ", -1>"),
+    "fwd1": (("hom::k_col_plain<float", "hom::k_col_reg2<float", "hom::k_col_mid2<float"), ", -1>"),
     "project0": (("hom::k_col_project<float", "hom::k_col_project_r2<float"), None),
     "update": (("hom::k_cg_update<float>",), None),
     "direction": (("hom::k_cg_direction<float>",), None),

@@ -157,7 +157,10 @@ VARIANT_CASES = [((1023, 15), 0, 0), ((15, 1023), 1, 0), ((255, 15), 0, 0),
                  ((31, 15), 0, 1), ((15, 31), 2, 1), ((15, 15, 31), 0, 1),
                  # middle axes of 255, 253 (trial 127) and 63: the register-pipeline
                  # plain passes beside the LDS-staged ones
-                 ((15, 255, 15), 0, 0), ((9, 127, 7), 1, 1), ((15, 63, 15), 2, 0)]
+                 ((15, 255, 15), 0, 0), ((9, 127, 7), 1, 1), ((15, 63, 15), 2, 0),
+                 # two spectra between the first- and middle-axis FP32 passes
+                 # (first axis 255 or Ga 253, middle axis 63 or Ga 253)
+                 ((255, 63, 15), 2, 0), ((127, 127, 3), 0, 1)]
 
 
 @gpu
