@@ -374,6 +374,15 @@ __device__ __forceinline__ void cg_book(ItemScal& q, double s) {
   q.rho = s;
 }
 
+// (p, q) of this iteration from the last-axis pass's partials, summed in
+// fixed order by the first wave of a projection's workgroup 0 for the update
+// of the same iteration (no workgroup of the projection reads it)
+__device__ __forceinline__ void pq_total(ItemScal& q, const double* part, int n) {
+  if (threadIdx.x >= 64) return;
+  const double s = sum_partials_wave(part, n);
+  if (threadIdx.x == 0) q.pq = s;
+}
+
 // the decision cg_book will take, derived by every workgroup of the next
 // expansion: 1 if the item stops after its last update
 __device__ __forceinline__ bool cg_stops(const ItemScal& q, double s) {
@@ -880,6 +889,7 @@ __global__ __launch_bounds__(NT) void k_col_project_r2(ColProjectArgs<T> a) {
       else cg_book(a.sc[item], s);
     }
   }
+  if (a.pq_part && blockIdx.x == 0) pq_total(a.sc[item], a.pq_part + (long)item * a.P, a.pq_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -1223,6 +1233,7 @@ __global__ __launch_bounds__(P::NT, P::WPE) void k_col_project(ColProjectArgs<T>
       else cg_book(a.sc[item], s);
     }
   }
+  if (a.pq_part && blockIdx.x == 0) pq_total(a.sc[item], a.pq_part + (long)item * a.P, a.pq_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -1370,6 +1381,9 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
 
   if (MODE == ROW_APPLY || MODE == ROW_CONST) {
     const T* A = a.A + (long)(item / a.A_group) * a.A_stride;
+    // e . (A e) over this workgroup's real points: the CG's (p, q) by
+    // Parseval, with the forward passes' 1 / |Q| in pscale
+    double part = 0.0;
     in_rounds<NT, CHF>(
         RP * n,
         [=](int f) __attribute__((always_inline)) {
@@ -1380,7 +1394,7 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
           load_coef<T>(a.kind, d, A, a.A_cstride, (long)min(r1, a.rows - 1) * n + x, v.c1);
           return v;
         },
-        [=](int f, const Coef2<T>& v) __attribute__((always_inline)) {
+        [=, &part](int f, const Coef2<T>& v) __attribute__((always_inline)) {
           const int lp = f / n, x = f % n;
           const int r0 = 2 * (pair0 + lp);
           if (r0 >= a.rows) return;
@@ -1400,8 +1414,20 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
           flux_coef<T>(a.kind, d, v.c0, e0, j0);
           flux_coef<T>(a.kind, d, v.c1, e1, j1);
           for (int q = 0; q < d; ++q) lds[(q * RP + lp) * ls + x] = cpx<T>{j0[q], j1[q]};
+          if (MODE == ROW_APPLY) {
+            // the few terms of one point add up in T (for positive definite
+            // A without cancellation), the points in FP64
+            const bool two = r0 + 1 < a.rows;
+            T t = T(0);
+            for (int q = 0; q < d; ++q) t += e0[q] * j0[q] + (two ? e1[q] * j1[q] : T(0));
+            part += (double)t;
+          }
         });
     __syncthreads();
+    if (MODE == ROW_APPLY && a.partials) {
+      part = block_sum<NT>(part);
+      if (threadIdx.x == 0) a.partials[(long)item * a.P + pair0 / RP] = part * a.pscale;
+    }
   }
 
   // forward transform and split of the two packed real lines

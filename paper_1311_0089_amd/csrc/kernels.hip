@@ -128,14 +128,15 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(CgUpdateArgs<T> a) {
       }
     }
   };
-  // alpha = rho / (p, q), derived by every workgroup from the projection's
-  // partials in the same order (their first loads go out ahead of the data's)
+  // alpha = rho / (p, q), derived by every workgroup from the (p, q) partials
+  // (left by the last-axis pass, or the projection) in the same order (their
+  // first loads go out ahead of the data's)
   const double* pq = a.pq_part + (long)item * a.P;
   double ph[8];
-  partials_head(pq, a.pq_n, ph);
+  if (!a.pq_sc) partials_head(pq, a.pq_n, ph);
   long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
   load(e0);
-  const double g = partials_finish(pq, a.pq_n, ph);
+  const double g = a.pq_sc ? a.sc[item].pq : partials_finish(pq, a.pq_n, ph);
   if (!(g > 0.0) || !isfinite(g)) {
     // every workgroup derives the breakdown itself; the first one records it
     // for the passes of later iterations (none of this launch reads it)
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_basis_project(BasisArgs<T> a) {
       else cg_book(a.sc[item], s);
     }
   }
+  if (a.pq_part && blockIdx.x == 0) pq_total(a.sc[item], a.pq_part + (long)item * a.P, a.pq_n);
 }
 
 template <class T>

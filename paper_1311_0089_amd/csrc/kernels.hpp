@@ -35,6 +35,10 @@ struct CgFuse {
   int rr_n;
   // the last update left x to the direction step: x += alpha p (old p) there
   int xdef;
+  // the (p, q) partials of this iteration's last-axis pass: the projection's
+  // first workgroup sums them into ItemScal::pq for the update
+  const double* pq;
+  int pq_n;
 };
 
 // per-item solver scalars, device resident
@@ -61,6 +65,9 @@ struct ItemScal {
   // Moulinec-Suquet step 1 / lambda, kept here rather than in a captured
   // kernel argument: cells of one shape share an engine and its graphs
   double step;
+  // (p, q) of the current CG iteration, summed by the projection's first
+  // workgroup from the last-axis pass's partials; read by the update
+  double pq;
 };
 
 // an item the passes of a CG iteration still work on (the projection tests
@@ -140,6 +147,9 @@ struct ColProjectArgs {
   // stopping test and rho from the (r, r) partials of the last update
   const double* rr_part;
   int rr_n;
+  // the (p, q) partials to sum into ItemScal::pq in workgroup 0 (nullable)
+  const double* pq_part;
+  int pq_n;
   T scale;
   NormalGeo g;
   FftPlan plan;
@@ -166,6 +176,11 @@ struct RowArgs {
   FftPlan plan;
   const cpx<T>* tw;
   ItemScal* sc;
+  // ROW_APPLY: when non-null, the partial sums of e . (A e) over the real
+  // points of each workgroup, times pscale, at [item][P] (slot: row tile)
+  double* partials;
+  int P;
+  double pscale;
 };
 
 template <class T>
@@ -181,9 +196,10 @@ struct CgUpdateArgs {
   int P;
   ItemScal* sc;
   // partials of (p, q) left by the projection: every workgroup derives
-  // alpha = rho / (p, q) itself
+  // alpha = rho / (p, q) itself; pq_sc: (p, q) is ItemScal::pq instead
   const double* pq_part;
   int pq_n;
+  int pq_sc;
   // 1: x += alpha p here; 0: the next expansion does it (it reads p anyway)
   int xupd;
 };
@@ -313,6 +329,8 @@ struct BasisArgs {
   int P, epi;
   const double* rr_part;
   int rr_n;
+  const double* pq_part;
+  int pq_n;
   NormalGeo g;
   ItemScal* sc;
 };

@@ -174,9 +174,11 @@ int update_blocks(long S) {
 }
 
 int partial_slots(const CellImpl* c) {
-  // enough for every producer: column tiles (<= inner) and update blocks
+  // enough for every producer: column tiles (<= inner), last-axis tiles
+  // (<= row pairs) and update blocks
   long inner = (c->dd == 3) ? (long)c->N[1] * c->H : c->H;
-  long P = std::max<long>(inner, 512);
+  long rows = (c->dd == 3) ? (long)c->Q[0] * c->Q[1] : c->Q[0];
+  long P = std::max<long>(std::max<long>(inner, (rows + 1) / 2), 512);
   return (int)P;
 }
 
@@ -436,7 +438,7 @@ static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int 
 template <class T>
 static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, cpx<T>* out,
                             int G0, int G1, int Glast, const double* ureal, double* oreal,
-                            const double* dE, ItemScal* sc) {
+                            const double* dE, ItemScal* sc, double* partials = nullptr) {
   const DevPlan* pl;
   hipError_t e = get_dev_plan(Glast, &pl);
   if (e != hipSuccess) return e;
@@ -463,6 +465,9 @@ static hipError_t stage_row(CellImpl* c, int items, int mode, const cpx<T>* in, 
   a.plan = pl->p;
   a.tw = tw_of<T>(pl);
   a.sc = sc;
+  a.partials = (mode == ROW_APPLY) ? partials : nullptr;
+  a.P = partial_slots(c);
+  a.pscale = 1.0 / ((double)rows * Glast);
   const int Nlast = c->N[c->dd - 1];
   const int kind = (mode == ROW_APPLY) ? KK_ROW : (mode == ROW_CONST) ? KK_ROW_CONST
                  : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
@@ -517,6 +522,8 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
   if (cg) {
     a.rr_part = cg->rr;
     a.rr_n = cg->rr_n;
+    a.pq_part = cg->pq;
+    a.pq_n = cg->pq_n;
   }
   a.scale = T(1.0 / (double)G0);
   a.g = normal_geo(c);
@@ -548,6 +555,8 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
     ba.epi = epi;
     ba.rr_part = a.rr_part;
     ba.rr_n = a.rr_n;
+    ba.pq_part = a.pq_part;
+    ba.pq_n = a.pq_n;
     ba.g = a.g;
     ba.sc = sc;
     const int blocks = basis_blocks(c);
@@ -582,6 +591,22 @@ int project_tiles(CellImpl* c) {
   return (inner + sh.W - 1) / sh.W;
 }
 
+// workgroups per item of the last-axis flux pass (its partial sums)
+template <class T>
+int row_tiles(CellImpl* c) {
+  const int Glast = c->Q[c->dd - 1];
+  const DevPlan* pl;
+  if (get_dev_plan(Glast, &pl) != hipSuccess) return 0;
+  const long rows = (c->dd == 3) ? (long)c->Q[0] * c->Q[1] : c->Q[0];
+  const long pairs = (rows + 1) / 2;
+  const StaticKernel* sk =
+      find_static(KK_ROW, sizeof(cpx<T>), Glast, c->N[c->dd - 1], c->nf, pl->p);
+  int RP = sk ? sk->W : 0;
+  size_t lds = 0;
+  if (!sk && row_shape(pl->p, c->nf, rows, sizeof(cpx<T>), &RP, &lds) != hipSuccess) return 0;
+  return (int)((pairs + RP - 1) / RP);
+}
+
 // q = Op(in) on the quadrature grid
 template <class T>
 hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int epi,
@@ -589,21 +614,25 @@ hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int 
                       double* partials, const CgFuse* cg) {
   hipError_t e;
   const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
+  // (in, q) with q = Op(in): the last-axis pass sums e . (A e) over the real
+  // points (Parseval), so the projection reads no second spectrum for it
+  const bool rowdot = (epi == EPI_STORE && pdot == in && partials != nullptr);
+  double* rpart = rowdot ? partials : nullptr;
   if ((e = stage_expand<T>(c, w, items, in, Q0, sc)) != hipSuccess) return e;
   if (c->dd == 3) {
     if ((e = stage_axis1<T>(c, w, items, +1, Q0, Q1, w.X1, w.X2, sc)) != hipSuccess) return e;
     if ((e = stage_row<T>(c, items, ROW_APPLY, w.X2, w.X2, Q0, Q1, Q2, nullptr, nullptr, nullptr,
-                          sc)) != hipSuccess)
+                          sc, rpart)) != hipSuccess)
       return e;
     if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc)) != hipSuccess) return e;
   } else {
     if ((e = stage_row<T>(c, items, ROW_APPLY, w.X1, w.X1, Q0, 1, Q1, nullptr, nullptr, nullptr,
-                          sc)) != hipSuccess)
+                          sc, rpart)) != hipSuccess)
       return e;
   }
   cpx<T>* rr = (epi == EPI_RESID) ? out : nullptr;
-  return stage_project<T>(c, w, items, w.X1, Q0, epi, out, pdot, rr, nullptr, nullptr, b,
-                          partials, sc, nullptr, cg);
+  return stage_project<T>(c, w, items, w.X1, Q0, epi, out, rowdot ? nullptr : pdot, rr, nullptr,
+                          nullptr, b, rowdot ? nullptr : partials, sc, nullptr, cg);
 }
 
 template <class T>
@@ -720,7 +749,8 @@ template hipError_t pipe_rhs<double>(CellImpl*, Work<double>&, int, const double
 // CG iterations, captured K at a time into a HIP graph
 // ---------------------------------------------------------------------------
 template <class T>
-static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles, bool xupd) {
+static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles, bool xupd,
+                                   bool pq_sc = false) {
   CgUpdateArgs<T> u{};
   u.xupd = xupd ? 1 : 0;
   u.x = w.x;
@@ -736,6 +766,7 @@ static CgUpdateArgs<T> update_args(CellImpl* c, Work<T>& w, int tiles, bool xupd
   u.sc = w.sc;
   u.pq_part = w.part;
   u.pq_n = tiles;
+  u.pq_sc = pq_sc ? 1 : 0;
   return u;
 }
 
@@ -759,22 +790,26 @@ template <class T>
 static hipError_t cg_body(CellImpl* c, Work<T>& w, int items, int K, bool finalize = true) {
   // one iteration: direction step (beta and stopping test from the last
   // update's (r, r) partials, x += alpha p left by that update, p <- r + beta
-  // p), the operator's passes on p, projection (q, (p, q) partials,
-  // bookkeeping of the last update), update (alpha from the (p, q) partials,
+  // p), the operator's passes on p (the last-axis pass leaves the (p, q)
+  // partials), projection (q, bookkeeping of the last update), update (alpha
+  // from the (p, q) partials,
   // r, (r, r) partials; x only in the last iteration, which leaves x current
   // at the end of the graph); after K iterations the last update is booked so
   // the host reads current scalars
   hipError_t e = hipSuccess;
   const int P = partial_slots(c);
-  const int tiles = project_tiles<T>(c);
+  // the (p, q) partials come from the last-axis pass; the projection's first
+  // workgroup sums them for the update
+  const int rtiles = row_tiles<T>(c);
   const int ub = update_blocks(c->S);
   for (int k = 0; k < K && e == hipSuccess; ++k) {
-    const CgFuse cg{w.part2, ub, k > 0 ? 1 : 0};
+    const CgFuse cg{w.part2, ub, k > 0 ? 1 : 0, w.part, rtiles};
     e = launch_cg_direction<T>(direction_args<T>(c, w, ub, k > 0), items, ub, c->stream);
     if (e == hipSuccess)
       e = pipe_apply<T>(c, w, items, w.p, EPI_STORE, w.q, w.p, nullptr, w.sc, w.part, &cg);
     if (e == hipSuccess)
-      e = launch_cg_update<T>(update_args<T>(c, w, tiles, k == K - 1), items, ub, c->stream);
+      e = launch_cg_update<T>(update_args<T>(c, w, rtiles, k == K - 1, true), items, ub,
+                              c->stream);
   }
   if (e == hipSuccess && finalize) e = launch_cg_finalize(w.sc, w.part2, P, ub, items, c->stream);
   return e;
@@ -1780,7 +1815,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   }
   const int P = partial_slots(c);
   const int Q0 = c->Q[0], Q1 = c->Q[1], Q2 = c->Q[2];
-  const int tiles = project_tiles<T>(c);
+  const int tiles = project_tiles<T>(c), rtiles = row_tiles<T>(c);
   const int ub = update_blocks(c->S);
   auto reset = [&]() -> hipError_t {
     hipError_t e2 = launch_set_scal(w.sc, L, 0.0, 1 << 30, 1, c->stream);
@@ -1811,7 +1846,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   for (int it = 0; it < reps && e == hipSuccess; ++it) {
     // as inside a launched graph: x is left to the next expansion except in
     // the last iteration
-    const CgFuse cg{w.part2, ub, it > 0 ? 1 : 0};
+    const CgFuse cg{w.part2, ub, it > 0 ? 1 : 0, w.part, rtiles};
     hipEvent_t* E = ev.data() + (size_t)it * NK * 2;
     int* Ln = launched.data() + (size_t)it * NK;
     // the first-axis stages of a cell with several potentials are two kernels
@@ -1832,7 +1867,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     if (e == hipSuccess) {
       arm(2);
       e = stage_row<T>(c, L, ROW_APPLY, Xrow, Xrow, Q0, c->dd == 3 ? Q1 : 1, c->dd == 3 ? Q2 : Q1,
-                       nullptr, nullptr, nullptr, w.sc);
+                       nullptr, nullptr, nullptr, w.sc, w.part);
     }
     if (e == hipSuccess && c->dd == 3) {
       arm(3);
@@ -1840,12 +1875,13 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     }
     if (e == hipSuccess) {
       arm(4);
-      e = stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, w.p, nullptr, nullptr, nullptr,
-                           nullptr, w.part, w.sc, nullptr, &cg);
+      e = stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, w.sc, nullptr, &cg);
     }
     if (e == hipSuccess) {
       arm(5);
-      e = launch_cg_update<T>(update_args<T>(c, w, tiles, it == reps - 1), L, ub, c->stream);
+      e = launch_cg_update<T>(update_args<T>(c, w, rtiles, it == reps - 1, true), L, ub,
+                              c->stream);
     }
     if (e == hipSuccess && it == reps - 1) {
       arm(6);
@@ -1881,7 +1917,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     bytes[3] = bytes[1];
   }
   bytes[2] = L * 2.0 * c->nf * rows * c->H * esz + (double)c->nA * c->nQ * Ts;
-  bytes[4] = L * (nx * Q0 * inner * esz + 2.0 * S * esz);
+  bytes[4] = L * (nx * Q0 * inner * esz + S * esz);
   bytes[5] = L * 3.0 * S * esz;
   for (int i = 0; i < 6; ++i) bytes[7] += bytes[i];
   bytes[7] += bytes[8];
