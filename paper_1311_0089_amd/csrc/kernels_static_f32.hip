@@ -130,6 +130,7 @@ RegColReg2<T, P63, 63, 16, 128> g63;
 // butterfly per thread in both stages, ran slower)
 RegColR2<T, P255, 255, 16, 256> e255;
 RegColR2<T, P253, 127, 16, 256> e253;
+RegColR2<T, P63, 63, 16, 128> e63;
 RegMid2<T, P255, 255, 16, 256> m255;
 RegMid2<T, P253, 127, 16, 256> m253;
 RegMid2<T, P63, 63, 16, 128> m63;
