@@ -893,6 +893,109 @@ __global__ __launch_bounds__(NT) void k_col_project_r2(ColProjectArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// 3-D elasticity, first-axis expansion with the basis map fused in (register
+// pipeline): the three displacement potentials of a tile column are loaded
+// once into registers, and each of the six Mandel components
+//   b_p[aa] = sqrt 2 n_a [a = p] + (1 - sqrt 2) n_p n_a^2,
+//   b_p[ab] = n_a [b = p] + n_b [a = p] + (sqrt 2 - 2) n_p n_a n_b
+// (see elastic_comp) is formed from them at the first-stage operand rows and
+// transformed in turn: the potentials are read once and the components
+// written once, where the basis map plus plain transform wrote and read the
+// components in between
+// ---------------------------------------------------------------------------
+template <class T, class SP, int NTRIAL, int W, int NT>
+__global__ __launch_bounds__(NT) void k_col_bexpand_r2(ColExpandArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int R1 = TwoRadices<typename SP::radices>::r1, R2 = TwoRadices<typename SP::radices>::r2;
+  constexpr int n = SP::n;
+  static_assert(R1 * R2 == n && !SP::blue, "two-stage Stockham plan");
+  static_assert(NT % W == 0, "a thread keeps one tile column");
+  constexpr int hk = (NTRIAL - 1) / 2;
+  const int item = blockIdx.y;
+  if (a.sc && !item_live(a.sc[item])) return;
+  const int col0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+  const int ncols = min(W, a.inner - col0);
+  const int w = (int)threadIdx.x % W;
+  const int wl = min(w, ncols - 1);
+  const cpx<T>* c = a.c + (long)item * a.c_stride + col0 + wl;
+  cpx<T>* X = a.X + (long)item * a.X_stride + col0 + w;
+  const ColXi<T> cx = col_xi<T>(a.g, col0 + wl);
+  const T y0 = T(a.g.invY[0]);
+  constexpr int T1 = R2 * W, M1 = (T1 + NT - 1) / NT;
+  constexpr int T2 = R1 * W, M2 = (T2 + NT - 1) / NT;
+  static_assert(M1 == 1, "one first-stage butterfly per thread");
+  const int j = min((int)threadIdx.x, T1 - 1) / W;
+  cpx<T> pv[3][R1];
+#pragma unroll
+  for (int r = 0; r < R1; ++r) {
+    const int k = kof(j + r * R2, n);
+    const bool trial = (k >= -hk && k <= hk);
+    const long row = (long)(trial ? posk(k, NTRIAL) : 0) * a.si;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const cpx<T> x = c[p * a.g.pot_stride + row];
+      pv[p][r] = trial ? x : cpx<T>{T(0), T(0)};
+    }
+  }
+  const T sq2 = T(1.4142135623730951);
+#pragma unroll 1
+  for (int comp = 0; comp < 6; ++comp) {
+    // Mandel pair (a, b) of the component: 11, 22, 33, 23, 13, 12
+    const int ca = (comp < 3) ? comp : (comp == 3) ? 1 : 0;
+    const int cb = (comp < 3) ? comp : (comp == 5) ? 1 : 2;
+    if ((int)threadIdx.x < T1) {
+      cpx<T> u[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int k = kof(j + r * R2, n);
+        const T iv = inv_xi<T>(a.g, k, cx);
+        const T nv[3] = {T(k) * y0 * iv, cx.x1 * iv, cx.x2 * iv};
+        // n . u over the potentials
+        const cpx<T> s = {nv[0] * pv[0][r].x + nv[1] * pv[1][r].x + nv[2] * pv[2][r].x,
+                          nv[0] * pv[0][r].y + nv[1] * pv[1][r].y + nv[2] * pv[2][r].y};
+        // selects, not indexing: the arrays stay in registers
+        const T na = (ca == 0) ? nv[0] : (ca == 1) ? nv[1] : nv[2];
+        const T nb = (cb == 0) ? nv[0] : (cb == 1) ? nv[1] : nv[2];
+        const cpx<T> ua = (ca == 0) ? pv[0][r] : (ca == 1) ? pv[1][r] : pv[2][r];
+        const cpx<T> ub = (cb == 0) ? pv[0][r] : (cb == 1) ? pv[1][r] : pv[2][r];
+        if (ca == cb) {
+          const T f = (T(1) - sq2) * na * na;
+          u[r] = {sq2 * na * ua.x + f * s.x, sq2 * na * ua.y + f * s.y};
+        } else {
+          const T f = (sq2 - T(2)) * na * nb;
+          u[r] = {na * ub.x + nb * ua.x + f * s.x, na * ub.y + nb * ua.y + f * s.y};
+        }
+      }
+      Dft<T, R1, +1>::run(u);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) lds[(j * R1 + r) * W + w] = u[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < M2; ++it) {
+      const int f = (int)threadIdx.x + it * NT;
+      if (f >= T2) continue;
+      const int k = f / W;
+      cpx<T> u[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) u[r] = lds[(k + r * R1) * W + w];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) {
+        cpx<T> t = a.tw[k * (R2 - 1) + r - 1];
+        t.y = -t.y;
+        u[r] = cmul(u[r], t);
+      }
+      Dft<T, R2, +1>::run(u);
+      if (w >= ncols) continue;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) X[comp * a.X_cstride + (long)(k + r * R1) * a.inner] = u[r];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // middle-axis (3-D axis 1) passes between PAIR first-axis passes, register
 // pipeline as in k_col_reg2.  Inverse: part 0 transforms X_0; part 1 reads Z
 // once and gives X_1 = F^-1[xi_1 Z] and X_2 = xi_2 F^-1[Z] (xi_1 varies along

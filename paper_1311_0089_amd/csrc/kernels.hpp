@@ -224,7 +224,9 @@ struct CgDirArgs {
 enum { KK_EXPAND = 0, KK_PROJECT = 1, KK_PLAIN_INV = 2, KK_PLAIN_FWD = 3, KK_ROW = 4,
        KK_ROW_CONST = 5, KK_ROW_SYNTH = 6,
        // 3-D cells with two spectra between the first- and middle-axis passes
-       KK_EXPAND2 = 7, KK_PROJECT2 = 8, KK_MID2_INV = 9, KK_MID2_FWD = 10 };
+       KK_EXPAND2 = 7, KK_PROJECT2 = 8, KK_MID2_INV = 9, KK_MID2_FWD = 10,
+       // 3-D elasticity: first-axis expansion with the basis map fused in
+       KK_BEXPAND = 11 };
 struct StaticKernel {
   int kind, esz, n, ntrial, d;  // d: component count (row kernels), else 0
   const void* fn;

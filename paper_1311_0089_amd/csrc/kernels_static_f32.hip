@@ -131,6 +131,7 @@ RegColReg2<T, P63, 63, 16, 128> g63;
 RegColR2<T, P255, 255, 16, 256> e255;
 RegColR2<T, P253, 127, 16, 256> e253;
 RegColR2<T, P63, 63, 16, 128> e63;
+RegBExpand<T, P255, 255, 16, 256> b255;
 RegMid2<T, P255, 255, 16, 256> m255;
 RegMid2<T, P253, 127, 16, 256> m253;
 RegMid2<T, P63, 63, 16, 128> m63;

@@ -260,6 +260,15 @@ static const StaticKernel* col_static(const CellImpl* c, int kind, int esz, int 
 
 static long inner0(const CellImpl* c) { return (c->dd == 3) ? (long)c->N[1] * c->H : c->H; }
 
+// the fused expansion kernel of a 3-D elastic cell's first axis, if any
+template <class T>
+static const StaticKernel* bexpand_kernel(const CellImpl* c) {
+  if (!c->elastic || c->dd != 3) return nullptr;
+  const DevPlan* p0;
+  if (get_dev_plan(c->Q[0], &p0) != hipSuccess) return nullptr;
+  return find_static(KK_BEXPAND, (int)sizeof(cpx<T>), c->Q[0], c->N[0], c->nf, p0->p);
+}
+
 // 3-D cells of one potential whose FP32 first- and middle-axis passes hand two
 // spectra to each other instead of three (X_0 and Z = F_0^-1[c / |xi|] on the
 // way in, X_0 and xi_1 X_1 + xi_2 X_2 on the way out; the middle-axis passes
@@ -355,6 +364,12 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
   a.tw = tw_of<T>(p0);
   a.sc = sc;
   if (c->npot > 1) {
+    // 3-D elasticity with a fused kernel for the length: the six components
+    // straight from the three potentials
+    if (const StaticKernel* sk = bexpand_kernel<T>(c)) {
+      a.W = sk->W;
+      return launch_col_expand<T>(a, items, sk->lds, c->stream, sk);
+    }
     // several potentials: basis map on the trial rows (into X2), then the
     // plain inverse pass with padding into X1
     BasisArgs<T> b{};
@@ -1851,7 +1866,8 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     int* Ln = launched.data() + (size_t)it * NK;
     // the first-axis stages of a cell with several potentials are two kernels
     auto arm = [&](int k) {
-      arm_launch_events(E[2 * k], E[2 * k + 1], (c->npot > 1 && (k == 0 || k == 4)) ? 2 : 1);
+      const bool two = c->npot > 1 && ((k == 0 && !bexpand_kernel<T>(c)) || k == 4);
+      arm_launch_events(E[2 * k], E[2 * k + 1], two ? 2 : 1);
       Ln[k] = 1;
     };
     arm(7);

@@ -192,6 +192,17 @@ struct RegMid2 {
   }
 };
 
+// 3-D elasticity: expansion of the six Mandel components from the three
+// displacement potentials in one register-pipeline pass
+template <class T, class SP, int NTRIAL, int W, int NT>
+struct RegBExpand {
+  static constexpr size_t lds = (size_t)SP::n * W * sizeof(cpx<T>);
+  RegBExpand() {
+    RegColReg2<T, SP, NTRIAL, W, NT>::add_kind(
+        KK_BEXPAND, 6, lds, (const void*)&k_col_bexpand_r2<T, SP, NTRIAL, W, NT>);
+  }
+};
+
 // plans
 using P1023 = SPlan<1023, 1023, 0, Rad<31, 11, 3>>;
 using P255 = SPlan<255, 255, 0, Rad<17, 15>>;
