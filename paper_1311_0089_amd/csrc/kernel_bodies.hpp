@@ -1557,4 +1557,153 @@ __global__ __launch_bounds__(P::NT) void k_row(RowArgs<T> a) {
       });
 }
 
+// ---------------------------------------------------------------------------
+// last axis, flux pass (ROW_APPLY) with IT items (load cases) per workgroup:
+// the d RP lines of every item of a row tile in one LDS tile, so that the
+// coefficient rows of the tile are read once for all of them (items of
+// another coefficient block, as in the server, read their own)
+// ---------------------------------------------------------------------------
+template <class SP, int NTRIAL, int D_, int RP_, int NT_, int IT_>
+struct RowMulti {
+  static constexpr int NT = NT_, IT = IT_, D = D_, RP = RP_, n = SP::n, H = (NTRIAL + 1) / 2;
+  static constexpr int LINES = IT_ * D_ * RP_, LS = SP::len;
+  template <class T, int S>
+  __device__ __forceinline__ static void fft(cpx<T>* lds, const FftPlan& P, const cpx<T>* tw) {
+    sfft<T, S, SP, LINES, false, SP::len, 1, NT_, false>(lds, tw, P);
+  }
+};
+
+template <class T, class P>
+__global__ __launch_bounds__(P::NT) void k_row_multi(RowArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  constexpr int NT = P::NT, IT = P::IT, D = P::D, RP = P::RP, n = P::n, H = P::H;
+  constexpr int ls = P::LS;
+  constexpr int CHR = rounds_ch(P::LINES * H, NT);
+  constexpr int CHF = rounds_ch(RP * n, NT) > 4 ? 4 : rounds_ch(RP * n, NT);
+  const int item0 = (int)blockIdx.y * IT;
+  const int nit = min(IT, a.items - item0);
+  // items still iterating, one bit each
+  unsigned lm = 0;
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+    if (it < nit && (!a.sc || item_live(a.sc[item0 + it]))) lm |= 1u << it;
+  if (!lm) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int pair0 = tile * RP;
+  // Z(h) = X_a(h) + i X_b(h), Z(n-h) = conj X_a(h) + i conj X_b(h); line
+  // (it, comp, lp) at ((it D + comp) RP + lp)
+  if (n > 2 * H - 1) {
+    constexpr int gap = n - (2 * H - 1);
+    for (int f = threadIdx.x; f < P::LINES * gap; f += NT) {
+      const int line = f / gap, x = H + f % gap;
+      lds[line * ls + x] = cpx<T>{T(0), T(0)};
+    }
+  }
+  in_rounds<NT, CHR>(
+      P::LINES * H,
+      [=](int f) __attribute__((always_inline)) {
+        const int line = f / H, h = f % H;
+        const int it = min(line / (D * RP), nit - 1), comp = (line / RP) % D, lp = line % RP;
+        const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+        const cpx<T>* src = a.in + (long)(item0 + it) * a.in_stride + (long)comp * a.in_cstride;
+        return cpx2<T>{src[(long)min(r0, a.rows - 1) * H + h], src[(long)min(r1, a.rows - 1) * H + h]};
+      },
+      [=](int f, cpx2<T> v) __attribute__((always_inline)) {
+        const int line = f / H, h = f % H;
+        const int lp = line % RP;
+        const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+        if (r0 >= a.rows || line / (D * RP) >= nit) v.a = v.b = cpx<T>{T(0), T(0)};
+        if (r1 >= a.rows) v.b = cpx<T>{T(0), T(0)};
+        if (h == 0) {
+          // the h = 0 bin of a real line is real
+          v.a.y = T(0);
+          v.b.y = T(0);
+        }
+        lds[line * ls + h] = cpx<T>{v.a.x - v.b.y, v.a.y + v.b.x};
+        if (h > 0) lds[line * ls + n - h] = cpx<T>{v.a.x + v.b.y, v.b.x - v.a.y};
+      });
+  __syncthreads();
+  P::template fft<T, +1>(lds, a.plan, a.tw);
+  // flux: the coefficient rows of a point once, applied to every item; (p, q)
+  // partials per item as in k_row
+  const long blk0 = (long)(item0 / a.A_group);
+  const T* A0 = a.A + blk0 * a.A_stride;
+  double part[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) part[it] = 0.0;
+  in_rounds<NT, CHF>(
+      RP * n,
+      [=](int f) __attribute__((always_inline)) {
+        const int lp = f / n, x = f % n;
+        const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+        Coef2<T> v;
+        load_coef<T>(a.kind, D, A0, a.A_cstride, (long)min(r0, a.rows - 1) * n + x, v.c0);
+        load_coef<T>(a.kind, D, A0, a.A_cstride, (long)min(r1, a.rows - 1) * n + x, v.c1);
+        return v;
+      },
+      [=, &part](int f, const Coef2<T>& v) __attribute__((always_inline)) {
+        const int lp = f / n, x = f % n;
+        const int r0 = 2 * (pair0 + lp);
+        if (r0 >= a.rows) return;
+        const bool two = r0 + 1 < a.rows;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          if (it >= nit) break;
+          Coef2<T> cv = v;
+          const long blk = (long)((item0 + it) / a.A_group);
+          if (blk != blk0) {
+            // another coefficient block (items of several cells)
+            const T* Ai = a.A + blk * a.A_stride;
+            load_coef<T>(a.kind, D, Ai, a.A_cstride, (long)r0 * n + x, cv.c0);
+            load_coef<T>(a.kind, D, Ai, a.A_cstride, (long)min(r0 + 1, a.rows - 1) * n + x, cv.c1);
+          }
+          T e0[D], e1[D], j0[D], j1[D];
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const cpx<T> z = lds[((it * D + q) * RP + lp) * ls + x];
+            e0[q] = z.x;
+            e1[q] = z.y;
+          }
+          flux_coef<T>(a.kind, D, cv.c0, e0, j0);
+          flux_coef<T>(a.kind, D, cv.c1, e1, j1);
+          T t = T(0);
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            lds[((it * D + q) * RP + lp) * ls + x] = cpx<T>{j0[q], j1[q]};
+            t += e0[q] * j0[q] + (two ? e1[q] * j1[q] : T(0));
+          }
+          part[it] += (double)t;
+        }
+      });
+  __syncthreads();
+  if (a.partials) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const double s = block_sum<NT>(part[it]);
+      if (threadIdx.x == 0 && ((lm >> it) & 1u)) a.partials[(long)(item0 + it) * a.P + tile] = s * a.pscale;
+    }
+  }
+  P::template fft<T, -1>(lds, a.plan, a.tw);
+  const T half = T(0.5) / T(n);
+  in_rounds<NT, CHR>(
+      P::LINES * H,
+      [=](int f) __attribute__((always_inline)) {
+        const int line = f / H, h = f % H;
+        return cpx2<T>{lds[line * ls + h], lds[line * ls + (h == 0 ? 0 : n - h)]};
+      },
+      [=](int f, const cpx2<T>& z) __attribute__((always_inline)) {
+        const int line = f / H, h = f % H;
+        const int it = line / (D * RP), comp = (line / RP) % D, lp = line % RP;
+        const int r0 = 2 * (pair0 + lp), r1 = r0 + 1;
+        if (r0 >= a.rows || !((lm >> it) & 1u)) return;
+        const cpx<T> zh = z.a, zm = z.b;
+        const cpx<T> va = {(zh.x + zm.x) * half, (zh.y - zm.y) * half};
+        const cpx<T> vb = {(zh.y + zm.y) * half, (zm.x - zh.x) * half};
+        cpx<T>* dst = a.out + (long)(item0 + it) * a.out_stride + (long)comp * a.out_cstride;
+        dst[(long)r0 * H + h] = va;
+        if (r1 < a.rows) dst[(long)r1 * H + h] = vb;
+      });
+}
+
 }  // namespace hom

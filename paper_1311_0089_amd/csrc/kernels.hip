@@ -864,6 +864,7 @@ hipError_t launch_row(const RowArgs<T>& a0, int items, int mode, size_t lds, hip
                    : (mode == ROW_SYNTH) ? KK_ROW_SYNTH : -1;
     if (sk->kind != kind) return hipErrorInvalidValue;
     if (sk->ilv) grid = dim3(ceil_div(pairs, a.RP) * items, 1);
+    if (sk->ipw > 1) grid = dim3(ceil_div(pairs, a.RP), ceil_div(items, sk->ipw));
     auto fn = reinterpret_cast<void (*)(RowArgs<T>)>(const_cast<void*>(sk->fn));
     launch_k(fn, grid, dim3(sk->NT), sk->lds, s, a);
     return hipGetLastError();

@@ -235,6 +235,7 @@ struct StaticKernel {
   size_t lds;                   // dynamic LDS bytes
   int len, blue, nst, rad[kMaxStages];  // the compile-time FFT plan
   int ilv;                      // row kernels: items interleaved on a 1-D grid
+  int ipw;                      // row kernels: items per workgroup (0: one)
 };
 std::vector<StaticKernel>& static_registry();
 void register_static(const StaticKernel& k);

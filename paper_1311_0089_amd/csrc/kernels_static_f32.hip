@@ -132,6 +132,10 @@ RegColR2<T, P255, 255, 16, 256> e255;
 RegColR2<T, P253, 127, 16, 256> e253;
 RegColR2<T, P63, 63, 16, 128> e63;
 RegBExpand<T, P255, 255, 16, 256> b255;
+// last-axis flux pass with the three load cases of a row tile together
+// (coefficient rows read once): 412 -> 366 us on the 253-point Ga axis; on the
+// 255-point GaNi axis (twice the bytes per line) 428-517 against 364 us
+RegRowMulti<T, P253, 127, 3, 2, 256, 3> q253_3;
 RegMid2<T, P255, 255, 16, 256> m255;
 RegMid2<T, P253, 127, 16, 256> m253;
 RegMid2<T, P63, 63, 16, 128> m63;

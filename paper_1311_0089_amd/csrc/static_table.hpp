@@ -203,6 +203,30 @@ struct RegBExpand {
   }
 };
 
+// last-axis flux pass with IT load cases per workgroup (k_row_multi)
+template <class T, class SP, int NTRIAL, int D, int RP, int NT, int IT>
+struct RegRowMulti {
+  static constexpr size_t lds = (size_t)IT * D * RP * SP::len * sizeof(cpx<T>);
+  static_assert(lds <= 66 * 1024 + 512, "row tile exceeds the LDS budget");
+  RegRowMulti() {
+    StaticKernel k{};
+    k.kind = KK_ROW;
+    k.esz = (int)sizeof(cpx<T>);
+    k.n = SP::n;
+    k.ntrial = NTRIAL;
+    k.d = D;
+    k.fn = (const void*)&k_row_multi<T, RowMulti<SP, NTRIAL, D, RP, NT, IT>>;
+    k.W = RP;
+    k.NT = NT;
+    k.lds = lds;
+    k.len = SP::len;
+    k.blue = SP::blue;
+    k.ipw = IT;
+    RegCol<T, SP, NTRIAL, 1, 256>::fill(k, typename SP::radices{});
+    register_static(k);
+  }
+};
+
 // plans
 using P1023 = SPlan<1023, 1023, 0, Rad<31, 11, 3>>;
 using P255 = SPlan<255, 255, 0, Rad<17, 15>>;
