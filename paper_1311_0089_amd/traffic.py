@@ -25,11 +25,12 @@ KERNEL_SOURCES = ["fft_device.hpp", "fft_static.hpp", "kernel_bodies.hpp", "kern
                   "kernels_static_f64.hip"]
 RECORD_TAG = "traffic-record:"
 
-# slot -> (kernel name prefixes, suffix or None) of the FP32 CG iteration
+# slot -> (kernel name prefixes, suffix or None) of the FP32 CG iteration;
+# a slot may list several such pairs
 SLOTS = {
     "expand0": (("hom::k_col_expand<float", "hom::k_col_expand_r2<float"), None),
     "inv1": (("hom::k_col_plain<float", "hom::k_col_reg2<float", "hom::k_col_mid2<float"), ", 1>"),
-    "row": (("hom::k_row<float",), ", 0>"),
+    "row": [(("hom::k_row<float",), ", 0>"), (("hom::k_row_multi<float",), None)],
     "fwd1": (("hom::k_col_plain<float", "hom::k_col_reg2<float", "hom::k_col_mid2<float"), ", -1>"),
     "project0": (("hom::k_col_project<float", "hom::k_col_project_r2<float"), None),
     "update": (("hom::k_cg_update<float>",), None),
@@ -48,9 +49,10 @@ def fingerprint() -> str:
 def _slot_of(name: str):
     head = name[5:] if name.startswith("void ") else name
     head = head.split("(")[0].rstrip()
-    for slot, (prefixes, suffix) in SLOTS.items():
-        if head.startswith(prefixes) and (suffix is None or head.endswith(suffix)):
-            return slot
+    for slot, rule in SLOTS.items():
+        for prefixes, suffix in (rule if isinstance(rule, list) else [rule]):
+            if head.startswith(prefixes) and (suffix is None or head.endswith(suffix)):
+                return slot
     return None
 
 
