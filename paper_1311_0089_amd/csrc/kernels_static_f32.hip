@@ -132,6 +132,13 @@ RegColR2<T, P255, 255, 16, 256> e255;
 RegColR2<T, P253, 127, 16, 256> e253;
 RegColR2<T, P63, 63, 16, 128> e63;
 RegBExpand<T, P255, 255, 16, 256> b255;
+// 32-column tiles (256-byte row segments), 512 threads: 255-point expansion
+// 164 -> 132 us, projection 182 -> 177 us, middle forward 230 -> 225 us (the
+// middle inverse ran slower, 204 -> 238 us; the tuner picks per pass)
+RegColR2<T, P255, 255, 32, 512> e255w;
+RegMid2<T, P255, 255, 32, 512> m255w;
+RegColR2<T, P253, 127, 32, 512> e253w;
+RegMid2<T, P253, 127, 32, 512> m253w;
 // last-axis flux pass with the three load cases of a row tile together
 // (coefficient rows read once): 412 -> 366 us on the 253-point Ga axis; on the
 // 255-point GaNi axis (twice the bytes per line) 428-517 against 364 us
