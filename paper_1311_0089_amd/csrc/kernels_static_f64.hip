@@ -63,5 +63,8 @@ RegRow<T, P509, 255, 3, 1, 256> r509_3;
 RegColReg2<T, P255, 255, 8, 256> g255;
 RegColReg2<T, P253, 127, 8, 256> g253;
 RegColReg2<T, P63, 63, 8, 128> g63;
+// two spectra between the first- and middle-axis passes (3-D)
+RegColR2<T, P255, 255, 8, 128> e255;
+RegMid2<T, P255, 255, 8, 128> m255;
 }  // namespace
 }  // namespace hom

@@ -276,7 +276,7 @@ static const StaticKernel* bexpand_kernel(const CellImpl* c) {
 // the shape.  Every pass decides it the same way, so they agree.
 template <class T>
 static bool pair_mode(const CellImpl* c) {
-  if (!std::is_same<T, float>::value || c->dd != 3 || c->npot != 1) return false;
+  if (c->dd != 3 || c->npot != 1) return false;
   const DevPlan *p0, *p1;
   if (get_dev_plan(c->Q[0], &p0) != hipSuccess || get_dev_plan(c->Q[1], &p1) != hipSuccess)
     return false;
