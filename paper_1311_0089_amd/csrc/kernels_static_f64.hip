@@ -66,5 +66,9 @@ RegColReg2<T, P63, 63, 8, 128> g63;
 // two spectra between the first- and middle-axis passes (3-D)
 RegColR2<T, P255, 255, 8, 128> e255;
 RegMid2<T, P255, 255, 8, 128> m255;
+RegColR2<T, P253, 127, 8, 128> e253;
+RegMid2<T, P253, 127, 8, 128> m253;
+RegColR2<T, P63, 63, 8, 128> e63;
+RegMid2<T, P63, 63, 8, 128> m63;
 }  // namespace
 }  // namespace hom

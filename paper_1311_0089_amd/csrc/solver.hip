@@ -287,6 +287,14 @@ static bool pair_mode(const CellImpl* c) {
          find_static(KK_MID2_FWD, esz, c->Q[1], c->N[1], 0, p1->p);
 }
 
+// the two-spectra form for passes over a G0 x G1 grid: the cell's form on the
+// quadrature grid only (the trial-grid synthesis of a Ga cell runs the
+// three-spectra kernels of its lengths)
+template <class T>
+static bool pair_on(const CellImpl* c, int G0, int G1) {
+  return G0 == c->Q[0] && G1 == c->Q[1] && pair_mode<T>(c);
+}
+
 // Layout of the scalar spectra (c, r, p, q, b, x) of an item: 2-D cells keep
 // them column-major (axis 0 contiguous), so the first-axis passes, whose
 // tiles are few columns wide there, load and store whole cache lines; 3-D
@@ -344,7 +352,7 @@ static hipError_t plain_axis0(CellImpl* c, int items, int sign, int G0, const cp
 
 template <class T>
 static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int G0,
-                               ItemScal* sc) {
+                               ItemScal* sc, bool pair) {
   const DevPlan* p0;
   hipError_t e = get_dev_plan(G0, &p0);
   if (e != hipSuccess) return e;
@@ -389,8 +397,8 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
     if ((e = launch_basis_expand<T>(b, items, blocks, c->stream)) != hipSuccess) return e;
     return plain_axis0<T>(c, items, +1, G0, w.X2, w.X1, sc);
   }
-  const StaticKernel* sk = col_static(c, pair_mode<T>(c) ? KK_EXPAND2 : KK_EXPAND, sizeof(cpx<T>),
-                                      G0, p0->p);
+  const StaticKernel* sk = col_static(c, pair ? KK_EXPAND2 : KK_EXPAND, sizeof(cpx<T>), G0, p0->p);
+  if (pair && !sk) return hipErrorInvalidValue;
   if (sk) {
     a.W = sk->W;
     return launch_col_expand<T>(a, items, sk->lds, c->stream, sk);
@@ -404,7 +412,7 @@ static hipError_t stage_expand(CellImpl* c, Work<T>& w, int items, const cpx<T>*
 // axis-1 pass (3-D): inverse with padding N1 -> G1, or forward with truncation G1 -> N1
 template <class T>
 static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int G0, int G1,
-                              const cpx<T>* in, cpx<T>* out, ItemScal* sc) {
+                              const cpx<T>* in, cpx<T>* out, ItemScal* sc, bool pair) {
   const DevPlan* p1;
   hipError_t e = get_dev_plan(G1, &p1);
   if (e != hipSuccess) return e;
@@ -424,7 +432,7 @@ static hipError_t stage_axis1(CellImpl* c, Work<T>& w, int items, int sign, int 
   a.plan = p1->p;
   a.tw = tw_of<T>(p1);
   a.sc = sc;
-  if (pair_mode<T>(c)) {
+  if (pair) {
     // two parts per item: X_0, and the xi_1 / xi_2 pair (k_col_mid2)
     const StaticKernel* sk = find_static(sign > 0 ? KK_MID2_INV : KK_MID2_FWD, sizeof(cpx<T>),
                                          G1, c->N[1], 0, p1->p);
@@ -509,7 +517,7 @@ template <class T>
 static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>* X, int G0,
                                 int epi, cpx<T>* out, const cpx<T>* pdot, cpx<T>* r, cpx<T>* pp,
                                 cpx<T>* x, const cpx<T>* b, double* partials, ItemScal* sc,
-                                int* tiles, const CgFuse* cg = nullptr) {
+                                int* tiles, bool pair, const CgFuse* cg = nullptr) {
   const DevPlan* p0;
   hipError_t e = get_dev_plan(G0, &p0);
   if (e != hipSuccess) return e;
@@ -578,8 +586,9 @@ static hipError_t stage_project(CellImpl* c, Work<T>& w, int items, const cpx<T>
     if (tiles) *tiles = blocks;
     return launch_basis_project<T>(ba, items, blocks, c->stream);
   }
-  const StaticKernel* sk = col_static(c, pair_mode<T>(c) ? KK_PROJECT2 : KK_PROJECT,
-                                      sizeof(cpx<T>), G0, p0->p);
+  const StaticKernel* sk = col_static(c, pair ? KK_PROJECT2 : KK_PROJECT, sizeof(cpx<T>), G0,
+                                      p0->p);
+  if (pair && !sk) return hipErrorInvalidValue;
   if (sk) {
     a.W = sk->W;
     if (tiles) *tiles = (a.inner + sk->W - 1) / sk->W;
@@ -633,13 +642,16 @@ hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int 
   // points (Parseval), so the projection reads no second spectrum for it
   const bool rowdot = (epi == EPI_STORE && pdot == in && partials != nullptr);
   double* rpart = rowdot ? partials : nullptr;
-  if ((e = stage_expand<T>(c, w, items, in, Q0, sc)) != hipSuccess) return e;
+  const bool pair = pair_mode<T>(c);
+  if ((e = stage_expand<T>(c, w, items, in, Q0, sc, pair)) != hipSuccess) return e;
   if (c->dd == 3) {
-    if ((e = stage_axis1<T>(c, w, items, +1, Q0, Q1, w.X1, w.X2, sc)) != hipSuccess) return e;
+    if ((e = stage_axis1<T>(c, w, items, +1, Q0, Q1, w.X1, w.X2, sc, pair)) != hipSuccess)
+      return e;
     if ((e = stage_row<T>(c, items, ROW_APPLY, w.X2, w.X2, Q0, Q1, Q2, nullptr, nullptr, nullptr,
                           sc, rpart)) != hipSuccess)
       return e;
-    if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc)) != hipSuccess) return e;
+    if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc, pair)) != hipSuccess)
+      return e;
   } else {
     if ((e = stage_row<T>(c, items, ROW_APPLY, w.X1, w.X1, Q0, 1, Q1, nullptr, nullptr, nullptr,
                           sc, rpart)) != hipSuccess)
@@ -647,7 +659,7 @@ hipError_t pipe_apply(CellImpl* c, Work<T>& w, int items, const cpx<T>* in, int 
   }
   cpx<T>* rr = (epi == EPI_RESID) ? out : nullptr;
   return stage_project<T>(c, w, items, w.X1, Q0, epi, out, rowdot ? nullptr : pdot, rr, nullptr,
-                          nullptr, b, rowdot ? nullptr : partials, sc, nullptr, cg);
+                          nullptr, b, rowdot ? nullptr : partials, sc, nullptr, pair, cg);
 }
 
 template <class T>
@@ -658,14 +670,16 @@ hipError_t pipe_rhs(CellImpl* c, Work<T>& w, int items, const double* dE, ItemSc
     if ((e = stage_row<T>(c, items, ROW_CONST, nullptr, w.X2, Q0, Q1, Q2, nullptr, nullptr, dE,
                           sc)) != hipSuccess)
       return e;
-    if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc)) != hipSuccess) return e;
+    if ((e = stage_axis1<T>(c, w, items, -1, Q0, Q1, w.X2, w.X1, sc, pair_mode<T>(c))) !=
+        hipSuccess)
+      return e;
   } else {
     if ((e = stage_row<T>(c, items, ROW_CONST, nullptr, w.X1, Q0, 1, Q1, nullptr, nullptr, dE,
                           sc)) != hipSuccess)
       return e;
   }
   if ((e = stage_project<T>(c, w, items, w.X1, Q0, EPI_RHS, w.b, nullptr, w.r, w.p, w.x, nullptr,
-                            w.part, sc, nullptr)) != hipSuccess)
+                            w.part, sc, nullptr, pair_mode<T>(c))) != hipSuccess)
     return e;
   // b (and r = p = b) given the exact symmetry of the potential of a real
   // field on the h = 0 plane; (b, b) again, in the first project_tiles
@@ -694,9 +708,11 @@ hipError_t pipe_synth(CellImpl* c, Work<double>& w, int items, const cpx<double>
   const int G0 = onQ ? c->Q[0] : c->N[0];
   const int G1 = onQ ? c->Q[1] : c->N[1];
   const int G2 = onQ ? c->Q[2] : c->N[2];
-  if ((e = stage_expand<double>(c, w, items, cin, G0, nullptr)) != hipSuccess) return e;
+  const bool pair = c->dd == 3 && pair_on<double>(c, G0, G1);
+  if ((e = stage_expand<double>(c, w, items, cin, G0, nullptr, pair)) != hipSuccess) return e;
   if (c->dd == 3) {
-    if ((e = stage_axis1<double>(c, w, items, +1, G0, G1, w.X1, w.X2, nullptr)) != hipSuccess)
+    if ((e = stage_axis1<double>(c, w, items, +1, G0, G1, w.X1, w.X2, nullptr, pair)) !=
+        hipSuccess)
       return e;
     return stage_row<double>(c, items, ROW_SYNTH, w.X2, nullptr, G0, G1, G2, nullptr, out, dE,
                              nullptr);
@@ -745,8 +761,9 @@ hipError_t pipe_project_real(CellImpl* c, Work<double>& w, int items, const doub
                                nullptr)) != hipSuccess)
       return e;
   }
+  // the axis-1 forward above leaves three spectra
   return stage_project<double>(c, w, items, X, N0, EPI_STORE, cout, nullptr, nullptr, nullptr,
-                               nullptr, nullptr, nullptr, nullptr, nullptr);
+                               nullptr, nullptr, nullptr, nullptr, nullptr, false);
 }
 
 template hipError_t pipe_apply<float>(CellImpl*, Work<float>&, int, const cpx<float>*, int,
@@ -1817,6 +1834,7 @@ namespace hom {
 
 template <class T>
 static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double* bytes) {
+  const bool pair = pair_mode<T>(c);
   Work<T>& w = work_of<T>(c);
   hipError_t e;
   std::vector<double> hE((size_t)L * c->nf, 0.0);
@@ -1874,11 +1892,11 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     e = launch_cg_direction<T>(direction_args<T>(c, w, ub, it > 0), L, ub, c->stream);
     if (e == hipSuccess) {
       arm(0);
-      e = stage_expand<T>(c, w, L, w.p, Q0, w.sc);
+      e = stage_expand<T>(c, w, L, w.p, Q0, w.sc, pair);
     }
     if (e == hipSuccess && c->dd == 3) {
       arm(1);
-      e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc);
+      e = stage_axis1<T>(c, w, L, +1, Q0, Q1, w.X1, w.X2, w.sc, pair);
     }
     if (e == hipSuccess) {
       arm(2);
@@ -1887,12 +1905,12 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
     }
     if (e == hipSuccess && c->dd == 3) {
       arm(3);
-      e = stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc);
+      e = stage_axis1<T>(c, w, L, -1, Q0, Q1, w.X2, w.X1, w.sc, pair);
     }
     if (e == hipSuccess) {
       arm(4);
       e = stage_project<T>(c, w, L, w.X1, Q0, EPI_STORE, w.q, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, nullptr, w.sc, nullptr, &cg);
+                           nullptr, nullptr, w.sc, nullptr, pair, &cg);
     }
     if (e == hipSuccess) {
       arm(5);
@@ -1925,7 +1943,7 @@ static hipError_t profile_impl(CellImpl* c, int L, int reps, double* ms, double*
   // fields; the update reads r, q, writes r
   // (cells that hand two spectra between the first- and middle-axis passes:
   // two fields there instead of d)
-  const double nx = pair_mode<T>(c) ? 2.0 : (double)c->nf;
+  const double nx = pair ? 2.0 : (double)c->nf;
   bytes[8] = L * 5.0 * S * esz;
   bytes[0] = L * (S * esz + nx * Q0 * inner * esz);
   if (c->dd == 3) {

@@ -161,7 +161,7 @@ VARIANT_CASES = [((1023, 15), 0, 0), ((15, 1023), 1, 0), ((255, 15), 0, 0),
                  # two spectra between the first- and middle-axis FP32 passes
                  # (first axis 255 or Ga 253, middle axis 63 or Ga 253)
                  ((255, 63, 15), 2, 0), ((127, 127, 3), 0, 1), ((63, 63, 15), 1, 0),
-                 ((63, 255, 15), 0, 0),
+                 ((63, 255, 15), 0, 0), ((255, 255, 7), 1, 0),
                  # last-axis pass with one line per component (diagonal A)
                  ((9, 7, 255), 1, 0)]
 
