@@ -148,5 +148,11 @@ RegMid2<T, P253, 127, 16, 256> m253;
 RegMid2<T, P63, 63, 16, 128> m63;
 RegMid2<T, P255, 255, 16, 512> m255t;
 RegMid2<T, P253, 127, 16, 512> m253t;
+// last-axis passes of one wave per workgroup: its barriers hold no other
+// wave, and more workgroups fit per CU under the LDS budget
+RegRow<T, P255, 255, 3, 2, 128> r255_3h;
+RegRow<T, P255, 255, 3, 1, 64> r255_3q;
+RegRow<T, P253, 127, 3, 1, 64> r253_3q;
+RegRow<T, P1023, 1023, 2, 1, 64> r1023_2q;
 }  // namespace
 }  // namespace hom

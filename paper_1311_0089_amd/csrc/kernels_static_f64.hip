@@ -70,5 +70,8 @@ RegColR2<T, P253, 127, 8, 128> e253;
 RegMid2<T, P253, 127, 8, 128> m253;
 RegColR2<T, P63, 63, 8, 128> e63;
 RegMid2<T, P63, 63, 8, 128> m63;
+// last-axis passes of one wave per workgroup
+RegRow<T, P255, 255, 3, 1, 64> r255_3q;
+RegRow<T, P253, 127, 3, 1, 64> r253_3q;
 }  // namespace
 }  // namespace hom

@@ -45,7 +45,10 @@ FP64_OP = 1e-13
 FP32_OP = 1e-6
 
 
-PROJ_CASES = [(15, 15), (9, 7), (63, 45), (37, 11), (7, 9, 5), (5, 37, 9), (31, 15, 17)]
+# (63, 63, 7): a cell whose operator hands two spectra between the first- and
+# middle-axis passes (the projection of a real field hands three)
+PROJ_CASES = [(15, 15), (9, 7), (63, 45), (37, 11), (7, 9, 5), (5, 37, 9), (31, 15, 17),
+              (63, 63, 7)]
 
 
 @gpu
